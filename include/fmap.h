@@ -1,0 +1,147 @@
+/*
+ * fmap.h -- C ABI of libfmap, a gfx950 (MI355X) implementation of the
+ * regularised least-squares functional-map solve of "DeepShapeMatchingKit"
+ * (Sec. 3.1, "Batched Functional Map Solver", Eqs. (1)-(9)).
+ *
+ * Conventions for every entry point
+ *   - Pointers are DEVICE pointers unless marked [host].  Arrays are dense,
+ *     row-major, contiguous, with the shapes written next to them.
+ *   - Sizes are int64_t; k, d, n >= 1.  `stream` is a hipStream_t (NULL means
+ *     the default stream).  All work is enqueued on `stream` and the call
+ *     returns without synchronising.
+ *   - The caller owns every buffer, workspaces included.  The library never
+ *     allocates device memory inside these calls.  A workspace must stay
+ *     untouched until the work enqueued on `stream` has finished.
+ *   - Argument errors are detected on the host before anything is enqueued and
+ *     returned as an fmap_status; nothing is launched then.  Numerical failures
+ *     are reported asynchronously per row system through `info` (LAPACK
+ *     convention, see fmap_solve) and the affected row of the output is NaN.
+ *   - Entry points are reentrant; calls that share a workspace must be ordered
+ *     on one stream.
+ *
+ * Notation: for a shape pair, x is the source and y the target.  Phi_x [n_x][k_x]
+ * is the Laplace-Beltrami eigenbasis of x, orthonormal under the lumped vertex
+ * mass M_x [n_x] (Phi_x^T diag(M_x) Phi_x = I), mu_x [k_x] its eigenvalues, F_x
+ * [n_x][d] per-vertex features; the same for y.  The functional map C [k_y][k_x]
+ * maps x-coefficients to y-coefficients, C A ~ B.
+ */
+#ifndef FMAP_H
+#define FMAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fmap_status;
+enum {
+    FMAP_OK = 0,
+    FMAP_ERR_NULL = 1,        /* a required pointer is NULL                          */
+    FMAP_ERR_SHAPE = 2,       /* a size is out of range or sizes disagree            */
+    FMAP_ERR_VALUE = 3,       /* a scalar option is out of range (gamma, threshold)  */
+    FMAP_ERR_DTYPE = 4,       /* unknown element type                                */
+    FMAP_ERR_WORKSPACE = 5,   /* workspace NULL or smaller than required             */
+    FMAP_ERR_UNSUPPORTED = 6, /* valid request this build does not implement         */
+    FMAP_ERR_HIP = 7          /* a HIP runtime call failed                           */
+};
+
+/* Penalty mask of the commutativity term (Eq. (3) and the mask defined after
+ * Eq. (4)); D [k_y][k_x], row i follows mu_y,i and column j follows mu_x,j.
+ *   LAPLACIAN: D_ij = (mu_y,i - mu_x,j)^2.
+ *   RESOLVENT: the resolvent mask the paper cites as the structured
+ *     alternative.  Eigenvalues are clipped at 0 and divided by
+ *     s = max(max mu_x, max mu_y) of the pair; with a = (mu/s)^gamma the
+ *     resolvent 1/(a - i) has real part a/(1+a^2) and imaginary part
+ *     1/(1+a^2); D_ij is the squared modulus of the difference of the two
+ *     resolvent values.  gamma > 0.                                             */
+enum { FMAP_MASK_LAPLACIAN = 0, FMAP_MASK_RESOLVENT = 1 };
+
+/* Element type of the basis / feature arrays read by the projections. */
+enum { FMAP_F32 = 0, FMAP_BF16 = 1 };
+
+/* Library facts. */
+int32_t fmap_abi_version(void);       /* increments on any incompatible change        */
+int32_t fmap_max_k(void);             /* largest k_x, k_y accepted by fmap_solve      */
+const char *fmap_status_str(fmap_status s); /* static string, never NULL            */
+
+/* ------------------------------------------------------------------------ */
+/* Spectral projection, Eq. (1).  The pseudo-inverse of an M-orthonormal basis */
+/* in the mass inner product is Phi^T diag(M), so for every batch item b       */
+/*     A[b] = Phi[b]^T diag(mass[b]) F[b].                                     */
+/* phi [batch][n][k] and feat [batch][n][d] in `in_dtype` (FMAP_F32: float,     */
+/* FMAP_BF16: bfloat16 bit patterns, uint16), mass [batch][n] float, A          */
+/* [batch][k][d] float.  Products are accumulated in float32 (matrix cores);    */
+/* the sum over vertices is split into chunks whose partial sums are added in  */
+/* a fixed order, so results are deterministic.                               */
+/* workspace: fmap_project_workspace_bytes(...) bytes (may be 0, then NULL ok). */
+/* ------------------------------------------------------------------------ */
+size_t fmap_project_workspace_bytes(int64_t batch, int64_t n, int64_t k, int64_t d, int32_t in_dtype);
+fmap_status fmap_project(const void *phi, const float *mass, const void *feat, int32_t in_dtype, int64_t batch,
+                         int64_t n, int64_t k, int64_t d, float *A, void *workspace, size_t workspace_bytes,
+                         void *stream);
+
+/* Adjoint of the projection (the chain rule of Eq. (1)):                      */
+/*     dF[b] = diag(mass[b]) Phi[b] dA[b].                                      */
+/* phi [batch][n][k] in `phi_dtype`, mass [batch][n], dA [batch][k][d] float,    */
+/* dF [batch][n][d] float (overwritten).                                         */
+fmap_status fmap_project_backward(const void *phi, const float *mass, int32_t phi_dtype, const float *dA,
+                                  int64_t batch, int64_t n, int64_t k, int64_t d, float *dF, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Regularised solve, Eqs. (2)-(9).  For every pair p and row i < k_y:          */
+/*     (A A^T + lambda[p] diag(D_i)) c_i = A b_i            (Eq. (5))          */
+/* with A = A[p] [k_x][d], b_i the i-th row of B[p] [k_y][d], D the mask of the   */
+/* pair; C[p] row i = c_i^T (Eq. (7)).  Each row system is factorised by        */
+/* Cholesky in float32; all k_y systems of all pairs run in one batched launch  */
+/* (the rows are a batch dimension, Eq. (8)), without materialising the         */
+/* [pairs][k_y][k_x][k_x] left-hand side of Eq. (9).                            */
+/*                                                                            */
+/* evals_x [pairs][k_x], evals_y [pairs][k_y], lambda [pairs] (all float).       */
+/* C [pairs][k_y][k_x] float (written).                                          */
+/* factors: NULL, or [pairs][k_y][k_x (k_x+1)/2] float receiving every row's     */
+/*   Cholesky factor L (S_i = L L^T) in LAPACK lower packed column-major order: */
+/*   L(r, c), r >= c, at index c*k_x - c*(c-1)/2 + (r - c).  fmap_solve_backward */
+/*   can reuse them instead of refactorising.                                   */
+/* info [pairs][k_y] int32 (written): 0 ok; j > 0 the leading minor of order j   */
+/*   of S_i is not positive (or not finite); -1 lambda[p] negative or not       */
+/*   finite; -2 resolvent normaliser not positive.  Failed rows of C are NaN.   */
+/* refine_steps: 0, or the number of iterative-refinement steps (residual of     */
+/*   the row system accumulated in float64, correction solved with the float32   */
+/*   factor).                                                                   */
+/* cond_fp64_threshold: when refine_steps > 0, pairs whose estimated 1-norm     */
+/*   condition number of A A^T exceeds it form A A^T in float64 before the       */
+/*   float32 factorisation; <= 0 disables the estimate.                         */
+/* cond_est: NULL, or [pairs] float receiving that estimate (only written when  */
+/*   the estimate runs).                                                         */
+/* workspace: fmap_solve_workspace_bytes(pairs, k_x, k_y, d) bytes.              */
+/* ------------------------------------------------------------------------ */
+size_t fmap_solve_workspace_bytes(int64_t pairs, int64_t kx, int64_t ky, int64_t d);
+size_t fmap_factor_floats(int64_t kx, int64_t ky); /* floats of `factors` per pair */
+fmap_status fmap_solve(const float *A, const float *B, const float *evals_x, const float *evals_y,
+                       const float *lambda, int32_t mask_kind, float gamma, int64_t pairs, int64_t kx, int64_t ky,
+                       int64_t d, int32_t refine_steps, float cond_fp64_threshold, float *C, float *factors,
+                       int32_t *info, float *cond_est, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Reverse mode of fmap_solve (the paper states no gradients; this is the exact */
+/* derivative of the minimiser).  With G = dC [pairs][k_y][k_x] and V the rows   */
+/* v_i = S_i^{-1} g_i (S_i is symmetric):                                        */
+/*     dB = V A,   dA = V^T B - (V^T C + C^T V) A,   dlambda = -sum_ij V_ij D_ij C_ij */
+/* A, B, C, evals, lambda and the mask are those of the forward call; C is its  */
+/* output.  factors: the forward's `factors` (reused), or NULL to refactorise   */
+/* every row system (no factor storage needed).                                 */
+/* dA [pairs][k_x][d], dB [pairs][k_y][d] float (overwritten); dlambda: NULL or  */
+/* [pairs] float; info: NULL or [pairs][k_y] int32 as in fmap_solve.             */
+/* workspace: fmap_solve_workspace_bytes(pairs, k_x, k_y, d) bytes.              */
+fmap_status fmap_solve_backward(const float *dC, const float *A, const float *B, const float *C,
+                                const float *evals_x, const float *evals_y, const float *lambda, int32_t mask_kind,
+                                float gamma, int64_t pairs, int64_t kx, int64_t ky, int64_t d, const float *factors,
+                                float *dA, float *dB, float *dlambda, int32_t *info, void *workspace,
+                                size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMAP_H */

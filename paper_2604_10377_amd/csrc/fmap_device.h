@@ -1,0 +1,91 @@
+// Device-side helpers shared by the libfmap kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fmap {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// One 32x32x2 float32 matrix-core step.  Operand layout (lane l, wave64):
+//   a = X[m = l % 32][kk = l / 32],  b = Y[kk = l / 32][n = l % 32],
+//   accumulator register r of lane l holds D[acc32_row(r, l)][l % 32].
+__device__ __forceinline__ f32x16 mfma32x32x2(float a, float b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int acc32_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+__device__ __forceinline__ f32x16 zero16()
+{
+    f32x16 z;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) z[i] = 0.f;
+    return z;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ float readlane(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// bfloat16 bit pattern -> float (exact).
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// Penalty mask entry for one (target i, source j) eigenvalue pair.
+//   kind 0 (Laplacian): (mu_y - mu_x)^2
+//   kind 1 (resolvent): |r(mu_y) - r(mu_x)|^2 with r(mu) = 1/(a - i),
+//   a = (max(mu,0) * inv_scale)^gamma.
+struct MaskParams {
+    int kind;
+    float gamma;
+    float inv_scale;
+};
+
+__device__ __forceinline__ void resolvent_point(float mu, const MaskParams &m, float &re, float &im)
+{
+    const float t = fmaxf(mu, 0.f) * m.inv_scale;
+    const float a = (m.gamma == 0.5f) ? sqrtf(t) : powf(t, m.gamma);
+    const float den = 1.f / (1.f + a * a);
+    re = a * den;
+    im = den;
+}
+
+__device__ __forceinline__ float mask_entry(float mu_y, float mu_x, const MaskParams &m)
+{
+    if (m.kind == 0) {
+        const float t = mu_y - mu_x;
+        return t * t;
+    }
+    float ry, iy, rx, ix;
+    resolvent_point(mu_y, m, ry, iy);
+    resolvent_point(mu_x, m, rx, ix);
+    const float a = ry - rx, b = iy - ix;
+    return a * a + b * b;
+}
+
+}  // namespace fmap

@@ -1,0 +1,39 @@
+// Host-side launch entry points shared between the kernel files and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fmap {
+
+// Largest k_x handled by the register-resident row-solve kernels.
+constexpr int kSmallK = 64;
+
+struct ProjPlan {
+    int MT, NT, kblocks, dblocks, nsplit, chunk;
+};
+
+ProjPlan plan_project(int64_t batch, int64_t n, int64_t k, int64_t d, int32_t dtype);
+size_t project_workspace_bytes(int64_t batch, int64_t n, int64_t k, int64_t d, int32_t dtype);
+hipError_t launch_project(const void *phi, const float *mass, const void *feat, int32_t dtype, int64_t batch, int64_t n,
+                          int64_t k, int64_t d, float *A, void *ws, hipStream_t st);
+hipError_t launch_project_backward(const void *phi, const float *mass, int32_t dtype, const float *dA, int64_t batch,
+                                   int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st);
+
+// Workspace carve-up of the solver (byte offsets, 256-aligned).
+struct SolveWs {
+    size_t K, R, V, dlam, total;
+};
+SolveWs solve_workspace_layout(int64_t pairs, int64_t kx, int64_t ky, int64_t d);
+
+hipError_t launch_solve(const float *A, const float *B, const float *ex, const float *ey, const float *lam,
+                        int32_t mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, int64_t d,
+                        int32_t refine_steps, float cond_threshold, float *C, float *factors, int32_t *info,
+                        float *cond_est, void *ws, hipStream_t st);
+hipError_t launch_solve_backward(const float *dC, const float *A, const float *B, const float *C, const float *ex,
+                                 const float *ey, const float *lam, int32_t mask_kind, float gamma, int64_t P,
+                                 int64_t kx, int64_t ky, int64_t d, const float *factors, float *dA, float *dB,
+                                 float *dlam, int32_t *info, void *ws, hipStream_t st);
+
+}  // namespace fmap

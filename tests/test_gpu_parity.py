@@ -1,0 +1,276 @@
+"""GPU parity: every HIP entry point against the FP64 oracle on the same seeded inputs.
+
+Tolerance: relative Frobenius error <= 1e-5 for every float32 result (C,
+factors, dA, dB, dF, dlambda), per item, on well-conditioned inputs (d >= 2k
+for random spectral data, so cond(A A^T) stays below ~40 and float32 rounding
+of the products and of the factorisation stays near 1e-6).  Integer results
+(info) are bit-exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_10377_amd import synth
+from tests.conftest import rel_fro
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def F(dev):
+    from paper_2604_10377_amd import fmap
+    return fmap
+
+
+def T(x, dev, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(dev)
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def _shapes(seed, b, n, k, d, bf16=False):
+    rng = np.random.default_rng(seed)
+    mass = (rng.uniform(0.5, 1.5, (b, n)) / n).astype(np.float32)
+    phi = rng.standard_normal((b, n, k)).astype(np.float32)
+    feat = rng.standard_normal((b, n, d)).astype(np.float32)
+    if bf16:
+        phi = synth.bf16_bits_to_f32(synth.to_bf16_bits(phi)).reshape(phi.shape)
+        feat = synth.bf16_bits_to_f32(synth.to_bf16_bits(feat)).reshape(feat.shape)
+    return phi, mass, feat
+
+
+# ----------------------------------------------------------------------------- projection
+
+@pytest.mark.parametrize("b,n,k,d", [(1, 1, 1, 1), (2, 37, 5, 7), (3, 1234, 30, 128), (2, 5000, 50, 256),
+                                     (1, 4097, 64, 300), (2, 999, 65, 33), (1, 20011, 120, 256)])
+def test_project_forward(F, dev, b, n, k, d):
+    import torch
+    phi, mass, feat = _shapes(1, b, n, k, d)
+    A = N(F.fmap_project(T(phi, dev), T(mass, dev), T(feat, dev)))
+    torch.cuda.synchronize()
+    for s in range(b):
+        ref = oracle.project(phi[s], mass[s], feat[s])
+        assert rel_fro(A[s], ref) <= TOL, (s, rel_fro(A[s], ref))
+
+
+@pytest.mark.parametrize("b,n,k,d", [(2, 777, 30, 128), (1, 5000, 50, 256)])
+def test_project_forward_bf16_inputs(F, dev, b, n, k, d):
+    """bf16 basis/features: compared with the oracle fed the same bf16-rounded values."""
+    import torch
+    phi, mass, feat = _shapes(2, b, n, k, d, bf16=True)
+    A = N(F.fmap_project(T(phi, dev, torch.bfloat16), T(mass, dev), T(feat, dev, torch.bfloat16)))
+    for s in range(b):
+        assert rel_fro(A[s], oracle.project(phi[s], mass[s], feat[s])) <= TOL
+
+
+@pytest.mark.parametrize("b,n,k,d", [(1, 1, 1, 1), (2, 37, 5, 7), (3, 1234, 30, 128), (2, 5000, 50, 256),
+                                     (1, 4097, 64, 300), (2, 999, 65, 33)])
+def test_project_backward(F, dev, b, n, k, d):
+    phi, mass, _ = _shapes(3, b, n, k, d)
+    dA = np.random.default_rng(4).standard_normal((b, k, d)).astype(np.float32)
+    dF = N(F.fmap_project_backward(T(phi, dev), T(mass, dev), T(dA, dev)))
+    for s in range(b):
+        assert rel_fro(dF[s], oracle.project_backward(phi[s], mass[s], dA[s])) <= TOL
+
+
+# ----------------------------------------------------------------------------- solve
+
+def _spectral(seed, P, kx, ky, d):
+    rng = synth.rng_for(555, seed, kx, ky)
+    A = rng.standard_normal((P, kx, d)).astype(np.float32)
+    B = rng.standard_normal((P, ky, d)).astype(np.float32)
+    ex = np.stack([synth.eigenvalues_linear(rng, kx) for _ in range(P)]).astype(np.float32)
+    ey = np.stack([synth.eigenvalues_linear(rng, ky) for _ in range(P)]).astype(np.float32)
+    lam = (10.0 ** rng.uniform(-3, 0, P)).astype(np.float32)
+    return A, B, ex, ey, lam
+
+
+def _oracle_solve(A, B, ex, ey, lam, mask, gamma, dC=None):
+    out = []
+    for p in range(A.shape[0]):
+        D = oracle.mask(ex[p], ey[p], mask, gamma)
+        C, info, L = oracle.solve(A[p], B[p], D, float(lam[p]), return_factors=True)
+        r = dict(C=C, info=info, L=L, D=D)
+        if dC is not None:
+            r["dA"], r["dB"], r["dl"] = oracle.solve_backward(A[p], B[p], C, D, float(lam[p]), dC[p])
+        out.append(r)
+    return out
+
+
+def _unpack_lower_colmajor(packed, m):
+    L = np.zeros((m, m))
+    idx = 0
+    for c in range(m):
+        for r in range(c, m):
+            L[r, c] = packed[idx]
+            idx += 1
+    return L
+
+
+SOLVE_CASES = [(3, 1, 1, 4), (5, 5, 5, 16), (4, 30, 30, 128), (3, 50, 50, 256), (2, 64, 64, 256),
+               (3, 17, 33, 80), (2, 40, 23, 96), (7, 32, 32, 64)]
+
+
+@pytest.mark.parametrize("mask", [0, 1])
+@pytest.mark.parametrize("P,kx,ky,d", SOLVE_CASES)
+def test_solve_forward(F, dev, mask, P, kx, ky, d):
+    if mask == 1 and kx == 1 and ky == 1:
+        pytest.skip("resolvent normaliser of a single zero eigenvalue is not positive")
+    A, B, ex, ey, lam = _spectral(1, P, kx, ky, d)
+    C, fac, info, _ = F.fmap_solve(T(A, dev), T(B, dev), T(ex, dev), T(ey, dev), T(lam, dev), mask, 0.5)
+    C, fac, info = N(C), N(fac), N(info)
+    ref = _oracle_solve(A, B, ex, ey, lam, mask, 0.5)
+    for p in range(P):
+        assert (info[p] == 0).all() and (ref[p]["info"] == 0).all()
+        assert rel_fro(C[p], ref[p]["C"]) <= TOL, (p, rel_fro(C[p], ref[p]["C"]))
+        m = kx * (kx + 1) // 2
+        for i in (0, ky // 2, ky - 1):
+            Lg = _unpack_lower_colmajor(fac[p, i * m:(i + 1) * m], kx)
+            assert rel_fro(Lg, ref[p]["L"][i]) <= TOL
+
+
+@pytest.mark.parametrize("mask", [0, 1])
+@pytest.mark.parametrize("stored", [True, False])
+@pytest.mark.parametrize("P,kx,ky,d", SOLVE_CASES)
+def test_solve_backward(F, dev, mask, stored, P, kx, ky, d):
+    if mask == 1 and kx == 1 and ky == 1:
+        pytest.skip("resolvent normaliser of a single zero eigenvalue is not positive")
+    A, B, ex, ey, lam = _spectral(2, P, kx, ky, d)
+    dC = np.random.default_rng(5).standard_normal((P, ky, kx)).astype(np.float32)
+    tA, tB, tex, tey, tl = (T(x, dev) for x in (A, B, ex, ey, lam))
+    C, fac, info, _ = F.fmap_solve(tA, tB, tex, tey, tl, mask, 0.5, store_factors=stored)
+    dA, dB, dl = F.fmap_solve_backward(T(dC, dev), tA, tB, C, tex, tey, tl, mask, 0.5, fac, want_dlam=True)
+    dA, dB, dl = N(dA), N(dB), N(dl)
+    # the oracle's backward consumes the GPU's C?  No: it recomputes its own C from the same inputs.
+    ref = _oracle_solve(A, B, ex, ey, lam, mask, 0.5, dC)
+    for p in range(P):
+        assert rel_fro(dA[p], ref[p]["dA"]) <= TOL, (p, rel_fro(dA[p], ref[p]["dA"]))
+        assert rel_fro(dB[p], ref[p]["dB"]) <= TOL, (p, rel_fro(dB[p], ref[p]["dB"]))
+        assert abs(dl[p] - ref[p]["dl"]) <= TOL * max(abs(ref[p]["dl"]), 1e-6 * np.linalg.norm(ref[p]["dA"]))
+
+
+def test_solve_info_convention(F, dev):
+    """-1 for a bad lambda, j+1 for an exactly zero pivot, -2 for a zero resolvent normaliser; NaN rows."""
+    import torch
+    P, k, d = 4, 12, 40
+    A, B, ex, ey, lam = _spectral(3, P, k, k, d)
+    lam[0] = -1.0
+    lam[1] = np.nan
+    A[2, 5] = 0.0          # zero row 5 of A ...
+    lam[2] = 0.0           # ... with lambda = 0: every row system has an exactly zero pivot 6
+    ey[3, 4] = ex[3, 7]    # pair 3: row 4's mask entry at column 7 vanishes; zero row 7 makes that pivot 0
+    A[3, 7] = 0.0
+    C, _, info, _ = F.fmap_solve(T(A, dev), T(B, dev), T(ex, dev), T(ey, dev), T(lam, dev), 0, 0.5)
+    C, info = N(C), N(info)
+    assert (info[0] == -1).all() and np.isnan(C[0]).all()
+    assert (info[1] == -1).all() and np.isnan(C[1]).all()
+    assert (info[2] == 6).all() and np.isnan(C[2]).all()
+    ref3 = _oracle_solve(A[3:], B[3:], ex[3:], ey[3:], lam[3:], 0, 0.5)[0]
+    np.testing.assert_array_equal(info[3], ref3["info"])
+    assert info[3, 4] == 8 and np.isnan(C[3, 4]).all()
+    ok = ref3["info"] == 0
+    assert rel_fro(C[3][ok], ref3["C"][ok]) <= TOL
+    # resolvent with all-zero eigenvalues
+    z = np.zeros((1, k), np.float32)
+    C, _, info, _ = F.fmap_solve(T(A[:1], dev), T(B[:1], dev), T(z, dev), T(z, dev),
+                                 T(np.ones(1, np.float32), dev), 1, 0.5)
+    assert (N(info) == -2).all() and np.isnan(N(C)).all()
+    torch.cuda.synchronize()
+
+
+# ----------------------------------------------------------------------------- whole pipeline
+
+def _pipeline_gpu(F, b, dev, bwd="stored"):
+    import torch
+    feat = T(b.feat, dev).requires_grad_(True)
+    C, info = F.functional_map(feat, T(b.phi, dev), T(b.mass, dev), T(b.evals, dev), T(b.lam, dev), b.mask,
+                               b.gamma, bwd=bwd)
+    C.backward(T(b.dC, dev))
+    torch.cuda.synchronize()
+    return N(C), N(info), N(feat.grad)
+
+
+def _pipeline_oracle_pair(b, p):
+    P = b.pairs
+    A, B, D, C, info = oracle.forward_pair(b.phi[p], b.mass[p], b.feat[p], b.phi[P + p], b.mass[P + p],
+                                           b.feat[P + p], b.evals[p], b.evals[P + p], float(b.lam[p]), b.mask, b.gamma)
+    dA, dB, _ = oracle.solve_backward(A, B, C, D, float(b.lam[p]), b.dC[p])
+    return C, info, oracle.project_backward(b.phi[p], b.mass[p], dA), oracle.project_backward(b.phi[P + p],
+                                                                                            b.mass[P + p], dB)
+
+
+@pytest.mark.parametrize("bwd", ["stored", "recompute"])
+def test_pipeline_headline_workload_full_size(F, dev, bwd):
+    """32 pairs, n=5000, k=50, d=256, resolvent mask: C and dF of sampled pairs vs the oracle."""
+    b = synth.workload_headline()
+    C, info, dF = _pipeline_gpu(F, b, dev, bwd)
+    assert (info == 0).all()
+    P = b.pairs
+    for p in (0, 1, 2, 3, 17, P - 1):
+        Cr, ir, dFx, dFy = _pipeline_oracle_pair(b, p)
+        assert rel_fro(C[p], Cr) <= TOL, (p, rel_fro(C[p], Cr))
+        assert rel_fro(dF[p], dFx) <= TOL, (p, rel_fro(dF[p], dFx))
+        assert rel_fro(dF[P + p], dFy) <= TOL, (p, rel_fro(dF[P + p], dFy))
+
+
+def test_pipeline_plain_workload_full_size(F, dev):
+    """1 pair, n=5000, k=30, d=128, Laplacian mask, forward."""
+    import torch
+    b = synth.workload_plain()
+    P = b.pairs
+    AB = F.fmap_project(T(b.phi, dev), T(b.mass, dev), T(b.feat, dev))
+    C, _, info, _ = F.fmap_solve(AB[:P], AB[P:], T(b.evals_x, dev), T(b.evals_y, dev), T(b.lam, dev), b.mask)
+    torch.cuda.synchronize()
+    A, B, D, Cr, ir = oracle.forward_pair(b.phi[0], b.mass[0], b.feat[0], b.phi[1], b.mass[1], b.feat[1],
+                                          b.evals[0], b.evals[1], float(b.lam[0]), b.mask, b.gamma)
+    assert (N(info) == 0).all()
+    assert rel_fro(N(C)[0], Cr) <= TOL
+
+
+def test_pipeline_ragged_small_batch(F, dev):
+    """n not a multiple of any tile, several pairs, both backward modes agree with the oracle."""
+    b = synth.make_batch("t", 77, 3, 1531, 37, 100, mask=synth.MASK_RESOLVENT)
+    for bwd in ("stored", "recompute"):
+        C, info, dF = _pipeline_gpu(F, b, dev, bwd)
+        for p in range(3):
+            Cr, _, dFx, dFy = _pipeline_oracle_pair(b, p)
+            assert rel_fro(C[p], Cr) <= TOL
+            assert rel_fro(dF[p], dFx) <= TOL and rel_fro(dF[3 + p], dFy) <= TOL
+
+
+def test_autograd_against_oracle_finite_differences(F, dev):
+    """Headline workload, pairs 0-3 (reduced n): GPU gradient wrt features vs FP64 central differences."""
+    b = synth.workload_headline(pairs=4, n=800)
+    C, info, dF = _pipeline_gpu(F, b, dev)
+    P = b.pairs
+    for p in range(P):
+        args = [b.phi[p], b.mass[p], b.feat[p].astype(np.float64), b.phi[P + p], b.mass[P + p],
+                b.feat[P + p].astype(np.float64), b.evals[p], b.evals[P + p], float(b.lam[p]), b.mask, b.gamma]
+        rng = np.random.default_rng(100 + p)
+        ux, uy = rng.standard_normal(b.feat[p].shape), rng.standard_normal(b.feat[P + p].shape)
+        h = 1e-4
+        def L_of(t):
+            a = list(args)
+            a[2] = args[2] + t * ux
+            a[5] = args[5] + t * uy
+            return float(np.sum(b.dC[p] * oracle.forward_pair(*a)[3]))
+        fd = (L_of(h) - L_of(-h)) / (2 * h)
+        an = float(np.sum(dF[p] * ux) + np.sum(dF[P + p] * uy))
+        assert abs(fd - an) <= 1e-5 * abs(fd), (p, fd, an)
+
+
+def test_repeat_calls_are_deterministic(F, dev):
+    import torch
+    b = synth.workload_headline(pairs=4, n=3000)
+    r1 = _pipeline_gpu(F, b, dev)
+    r2 = _pipeline_gpu(F, b, dev)
+    for x, y in zip(r1, r2):
+        np.testing.assert_array_equal(x, y)
+    torch.cuda.synchronize()
