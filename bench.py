@@ -1,0 +1,298 @@
+"""Throughput of the batched functional-map solve (forward + backward) on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload headline|mixed|large|plain]
+
+One step = one pass of the whole path over one batch of shape pairs already
+resident in HBM: projection of both shapes of every pair (Eq. 1), mask, normal
+products, per-row Cholesky solves (Eqs. 4-9), adjoint, projection backward.
+The four library calls of a step are captured once in a HIP graph per input
+set; K graph replays are timed with HIP events on the replay stream, rotating
+over three copies of the inputs so that the reads are not served from the
+256 MB last-level cache.
+
+Prints ONE JSON line (metric, value = solves/s over the whole job, roofline of
+the dominant kernel measured with HIP events, CPU oracle baseline, accuracy of
+sampled pairs against the oracle).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # MI355X dense float32 matrix
+BF16_PEAK_TFLOPS = 2500.0      # MI355X dense bf16 matrix
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="headline", choices=["headline", "plain", "mixed", "large"])
+    ap.add_argument("--bwd", default="stored", choices=["stored", "recompute"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many eager steps (for rocprofv3), no JSON")
+    return ap.parse_args()
+
+
+def make_workload(name: str):
+    from paper_2604_10377_amd import synth
+    if name == "headline":
+        return synth.workload_headline()
+    if name == "plain":
+        return synth.workload_plain()
+    if name == "mixed":
+        return synth.workload_mixed()
+    return synth.workload_large()
+
+
+class Step:
+    """Preallocated buffers and the four library calls of one forward + backward pass."""
+
+    def __init__(self, F, dev, b, inputs, bwd="stored"):
+        import torch
+        self.F, self.b, self.bwd = F, b, bwd
+        P, n, k, d = b.pairs, b.n, b.k, b.d
+        self.phi, self.mass, self.feat, self.ex, self.ey, self.lam, self.dC = inputs
+        self.AB = torch.empty((2 * P, k, d), dtype=torch.float32, device=dev)
+        self.C = torch.empty((P, k, k), dtype=torch.float32, device=dev)
+        self.info = torch.empty((P, k), dtype=torch.int32, device=dev)
+        self.fac = (torch.empty((P, F.fmap_factor_floats(k, k)), dtype=torch.float32, device=dev)
+                    if bwd == "stored" else None)
+        self.dAB = torch.empty_like(self.AB)
+        self.dF = torch.empty((2 * P, n, d), dtype=torch.float32, device=dev)
+        dt = F.FMAP_BF16 if self.phi.dtype == torch.bfloat16 else F.FMAP_F32
+        self.wsp = torch.empty(max(F.fmap_project_workspace_bytes(2 * P, n, k, d, dt), 256), dtype=torch.uint8,
+                               device=dev)
+        self.wss = torch.empty(F.fmap_solve_workspace_bytes(P, k, k, d), dtype=torch.uint8, device=dev)
+
+    def project(self):
+        self.F.fmap_project(self.phi, self.mass, self.feat, A=self.AB, workspace=self.wsp)
+
+    def solve(self):
+        P, b = self.b.pairs, self.b
+        self.F.fmap_solve(self.AB[:P], self.AB[P:], self.ex, self.ey, self.lam, b.mask, b.gamma, C=self.C,
+                          factors=self.fac, info=self.info, workspace=self.wss, store_factors=self.bwd == "stored")
+
+    def solve_backward(self):
+        P, b = self.b.pairs, self.b
+        self.F.fmap_solve_backward(self.dC, self.AB[:P], self.AB[P:], self.C, self.ex, self.ey, self.lam, b.mask,
+                                   b.gamma, self.fac, dA=self.dAB[:P], dB=self.dAB[P:], workspace=self.wss)
+
+    def project_backward(self):
+        self.F.fmap_project_backward(self.phi, self.mass, self.dAB, dF=self.dF)
+
+    def run(self):
+        self.project()
+        self.solve()
+        self.solve_backward()
+        self.project_backward()
+
+
+def phase_costs(b, bf16: bool):
+    """Algorithmic flops and HBM bytes of each phase for the whole batch (see DESIGN)."""
+    P, n, k, d = b.pairs, b.n, b.k, b.d
+    S = 2 * P
+    eb = 2 if bf16 else 4
+    proj_flops = 2.0 * n * k * d * S
+    proj_bytes = S * (n * k * eb + n * d * eb + n * 4 + k * d * 4)
+    tri = k * (k + 1) // 2
+    solve_flops = P * (3.0 * k * k * d + k ** 4 / 3.0 + 2.0 * k ** 3)
+    solve_bytes = P * (2 * k * d * 4 + 2 * k * 4 + 4 + k * k * 4 + k * tri * 4 + k * 4)
+    adj_flops = P * (4.0 * k ** 3 + 6.0 * k * k * d)
+    adj_bytes = P * (k * k * 4 * 2 + 2 * k * d * 4 + k * tri * 4 + 2 * k * d * 4)
+    pbwd_flops = proj_flops
+    pbwd_bytes = S * (n * k * eb + n * 4 + k * d * 4 + n * d * 4)
+    return {"project": (proj_flops, proj_bytes), "solve": (solve_flops, solve_bytes),
+            "solve_backward": (adj_flops, adj_bytes), "project_backward": (pbwd_flops, pbwd_bytes)}
+
+
+def roofline_entry(flops, nbytes, seconds, mfma_peak_tflops):
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_mfma = flops / (mfma_peak_tflops * 1e12)
+    if t_mfma >= t_hbm:
+        ach = flops / seconds / 1e12
+        return {"bound": "mfma", "achieved": round(ach, 2), "peak": mfma_peak_tflops, "unit": "TFLOP/s",
+                "frac": round(ach / mfma_peak_tflops, 4)}
+    ach = nbytes / seconds / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4)}
+
+
+def cpu_baseline(b, seconds: float):
+    """The oracle, as it stands, on a bounded sample of the same workload (whole pairs, full n)."""
+    import oracle
+    P = b.pairs
+    npairs = max(1, min(P, 4))
+    sel = list(range(npairs))
+    idx = sel + [P + p for p in sel]
+    args = (b.phi_consumed()[idx], b.mass[idx], b.feat_consumed()[idx], b.evals[idx], b.lam[sel], b.mask, b.gamma,
+            b.dC[sel])
+    done, t0 = 0, time.perf_counter()
+    while True:
+        oracle.pipeline_batch(*args)
+        done += npairs
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": round(done / el, 3), "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{done} solves ({npairs}-pair batches of the {b.name} workload, full n) in {el:.1f} s, fp64"}
+
+
+def accuracy(b, step, pairs=(0, 1)):
+    """Relative Frobenius error of C and dF of sampled pairs against the oracle."""
+    import oracle
+    P = b.pairs
+    C = step.C.cpu().numpy()
+    dF = step.dF.cpu().numpy()
+    phi, feat = b.phi_consumed(), b.feat_consumed()
+    worst = {"C": 0.0, "dF": 0.0}
+    rel = lambda x, r: float(np.linalg.norm(x - r) / np.linalg.norm(r))
+    for p in pairs:
+        A, B, D, Cr, _ = oracle.forward_pair(phi[p], b.mass[p], feat[p], phi[P + p], b.mass[P + p], feat[P + p],
+                                             b.evals[p], b.evals[P + p], float(b.lam[p]), b.mask, b.gamma)
+        dA, dB, _ = oracle.solve_backward(A, B, Cr, D, float(b.lam[p]), b.dC[p])
+        worst["C"] = max(worst["C"], rel(C[p], Cr))
+        worst["dF"] = max(worst["dF"], rel(dF[p], oracle.project_backward(phi[p], b.mass[p], dA)),
+                          rel(dF[P + p], oracle.project_backward(phi[P + p], b.mass[P + p], dB)))
+    return {k: float(f"{v:.3e}") for k, v in worst.items()} | {"pairs": list(pairs)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build runs the solve on a single device (asked for --gpus "
+              f"{args.gpus}); pairs are independent, so several GPUs would each take a share of the batch.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2604_10377_amd import fmap as F
+
+    dev = torch.device("cuda:0")
+    b = make_workload(args.workload)
+    bf16 = b.phi_bf16 is not None
+    P = b.pairs
+
+    def upload():
+        if bf16:
+            phi = torch.from_numpy(b.phi_bf16.view(np.int16)).to(dev).view(torch.bfloat16)
+            feat = torch.from_numpy(b.feat_bf16.view(np.int16)).to(dev).view(torch.bfloat16)
+        else:
+            phi = torch.from_numpy(b.phi).to(dev)
+            feat = torch.from_numpy(b.feat).to(dev)
+        t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+        return (phi, t(b.mass), feat, t(b.evals_x), t(b.evals_y), t(b.lam), t(b.dC))
+
+    base = upload()
+    sets = [base] + [tuple(x.clone() for x in base) for _ in range(2)]
+    steps = [Step(F, dev, b, s, args.bwd) for s in sets]
+    stream = torch.cuda.current_stream(dev)
+
+    if args.profile_steps:
+        for i in range(args.profile_steps):
+            steps[i % 3].run()
+        torch.cuda.synchronize()
+        print(f"profiled {args.profile_steps} eager steps of {b.name}", flush=True)
+        return
+
+    # warm-up (also JIT-free: the library is AOT compiled) and graph capture
+    for s in steps:
+        s.run()
+    torch.cuda.synchronize()
+    graphs = None
+    if not args.no_graph:
+        graphs = []
+        for s in steps:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                s.run()
+            graphs.append(g)
+        torch.cuda.synchronize()
+    replay = (lambda i: graphs[i % 3].replay()) if graphs else (lambda i: steps[i % 3].run())
+    for i in range(args.warmup):
+        replay(i)
+    torch.cuda.synchronize()
+
+    # timed region: K steps between two events on the replay stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(args.steps):
+        replay(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+
+    # per-phase average launch time (same launch configuration), HIP events on the same stream
+    # (one graph holding `reps` back-to-back calls of the phase, rotating input sets)
+    reps = 30
+    phase_ms = {}
+    for name in ("project", "solve", "solve_backward", "project_backward"):
+        fns = [getattr(s, name) for s in steps]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for i in range(reps):
+                fns[i % 3]()
+        g.replay()
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        rs = torch.cuda.current_stream(dev)
+        a.record(rs)
+        g.replay()
+        z.record(rs)
+        torch.cuda.synchronize()
+        phase_ms[name] = a.elapsed_time(z) / reps
+    costs = phase_costs(b, bf16)
+    peak = BF16_PEAK_TFLOPS if bf16 else FP32_PEAK_TFLOPS
+    dom = max(("project", "project_backward"), key=lambda nme: phase_ms[nme])
+    pk = peak if dom == "project" else FP32_PEAK_TFLOPS
+    roof = roofline_entry(costs[dom][0], costs[dom][1], phase_ms[dom] * 1e-3, pk)
+    roof["kernel"] = "fmap_project (split-K partial + fixed-order reduce)" if dom == "project" else \
+        "fmap_project_backward"
+    roof["traffic"] = None
+    roof["phase_us"] = {k: round(v * 1e3, 2) for k, v in phase_ms.items()}
+    t_roof = sum(max(f / (((peak if nme == "project" else FP32_PEAK_TFLOPS)) * 1e12), by / (HBM_PEAK_GBS * 1e9))
+                 for nme, (f, by) in costs.items())
+    roof["step_roofline_us"] = round(t_roof * 1e6, 2)
+    roof["step_frac"] = round(t_roof * 1e3 / ms, 4)
+
+    acc = accuracy(b, steps[0])
+    cpu = None if args.no_cpu_baseline else cpu_baseline(b, args.cpu_seconds)
+    out = {
+        "metric": "functional map solves/sec (fwd+bwd) at k=50,d=256,batch 32" if args.workload == "headline"
+        else f"functional map solves/sec (fwd+bwd), {b.name}",
+        "value": round(P / (ms * 1e-3), 1),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-proj/f32" if bf16 else "f32",
+        "data": "synthetic",
+        "config": {"workload": b.name, "pairs": P, "n": b.n, "k": b.k, "d": b.d,
+                   "mask": "resolvent" if b.mask == 1 else "laplacian", "lambda": float(b.lam[0]),
+                   "backward": args.bwd, "graph": not args.no_graph},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "accuracy_vs_oracle": acc,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,13 +1,15 @@
 """GPU parity: every HIP entry point against the FP64 oracle on the same seeded inputs.
 
-Tolerance: relative Frobenius error <= 1e-5 for every float32 result (C,
-factors, dA, dB, dF, dlambda), per item, on well-conditioned inputs (d >= 2k
-for random spectral data, so cond(A A^T) stays below ~40 and float32 rounding
-of the products and of the factorisation stays near 1e-6).  Integer results
-(info) are bit-exact.
+Tolerance: relative Frobenius error <= 1e-5 for every float32 array result
+(C, factors, dA, dB, dF), per item, on well-conditioned inputs (d >= 2k for
+random spectral data, so cond(A A^T) stays below ~40 and float32 rounding of
+the products and of the factorisation stays near 1e-6).  The scalar dlambda
+is a sum of k^2 cancelling terms; its error is bounded by 1e-5 times the sum
+of the terms' magnitudes.  Integer results (info) are bit-exact.
 """
 import numpy as np
 import pytest
+import scipy.linalg
 
 import oracle
 from paper_2604_10377_amd import synth
@@ -100,6 +102,10 @@ def _oracle_solve(A, B, ex, ey, lam, mask, gamma, dC=None):
         r = dict(C=C, info=info, L=L, D=D)
         if dC is not None:
             r["dA"], r["dB"], r["dl"] = oracle.solve_backward(A[p], B[p], C, D, float(lam[p]), dC[p])
+            # error scale of the scalar dlambda = -sum_ij V_ij D_ij C_ij: a float32 sum of k^2 terms
+            # is accurate relative to sum |terms|, not to |sum| (the terms cancel)
+            V = np.stack([scipy.linalg.cho_solve((L[i], True), dC[p][i]) for i in range(L.shape[0])])
+            r["dl_scale"] = float(np.sum(np.abs(V * D * C)))
         out.append(r)
     return out
 
@@ -148,12 +154,12 @@ def test_solve_backward(F, dev, mask, stored, P, kx, ky, d):
     C, fac, info, _ = F.fmap_solve(tA, tB, tex, tey, tl, mask, 0.5, store_factors=stored)
     dA, dB, dl = F.fmap_solve_backward(T(dC, dev), tA, tB, C, tex, tey, tl, mask, 0.5, fac, want_dlam=True)
     dA, dB, dl = N(dA), N(dB), N(dl)
-    # the oracle's backward consumes the GPU's C?  No: it recomputes its own C from the same inputs.
+    # the oracle recomputes its own C from the same inputs; it never consumes GPU results
     ref = _oracle_solve(A, B, ex, ey, lam, mask, 0.5, dC)
     for p in range(P):
         assert rel_fro(dA[p], ref[p]["dA"]) <= TOL, (p, rel_fro(dA[p], ref[p]["dA"]))
         assert rel_fro(dB[p], ref[p]["dB"]) <= TOL, (p, rel_fro(dB[p], ref[p]["dB"]))
-        assert abs(dl[p] - ref[p]["dl"]) <= TOL * max(abs(ref[p]["dl"]), 1e-6 * np.linalg.norm(ref[p]["dA"]))
+        assert abs(dl[p] - ref[p]["dl"]) <= TOL * ref[p]["dl_scale"], (p, dl[p], ref[p]["dl"], ref[p]["dl_scale"])
 
 
 def test_solve_info_convention(F, dev):
@@ -263,7 +269,12 @@ def test_autograd_against_oracle_finite_differences(F, dev):
             return float(np.sum(b.dC[p] * oracle.forward_pair(*a)[3]))
         fd = (L_of(h) - L_of(-h)) / (2 * h)
         an = float(np.sum(dF[p] * ux) + np.sum(dF[P + p] * uy))
-        assert abs(fd - an) <= 1e-5 * abs(fd), (p, fd, an)
+        # u ~ N(0, I): <e, u> ~ N(0, |e|^2) for a gradient error e, so the scale is |dF|, not |<dF, u>|;
+        # a gradient within 1e-5 relative passes with a 5-sigma margin
+        scale = float(np.sqrt(np.sum(dF[p] ** 2) + np.sum(dF[P + p] ** 2)))
+        assert abs(fd - an) <= 5e-5 * scale, (p, fd, an, scale)
+        _, _, dFx, dFy = _pipeline_oracle_pair(b, p)
+        assert rel_fro(dF[p], dFx) <= TOL and rel_fro(dF[P + p], dFy) <= TOL
 
 
 def test_repeat_calls_are_deterministic(F, dev):
