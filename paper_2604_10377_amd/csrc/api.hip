@@ -33,7 +33,7 @@ extern "C" {
 
 int32_t fmap_abi_version(void) { return 1; }
 
-int32_t fmap_max_k(void) { return fmap::kSmallK; }
+int32_t fmap_max_k(void) { return fmap::kMaxK; }
 
 const char *fmap_status_str(fmap_status s)
 {
@@ -103,7 +103,8 @@ fmap_status fmap_solve(const float *A, const float *B, const float *evals_x, con
     if (!C || !info) return FMAP_ERR_NULL;
     if (refine_steps < 0 || refine_steps > 8) return FMAP_ERR_VALUE;
     if (isnan(cond_fp64_threshold)) return FMAP_ERR_VALUE;
-    if (refine_steps > 0) return FMAP_ERR_UNSUPPORTED;
+    if (refine_steps > 0 && !factors) return FMAP_ERR_NULL;  // the corrections reuse the float32 factors
+    if ((cond_fp64_threshold > 0.f || cond_est) && kx > fmap::kMaxCondK) return FMAP_ERR_UNSUPPORTED;
     const size_t need = fmap::solve_workspace_layout(pairs, kx, ky, d).total;
     if (!workspace || workspace_bytes < need) return FMAP_ERR_WORKSPACE;
     return hip_status(fmap::launch_solve(A, B, evals_x, evals_y, lambda, mask_kind, gamma, pairs, kx, ky, d,

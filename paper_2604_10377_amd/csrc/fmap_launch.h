@@ -9,6 +9,8 @@ namespace fmap {
 
 // Largest k_x handled by the register-resident row-solve kernels.
 constexpr int kSmallK = 64;
+// Largest k_x of the tiled row solve (k_x + 1 rows in at most 10 tile rows of 32).
+constexpr int kMaxK = 319;
 
 struct ProjPlan {
     int MT, NT, kblocks, dblocks, nsplit, chunk;
@@ -23,7 +25,7 @@ hipError_t launch_project_backward(const void *phi, const float *mass, int32_t d
 
 // Workspace carve-up of the solver (byte offsets, 256-aligned).
 struct SolveWs {
-    size_t K, R, V, dlam, total;
+    size_t K, R, V, W, tiles, K64, R64, dlam, total;
 };
 SolveWs solve_workspace_layout(int64_t pairs, int64_t kx, int64_t ky, int64_t d);
 
@@ -35,5 +37,24 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
                                  const float *ey, const float *lam, int32_t mask_kind, float gamma, int64_t P,
                                  int64_t kx, int64_t ky, int64_t d, const float *factors, float *dA, float *dB,
                                  float *dlam, int32_t *info, void *ws, hipStream_t st);
+
+void launch_rowsolve_tiled(int mode, const float *K, const float *Lin, const float *rhs, const float *ex,
+                           const float *ey, const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx,
+                           int64_t ky, float *out, float *Lout, int *info, const float *Cfwd, float *dlam_part,
+                           float *tile_ws, hipStream_t st, const float *addend = nullptr);
+size_t tiled_workspace_bytes(int64_t P, int64_t kx, int64_t ky);
+void launch_adjoint_general(const float *V, const float *C, const float *A, const float *B, int64_t P, int64_t kx,
+                            int64_t ky, int64_t d, float *Wbuf, const float *dlam_part, float *dlam, float *dA,
+                            float *dB, hipStream_t st);
+
+void launch_gram64(const float *A, const float *B, int64_t P, int64_t kx, int64_t ky, int64_t d, double *K64,
+                   double *R64, hipStream_t st);
+void launch_residual64(const float *C, const double *K64, const double *R64, const float *ex, const float *ey,
+                       const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *rho,
+                       hipStream_t st);
+void launch_cond(const float *K, int64_t P, int64_t kx, int64_t ky, float threshold, const double *K64,
+                 const double *R64, float *Kout, float *Rout, float *cond_est, hipStream_t st);
+// Largest k_x for the condition estimate (its float32 factor lives in LDS).
+constexpr int kMaxCondK = 256;
 
 }  // namespace fmap

@@ -1,0 +1,319 @@
+// Mixed-precision support of the row solve: float64 normal products, the
+// float64 residual of the row systems for iterative refinement, and a 1-norm
+// condition estimate of A A^T that selects float64 formation of the normal
+// matrix for ill-conditioned pairs.
+//
+//   gram64_kernel     K64 = A A^T, R64 = B A^T accumulated in float64 (the
+//                     float32 inputs multiply exactly in float64)
+//   residual64_kernel rho_i = R64_i - (C K64)_i - lambda D_i o c_i, in float64,
+//                     for every row i of C (the residual of Eq. (4), row-wise);
+//                     the correction S_i delta_i = rho_i reuses the float32
+//                     factors (stored-factor row solve with C as addend)
+//   cond_kernel       per pair: Cholesky of A A^T in float32 (packed, in LDS),
+//                     then Hager's estimate of ||(A A^T)^{-1}||_1 with Higham's
+//                     extra probe vector; cond = ||A A^T||_1 * estimate (or +inf
+//                     when the factorisation breaks down).  Pairs whose estimate
+//                     exceeds the threshold get K, R replaced by the rounded
+//                     float64 products before the float32 row factorisations.
+#include "fmap_device.h"
+#include "fmap_launch.h"
+
+namespace fmap {
+
+// ---------------------------------------------------------------------------
+// float64 mask entry (same definition as mask_entry)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double mask_entry64(double mu_y, double mu_x, int kind, double gamma, double inv_scale)
+{
+    if (kind == 0) {
+        const double t = mu_y - mu_x;
+        return t * t;
+    }
+    const double ty = fmax(mu_y, 0.0) * inv_scale, tx = fmax(mu_x, 0.0) * inv_scale;
+    const double ay = pow(ty, gamma), ax = pow(tx, gamma);
+    const double dy = 1.0 / (1.0 + ay * ay), dx = 1.0 / (1.0 + ax * ax);
+    const double a = ay * dy - ax * dx, b = dy - dx;
+    return a * a + b * b;
+}
+
+// ---------------------------------------------------------------------------
+// K64 = A A^T (kx x kx) and R64 = B A^T (ky x kx) in float64.  One 256-thread
+// workgroup per 16 x 16 output tile; rows staged in LDS in chunks of 64 columns.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gram64_kernel(const float *__restrict__ A, const float *__restrict__ B, int kx,
+                                                     int ky, int d, int tkx, int tky, double *__restrict__ K64,
+                                                     double *__restrict__ R64)
+{
+    __shared__ double sx[16][65], sy[16][65];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int tiles = tkx * tkx + tky * tkx;
+    const int p = blockIdx.x / tiles;
+    int t = blockIdx.x % tiles;
+    const float *X;
+    double *O;
+    int rowsX;
+    if (t < tkx * tkx) {
+        X = A + (size_t)p * kx * d;
+        O = K64 + (size_t)p * kx * kx;
+        rowsX = kx;
+    } else {
+        t -= tkx * tkx;
+        X = B + (size_t)p * ky * d;
+        O = R64 + (size_t)p * ky * kx;
+        rowsX = ky;
+    }
+    const int I = t / tkx, J = t % tkx;
+    const float *Y = A + (size_t)p * kx * d;
+    double acc = 0.0;
+    for (int c0 = 0; c0 < d; c0 += 64) {
+        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+            const int r = e >> 6, c = e & 63, col = c0 + c;
+            const int xr = I * 16 + r, yr = J * 16 + r;
+            sx[r][c] = (xr < rowsX && col < d) ? (double)X[(size_t)xr * d + col] : 0.0;
+            sy[r][c] = (yr < kx && col < d) ? (double)Y[(size_t)yr * d + col] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int c = 0; c < 64; ++c) acc = fma(sx[ty][c], sy[tx][c], acc);
+        __syncthreads();
+    }
+    const int row = I * 16 + ty, col = J * 16 + tx;
+    if (row < rowsX && col < kx) O[(size_t)row * kx + col] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// rho[p][i][j] = R64[i][j] - sum_q C[i][q] K64[q][j] - lambda D_ij C[i][j] for a
+// block of 16 rows of one pair (float64 arithmetic, result rounded to float32).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void residual64_kernel(const float *__restrict__ C, const double *__restrict__ K64,
+                                                         const double *__restrict__ R64, const float *__restrict__ ex,
+                                                         const float *__restrict__ ey, const float *__restrict__ lam,
+                                                         int mask_kind, float gamma, int kx, int ky,
+                                                         float *__restrict__ rho)
+{
+    extern __shared__ double sC[];  // [16][kx]
+    __shared__ double s_red[4];
+    const int rb = (ky + 15) / 16;
+    const int p = blockIdx.x / rb, i0 = (blockIdx.x % rb) * 16;
+    const int tid = threadIdx.x;
+    const int nr = min(16, ky - i0);
+    for (int e = tid; e < 16 * kx; e += 256) {
+        const int r = e / kx, q = e - r * kx;
+        sC[e] = r < nr ? (double)C[((size_t)p * ky + i0 + r) * kx + q] : 0.0;
+    }
+    double inv_scale = 1.0;
+    if (mask_kind == 1) {
+        float mx = -INFINITY;
+        for (int q = tid; q < kx; q += 256) mx = fmaxf(mx, ex[(size_t)p * kx + q]);
+        for (int q = tid; q < ky; q += 256) mx = fmaxf(mx, ey[(size_t)p * ky + q]);
+        mx = wave_max(mx);
+        if ((tid & 63) == 0) s_red[tid >> 6] = mx;
+        __syncthreads();
+        const double m4 = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
+        inv_scale = 1.0 / m4;
+    }
+    __syncthreads();
+    const double lamd = (double)lam[p];
+    const double *Kp = K64 + (size_t)p * kx * kx;
+    for (int j = tid; j < kx; j += 256) {
+        double acc[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+        for (int q = 0; q < kx; ++q) {
+            const double kq = Kp[(size_t)q * kx + j];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = fma(sC[r * kx + q], kq, acc[r]);
+        }
+        const double mux = (double)ex[(size_t)p * kx + j];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (r < nr) {
+                const int i = i0 + r;
+                const double D = mask_entry64((double)ey[(size_t)p * ky + i], mux, mask_kind, (double)gamma, inv_scale);
+                const double v = R64[((size_t)p * ky + i) * kx + j] - acc[r] - lamd * D * sC[r * kx + j];
+                rho[((size_t)p * ky + i) * kx + j] = (float)v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Condition estimate of K = A A^T per pair (one 512-thread workgroup).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int pk(int r, int c) { return r * (r + 1) / 2 + c; }  // packed lower, row-major
+
+// x := K^{-1} x with the packed factor in LDS (one wave; x in LDS).
+__device__ void chol_solve_wave(const float *L, float *x, int k)
+{
+    const int lane = threadIdx.x & 63;
+    // L y = x (column oriented): y_c final at step c
+    for (int c = 0; c < k; ++c) {
+        const float yc = x[c] / L[pk(c, c)];
+        __builtin_amdgcn_wave_barrier();
+        for (int r = c + 1 + lane; r < k; r += 64) x[r] -= L[pk(r, c)] * yc;
+        if (lane == 0) x[c] = yc;
+        __builtin_amdgcn_wave_barrier();
+    }
+    // L^T z = y (row oriented): z_c = (y_c - sum_{r>c} L_rc z_r) / L_cc
+    for (int c = k - 1; c >= 0; --c) {
+        float s = 0.f;
+        for (int r = c + 1 + lane; r < k; r += 64) s += L[pk(r, c)] * x[r];
+        s = wave_sum(s);
+        if (lane == 0) x[c] = (x[c] - s) / L[pk(c, c)];
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+__global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, int kx, float threshold,
+                                                   const double *__restrict__ K64, const double *__restrict__ R64,
+                                                   float *__restrict__ Kout, float *__restrict__ Rout, int ky,
+                                                   float *__restrict__ cond_est)
+{
+    extern __shared__ float sm[];
+    float *L = sm;                                   // packed lower, kx(kx+1)/2
+    float *x = L + kx * (kx + 1) / 2;                // kx
+    float *z = x + kx;                               // kx
+    __shared__ float s_red[8];
+    __shared__ int s_fail, s_j;
+    const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float *Kp = K + (size_t)p * kx * kx;
+    for (int e = tid; e < kx * kx; e += 512) {
+        const int r = e / kx, c = e - r * kx;
+        if (c <= r) L[pk(r, c)] = Kp[e];
+    }
+    // ||K||_1 = max column sum of |K|
+    float cmax = 0.f;
+    for (int c = tid; c < kx; c += 512) {
+        float s = 0.f;
+        for (int r = 0; r < kx; ++r) s += fabsf(Kp[(size_t)r * kx + c]);
+        cmax = fmaxf(cmax, s);
+    }
+    cmax = wave_max(cmax);
+    if (lane == 0) s_red[wave] = cmax;
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+    float knorm = s_red[0];
+    for (int w = 1; w < 8; ++w) knorm = fmaxf(knorm, s_red[w]);
+    // right-looking Cholesky in LDS, one column per step
+    for (int c = 0; c < kx; ++c) {
+        const float piv = L[pk(c, c)];
+        if (!(piv > 0.f) || !isfinite(piv)) {
+            if (tid == 0) s_fail = 1;
+            break;
+        }
+        const float lc = sqrtf(piv);
+        __syncthreads();
+        if (tid == 0) L[pk(c, c)] = lc;
+        for (int r = c + 1 + tid; r < kx; r += 512) L[pk(r, c)] /= lc;
+        __syncthreads();
+        const int m = kx - c - 1;
+        for (int e = tid; e < m * (m + 1) / 2; e += 512) {
+            int rr = (int)((sqrtf(8.f * e + 1.f) - 1.f) * 0.5f);
+            while (rr * (rr + 1) / 2 > e) --rr;
+            while ((rr + 1) * (rr + 2) / 2 <= e) ++rr;
+            const int cc = e - rr * (rr + 1) / 2;
+            const int r = c + 1 + rr, q = c + 1 + cc;
+            L[pk(r, q)] -= L[pk(r, c)] * L[pk(q, c)];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    float est = INFINITY;
+    if (s_fail == 0) {
+        if (wave == 0) {
+            // Hager: b = 1/n; up to 5 sweeps of x = K^{-1} b, xi = sign(x), z = K^{-1} xi
+            for (int r = lane; r < kx; r += 64) x[r] = 1.f / kx;
+            __builtin_amdgcn_wave_barrier();
+            float e1 = 0.f;
+            for (int it = 0; it < 5; ++it) {
+                chol_solve_wave(L, x, kx);
+                float s = 0.f;
+                for (int r = lane; r < kx; r += 64) s += fabsf(x[r]);
+                s = wave_sum(s);
+                if (it > 0 && s <= e1) break;
+                e1 = s;
+                for (int r = lane; r < kx; r += 64) z[r] = x[r] >= 0.f ? 1.f : -1.f;
+                __builtin_amdgcn_wave_barrier();
+                chol_solve_wave(L, z, kx);
+                // j = argmax |z|, compare with z^T b (b is the previous probe, stored implicitly)
+                float best = -1.f;
+                int bj = 0;
+                for (int r = lane; r < kx; r += 64)
+                    if (fabsf(z[r]) > best) {
+                        best = fabsf(z[r]);
+                        bj = r;
+                    }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const float ob = __shfl_xor(best, off, 64);
+                    const int oj = __shfl_xor(bj, off, 64);
+                    if (ob > best || (ob == best && oj < bj)) {
+                        best = ob;
+                        bj = oj;
+                    }
+                }
+                for (int r = lane; r < kx; r += 64) x[r] = (r == bj) ? 1.f : 0.f;
+                __builtin_amdgcn_wave_barrier();
+            }
+            // Higham's extra probe: b_i = (-1)^i (1 + i/(n-1)); estimate 2 ||K^{-1} b||_1 / (3n)
+            for (int r = lane; r < kx; r += 64) z[r] = ((r & 1) ? -1.f : 1.f) * (1.f + (kx > 1 ? (float)r / (kx - 1) : 0.f));
+            __builtin_amdgcn_wave_barrier();
+            chol_solve_wave(L, z, kx);
+            float s2 = 0.f;
+            for (int r = lane; r < kx; r += 64) s2 += fabsf(z[r]);
+            s2 = wave_sum(s2) * 2.f / (3.f * kx);
+            if (lane == 0) s_red[0] = fmaxf(e1, s2) * knorm;
+        }
+        __syncthreads();
+        est = s_red[0];
+    }
+    if (tid == 0 && cond_est) cond_est[p] = est;
+    // ill-conditioned pair: use the float64-formed products (rounded) for the row factorisations
+    if (threshold > 0.f && !(est <= threshold) && K64) {
+        for (int e = tid; e < kx * kx; e += 512) Kout[(size_t)p * kx * kx + e] = (float)K64[(size_t)p * kx * kx + e];
+        for (int e = tid; e < ky * kx; e += 512) Rout[(size_t)p * ky * kx + e] = (float)R64[(size_t)p * ky * kx + e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+void launch_gram64(const float *A, const float *B, int64_t P, int64_t kx, int64_t ky, int64_t d, double *K64,
+                   double *R64, hipStream_t st)
+{
+    const int tkx = (int)((kx + 15) / 16), tky = (int)((ky + 15) / 16);
+    hipLaunchKernelGGL(gram64_kernel, dim3((unsigned)(P * (tkx * tkx + tky * tkx))), dim3(256), 0, st, A, B, (int)kx,
+                       (int)ky, (int)d, tkx, tky, K64, R64);
+}
+
+void launch_residual64(const float *C, const double *K64, const double *R64, const float *ex, const float *ey,
+                       const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *rho,
+                       hipStream_t st)
+{
+    const size_t lds = (size_t)16 * kx * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)residual64_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(16 * kMaxK * sizeof(double)));
+        attr = true;
+    }
+    hipLaunchKernelGGL(residual64_kernel, dim3((unsigned)(P * ((ky + 15) / 16))), dim3(256), lds, st, C, K64, R64,
+                       ex, ey, lam, mask_kind, gamma, (int)kx, (int)ky, rho);
+}
+
+void launch_cond(const float *K, int64_t P, int64_t kx, int64_t ky, float threshold, const double *K64,
+                 const double *R64, float *Kout, float *Rout, float *cond_est, hipStream_t st)
+{
+    const size_t lds = ((size_t)kx * (kx + 1) / 2 + 2 * kx) * sizeof(float);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)cond_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(((size_t)kMaxK * (kMaxK + 1) / 2 + 2 * kMaxK) * sizeof(float)));
+        attr = true;
+    }
+    hipLaunchKernelGGL(cond_kernel, dim3((unsigned)P), dim3(512), lds, st, K, (int)kx, threshold, K64, R64, Kout, Rout,
+                       (int)ky, cond_est);
+}
+
+}  // namespace fmap

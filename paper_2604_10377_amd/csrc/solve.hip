@@ -28,8 +28,11 @@ enum { RS_FWD = 0, RS_BWD_STORED = 1, RS_BWD_RECOMPUTE = 2 };
 
 // ---------------------------------------------------------------------------
 // K = A A^T and (optionally) R = B A^T.  One workgroup per 32x32 output tile;
-// its four waves split the feature range d and reduce through LDS.
+// its four waves split the feature range d and reduce through LDS.  Loads are
+// issued in batches of GU matrix-core steps ahead of the multiplies.
 // ---------------------------------------------------------------------------
+constexpr int GU = 8;
+
 __global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ A, const float *__restrict__ B, int kx,
                                                    int ky, int d, int tkx, int tky, int with_R,
                                                    float *__restrict__ K, float *__restrict__ R)
@@ -57,18 +60,25 @@ __global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ A, 
     const float *Y = A + (size_t)p * kx * d;
     const int m = I * 32 + l32, nn = J * 32 + l32;
     const bool mok = m < rowsX, nok = nn < kx;
+    const float *xr = X + (size_t)(mok ? m : 0) * d;
+    const float *yr = Y + (size_t)(nok ? nn : 0) * d;
 
-    // wave range of d, split into two halves for the two lane halves
     const int dq = (d + 3) / 4;
     const int lo = wave * dq, hi = min(d, lo + dq);
     const int H = (max(hi - lo, 0) + 1) >> 1;
+    const int base = lo + half * H;
     f32x16 acc = zero16();
-    for (int s = 0; s < H; ++s) {
-        const int dd = lo + half * H + s;
-        const bool ok = dd < hi;
-        const float a = (mok && ok) ? X[(size_t)m * d + dd] : 0.f;
-        const float b = (nok && ok) ? Y[(size_t)nn * d + dd] : 0.f;
-        acc = mfma32x32x2(a, b, acc);
+    for (int s0 = 0; s0 < H; s0 += GU) {
+        float a[GU], b[GU];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int dd = base + s0 + u;
+            const bool ok = (s0 + u < H) && dd < hi;
+            a[u] = (mok && ok) ? xr[dd] : 0.f;
+            b[u] = (nok && ok) ? yr[dd] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < GU; ++u) acc = mfma32x32x2(a[u], b[u], acc);
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[r];
@@ -86,16 +96,27 @@ __global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ A, 
 // Offset of column c in LAPACK lower packed column-major storage of order m.
 __device__ __forceinline__ int packed_col(int c, int m) { return c * m - (c * (c - 1)) / 2; }
 
+__device__ __forceinline__ float uniform(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+
 // ---------------------------------------------------------------------------
-// One wave per row system.  KMAX >= k_x (register row length).
+// One wave per row system; KMAX >= k_x is the register row length.
+//
+// Lane j holds row j of S_i (entries q <= j, the rest zero).  Step c of the
+// right-looking factorisation: the pivot comes from lane c, every lane scales
+// its column-c entry, the column is broadcast through LDS (all reads of a step
+// issued together) and each lane updates its row.  The forward substitution
+// L y = r rides along (y_c is final once column c is).  The back substitution
+// L^T c = y reads a register copy of column j of L (row j of L^T) staged
+// through LDS, so it needs only readlanes.  All control flow is wave-uniform.
 // ---------------------------------------------------------------------------
 template <int KMAX, int MODE>
 __global__ __launch_bounds__(256) void rowsolve_kernel(
     const float *__restrict__ K, const float *__restrict__ Lin, const float *__restrict__ rhs,
     const float *__restrict__ ex, const float *__restrict__ ey, const float *__restrict__ lam, int mask_kind,
-    float gamma, int kx, int ky, float *__restrict__ out, float *__restrict__ Lout, int *__restrict__ info,
-    const float *__restrict__ Cfwd, float *__restrict__ dlam_part)
+    float gamma, int kx, int ky, float *out, float *__restrict__ Lout, int *__restrict__ info,
+    const float *__restrict__ Cfwd, float *__restrict__ dlam_part, const float *addend)
 {
+    static_assert(KMAX % 4 == 0 && KMAX <= 64, "register row length");
     __shared__ __align__(16) float s_bc[4][KMAX];
     __shared__ float s_L[4][KMAX * (KMAX + 1) / 2];  // rows of L, packed (row r at r(r+1)/2)
     const int j = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -118,53 +139,57 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
         float mx = -INFINITY;
         for (int q = j; q < kx; q += 64) mx = fmaxf(mx, ex[(size_t)p * kx + q]);
         for (int q = j; q < ky; q += 64) mx = fmaxf(mx, ey[(size_t)p * ky + q]);
-        mx = wave_max(mx);
+        mx = uniform(wave_max(mx));
         if ((!(mx > 0.f) || !isfinite(mx)) && fail == 0) fail = -2;
         mp.inv_scale = 1.f / mx;
     }
+    fail = __builtin_amdgcn_readfirstlane(fail);
     const float muy = ey[(size_t)p * ky + i];
     const float dval = (jok && fail == 0) ? mask_entry(muy, ex[(size_t)p * kx + j], mp) : 0.f;
     const float shift = lamv * dval;
 
-    // --- load row j of S_i (lower part) or of the stored factor -----------------
+    // --- row j of S_i (lower part) or of the stored factor, and the right-hand side
     float sr[KMAX];
     if (MODE == RS_BWD_STORED) {
         const float *Lp = Lin + ((size_t)p * ky + i) * T;
 #pragma unroll
         for (int q = 0; q < KMAX; ++q) sr[q] = (jok && q <= j) ? Lp[packed_col(q, kx) + j - q] : 0.f;
     } else {
-        const float *Kp = K + (size_t)p * kx * kx + (size_t)j * kx;
+        const float *Kp = K + (size_t)p * kx * kx + (size_t)(jok ? j : 0) * kx;
 #pragma unroll
         for (int q = 0; q < KMAX; ++q) sr[q] = (jok && q <= j) ? Kp[q] : 0.f;
     }
+    float r = jok ? rhs[((size_t)p * ky + i) * kx + j] : 0.f;
+    float yv = 0.f, myinv = 0.f;
 
-    // --- Cholesky of S_i = K + diag(shift) -----------------------------------------
-    // All loops have static bounds so that sr[] stays in registers; the runtime
-    // size kx only enters through wave-uniform branches.
     if (MODE != RS_BWD_STORED) {
         float *bc = s_bc[w];
 #pragma unroll
         for (int c = 0; c < KMAX; ++c) {
             if (c < kx && fail == 0) {
-                const float piv = readlane(sr[c], c) + readlane(shift, c);
+                const float piv = uniform(readlane(sr[c], c) + readlane(shift, c));
                 if (!(piv > 0.f) || !isfinite(piv)) {
                     fail = c + 1;
                 } else {
-                    const float sq = sqrtf(piv);
-                    const float inv = 1.f / sq;
-                    const float l = (j > c) ? sr[c] * inv : ((j == c) ? sq : 0.f);
+                    const float inv = __builtin_amdgcn_rsqf(piv);
+                    const float l = (j > c) ? sr[c] * inv : ((j == c) ? piv * inv : 0.f);
                     sr[c] = l;
+                    if (j == c) myinv = inv;
+                    const float yc = readlane(r, c) * inv;  // forward substitution, step c
+                    if (j == c) yv = yc;
+                    r -= l * yc;
                     if (j < KMAX) bc[j] = l;  // lanes >= KMAX hold zero rows
                     __builtin_amdgcn_wave_barrier();
+                    constexpr int NQ = KMAX / 4;
+                    f32x4 lq[NQ];
 #pragma unroll
-                    for (int q4 = 0; q4 < KMAX / 4; ++q4) {
-                        if (4 * q4 + 3 > c && 4 * q4 < kx) {
-                            const f32x4 lq = *reinterpret_cast<const f32x4 *>(&bc[4 * q4]);
+                    for (int q4 = 0; q4 < NQ; ++q4)
+                        if (4 * q4 + 3 > c) lq[q4] = *reinterpret_cast<const f32x4 *>(&bc[4 * q4]);
 #pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                if (4 * q4 + e > c) sr[4 * q4 + e] -= l * lq[e];
-                        }
-                    }
+                    for (int q4 = 0; q4 < NQ; ++q4)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (4 * q4 + e > c) sr[4 * q4 + e] -= l * lq[q4][e];
                     __builtin_amdgcn_wave_barrier();
                 }
             }
@@ -173,53 +198,56 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
 #pragma unroll
         for (int c = 0; c < KMAX; ++c) {
             if (c < kx && fail == 0) {
-                const float dg = readlane(sr[c], c);
-                if (!(dg > 0.f) || !isfinite(dg)) fail = c + 1;
+                const float dg = uniform(readlane(sr[c], c));
+                if (!(dg > 0.f) || !isfinite(dg)) {
+                    fail = c + 1;
+                } else {
+                    const float inv = __builtin_amdgcn_rcpf(dg);
+                    if (j == c) myinv = inv;
+                    const float yc = readlane(r, c) * inv;
+                    if (j == c) yv = yc;
+                    r -= sr[c] * yc;
+                }
             }
         }
     }
 
-    float cv = NAN;
-    if (fail == 0) {
-        // forward substitution L y = r (column oriented; lane c finishes at step c)
-        float r = jok ? rhs[((size_t)p * ky + i) * kx + j] : 0.f;
-        float yv = 0.f;
-#pragma unroll
-        for (int c = 0; c < KMAX; ++c) {
-            if (c < kx) {
-                const float yc = readlane(r, c) / readlane(sr[c], c);
-                if (j == c) yv = yc;
-                r -= sr[c] * yc;
-            }
-        }
-        // back substitution L^T c = y with the rows of L staged in LDS
-        float *Lr = s_L[w];
-        const int rowoff = j * (j + 1) / 2;
-#pragma unroll
-        for (int q = 0; q < KMAX; ++q)
-            if (j < KMAX && q <= j) Lr[rowoff + q] = sr[q];
-        __builtin_amdgcn_wave_barrier();
-        float y = yv;
-        cv = 0.f;
-#pragma unroll
-        for (int c = KMAX - 1; c >= 0; --c) {
-            if (c < kx) {
-                const float cc = readlane(y, c) / readlane(sr[c], c);
-                if (j == c) cv = cc;
-                if (j < c) y -= Lr[c * (c + 1) / 2 + j] * cc;  // L[c][j], j < c
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-
-    if (jok) out[((size_t)p * ky + i) * kx + j] = cv;
-    if (info && j == 0) info[(size_t)p * ky + i] = fail;
     if (MODE == RS_FWD && Lout) {
         float *Lp = Lout + ((size_t)p * ky + i) * T;
 #pragma unroll
         for (int q = 0; q < KMAX; ++q)
             if (q < kx && jok && j >= q) Lp[packed_col(q, kx) + j - q] = fail == 0 ? sr[q] : NAN;
     }
+
+    float cv = NAN;
+    if (fail == 0) {
+        // stage the rows of L, then take column j of L into registers
+        float *Lr = s_L[w];
+        const int rowoff = j * (j + 1) / 2;
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q)
+            if (j < KMAX && q <= j) Lr[rowoff + q] = sr[q];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c) sr[c] = (c > j) ? Lr[c * (c + 1) / 2 + j] : 0.f;  // L[c][j]
+        __builtin_amdgcn_wave_barrier();
+        float y = yv;
+        cv = 0.f;
+#pragma unroll
+        for (int c = KMAX - 1; c >= 0; --c) {
+            if (c < kx) {
+                const float cc = readlane(y, c) * readlane(myinv, c);
+                if (j == c) cv = cc;
+                y -= sr[c] * cc;
+            }
+        }
+    }
+
+    if (jok) {
+        const size_t o = ((size_t)p * ky + i) * kx + j;
+        out[o] = addend ? addend[o] + cv : cv;  // addend: refinement correction c += delta (in place)
+    }
+    if (info && j == 0) info[(size_t)p * ky + i] = fail;
     if (MODE != RS_FWD && dlam_part) {
         const float cf = jok ? Cfwd[((size_t)p * ky + i) * kx + j] : 0.f;
         const float term = jok ? cv * dval * cf : 0.f;
@@ -231,6 +259,8 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
 // ---------------------------------------------------------------------------
 // Adjoint products for one pair and one 64-column block of d:
 //   W = V^T C + C^T V,  dA = V^T B - W A,  dB = V A.
+// V, C, W and the A, B column blocks are staged in LDS; matrix-core loops
+// read their operands in batches of GU steps.
 // ---------------------------------------------------------------------------
 template <int KM>
 __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ V, const float *__restrict__ C,
@@ -240,10 +270,12 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
                                                       float *__restrict__ dA, float *__restrict__ dB)
 {
     __shared__ float sV[KM * KM], sC[KM * KM], sW[KM * KM];
+    __shared__ float sA[KM * 64], sB[KM * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, l32 = lane & 31;
     const int p = blockIdx.x / dblocks, db = blockIdx.x % dblocks;
     const int d0 = db * 64;
+    const int dw = min(64, d - d0);
     const float *Vp = V + (size_t)p * ky * kx;
     const float *Cp = C + (size_t)p * ky * kx;
     const float *Ap = A + (size_t)p * kx * d;
@@ -251,6 +283,14 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
     for (int e = threadIdx.x; e < ky * kx; e += 256) {
         sV[e] = Vp[e];
         sC[e] = Cp[e];
+    }
+    for (int e = threadIdx.x; e < kx * 64; e += 256) {
+        const int rr = e >> 6, cc = e & 63;
+        sA[e] = cc < dw ? Ap[(size_t)rr * d + d0 + cc] : 0.f;
+    }
+    for (int e = threadIdx.x; e < ky * 64; e += 256) {
+        const int rr = e >> 6, cc = e & 63;
+        sB[e] = cc < dw ? Bp[(size_t)rr * d + d0 + cc] : 0.f;
     }
     if (db == 0 && dlam && threadIdx.x == 0) {
         float s = 0.f;
@@ -260,22 +300,23 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
     __syncthreads();
 
     const int TI = (kx + 31) / 32, TY = (ky + 31) / 32;
-    // W tiles (TI*TI <= 4)
-    if (wave < TI * TI) {
+    if (wave < TI * TI) {  // W tiles (TI*TI <= 4)
         const int I = wave / TI, J = wave % TI;
         const int m = I * 32 + l32, nn = J * 32 + l32;
         const bool mok = m < kx, nok = nn < kx;
+        const float *Xs = half == 0 ? sV : sC;  // half 0: V^T C, half 1: C^T V
+        const float *Ys = half == 0 ? sC : sV;
         f32x16 acc = zero16();
-        for (int t = 0; t < ky; ++t) {
-            float a, b;
-            if (half == 0) {
-                a = mok ? sV[t * kx + m] : 0.f;
-                b = nok ? sC[t * kx + nn] : 0.f;
-            } else {
-                a = mok ? sC[t * kx + m] : 0.f;
-                b = nok ? sV[t * kx + nn] : 0.f;
+        for (int t0 = 0; t0 < ky; t0 += GU) {
+            float a[GU], b[GU];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int t = t0 + u;
+                a[u] = (mok && t < ky) ? Xs[t * kx + m] : 0.f;
+                b[u] = (nok && t < ky) ? Ys[t * kx + nn] : 0.f;
             }
-            acc = mfma32x32x2(a, b, acc);
+#pragma unroll
+            for (int u = 0; u < GU; ++u) acc = mfma32x32x2(a[u], b[u], acc);
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -290,23 +331,25 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
         f32x16 acc = zero16();
         if (job < nA) {
             const int I = job >> 1, cblk = job & 1;
-            const int m = I * 32 + l32, col = d0 + cblk * 32 + l32;
+            const int m = I * 32 + l32, cl = cblk * 32 + l32, col = d0 + cl;
             const bool mok = m < kx, cok = col < d;
+            // half 0: (V^T B)[m][col] over t < ky; half 1: -(W A)[m][col] over t < kx (W symmetric)
+            const float *Xs = half == 0 ? sV : sW;
+            const float *Ys = half == 0 ? sB : sA;
+            const int tn = half == 0 ? ky : kx;
+            const float sg = half == 0 ? 1.f : -1.f;
             const int steps = max(kx, ky);
-            for (int t = 0; t < steps; ++t) {
-                float a = 0.f, b = 0.f;
-                if (half == 0) {
-                    if (t < ky) {
-                        a = mok ? sV[t * kx + m] : 0.f;
-                        b = cok ? Bp[(size_t)t * d + col] : 0.f;
-                    }
-                } else {
-                    if (t < kx) {
-                        a = mok ? -sW[t * kx + m] : 0.f;
-                        b = cok ? Ap[(size_t)t * d + col] : 0.f;
-                    }
+            for (int t0 = 0; t0 < steps; t0 += GU) {
+                float a[GU], b[GU];
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    const int t = t0 + u;
+                    const bool ok = t < tn;
+                    a[u] = (mok && ok) ? sg * Xs[t * kx + m] : 0.f;
+                    b[u] = ok ? Ys[t * 64 + cl] : 0.f;
                 }
-                acc = mfma32x32x2(a, b, acc);
+#pragma unroll
+                for (int u = 0; u < GU; ++u) acc = mfma32x32x2(a[u], b[u], acc);
             }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -316,15 +359,20 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
         } else {
             const int jb = job - nA;
             const int I = jb >> 1, cblk = jb & 1;
-            const int m = I * 32 + l32, col = d0 + cblk * 32 + l32;
+            const int m = I * 32 + l32, cl = cblk * 32 + l32, col = d0 + cl;
             const bool mok = m < ky, cok = col < d;
             const int KH = (kx + 1) >> 1;
-            for (int t = 0; t < KH; ++t) {
-                const int kk = half * KH + t;
-                const bool kok = kk < kx;
-                const float a = (mok && kok) ? sV[m * kx + kk] : 0.f;
-                const float b = (cok && kok) ? Ap[(size_t)kk * d + col] : 0.f;
-                acc = mfma32x32x2(a, b, acc);
+            for (int t0 = 0; t0 < KH; t0 += GU) {
+                float a[GU], b[GU];
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    const int kk = half * KH + t0 + u;
+                    const bool ok = (t0 + u < KH) && kk < kx;
+                    a[u] = (mok && ok) ? sV[m * kx + kk] : 0.f;
+                    b[u] = ok ? sA[kk * 64 + cl] : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < GU; ++u) acc = mfma32x32x2(a[u], b[u], acc);
             }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -352,6 +400,14 @@ SolveWs solve_workspace_layout(int64_t P, int64_t kx, int64_t ky, int64_t d)
     off += align256((size_t)P * ky * kx * sizeof(float));
     w.V = off;
     off += align256((size_t)P * ky * kx * sizeof(float));
+    w.W = off;
+    off += (kx > kSmallK || ky > kSmallK) ? align256((size_t)P * kx * kx * sizeof(float)) : 0;
+    w.tiles = off;
+    off += kx > kSmallK ? align256(tiled_workspace_bytes(P, kx, ky)) : 0;
+    w.K64 = off;
+    off += align256((size_t)P * kx * kx * sizeof(double));
+    w.R64 = off;
+    off += align256((size_t)P * ky * kx * sizeof(double));
     w.dlam = off;
     off += align256((size_t)P * ky * sizeof(float));
     w.total = off;
@@ -370,15 +426,22 @@ static void launch_gram(const float *A, const float *B, int64_t P, int64_t kx, i
 template <int MODE>
 static void launch_rowsolve(const float *K, const float *Lin, const float *rhs, const float *ex, const float *ey,
                             const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky,
-                            float *out, float *Lout, int *info, const float *Cfwd, float *dlam_part, hipStream_t st)
+                            float *out, float *Lout, int *info, const float *Cfwd, float *dlam_part, hipStream_t st,
+                            const float *addend = nullptr)
 {
     const unsigned grid = (unsigned)(P * ((ky + 3) / 4));
-    if (kx <= 32)
-        hipLaunchKernelGGL((rowsolve_kernel<32, MODE>), dim3(grid), dim3(256), 0, st, K, Lin, rhs, ex, ey, lam,
-                           mask_kind, gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part);
-    else
-        hipLaunchKernelGGL((rowsolve_kernel<64, MODE>), dim3(grid), dim3(256), 0, st, K, Lin, rhs, ex, ey, lam,
-                           mask_kind, gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part);
+#define FMAP_RS(KM)                                                                                            \
+    hipLaunchKernelGGL((rowsolve_kernel<KM, MODE>), dim3(grid), dim3(256), 0, st, K, Lin, rhs, ex, ey, lam,    \
+                       mask_kind, gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part, addend)
+    if (kx <= 8) FMAP_RS(8);
+    else if (kx <= 16) FMAP_RS(16);
+    else if (kx <= 24) FMAP_RS(24);
+    else if (kx <= 32) FMAP_RS(32);
+    else if (kx <= 40) FMAP_RS(40);
+    else if (kx <= 48) FMAP_RS(48);
+    else if (kx <= 56) FMAP_RS(56);
+    else FMAP_RS(64);
+#undef FMAP_RS
 }
 
 hipError_t launch_solve(const float *A, const float *B, const float *ex, const float *ey, const float *lam,
@@ -386,15 +449,33 @@ hipError_t launch_solve(const float *A, const float *B, const float *ex, const f
                         int32_t refine_steps, float cond_threshold, float *C, float *factors, int32_t *info,
                         float *cond_est, void *ws, hipStream_t st)
 {
-    (void)refine_steps;
-    (void)cond_threshold;
-    (void)cond_est;
     SolveWs L = solve_workspace_layout(P, kx, ky, d);
     char *base = (char *)ws;
     float *K = (float *)(base + L.K), *R = (float *)(base + L.R);
+    double *K64 = (double *)(base + L.K64), *R64 = (double *)(base + L.R64);
+    float *tiles = (float *)(base + L.tiles);
     launch_gram(A, B, P, kx, ky, d, true, K, R, st);
-    launch_rowsolve<RS_FWD>(K, nullptr, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info, nullptr,
-                            nullptr, st);
+    if (refine_steps > 0) launch_gram64(A, B, P, kx, ky, d, K64, R64, st);
+    if (cond_threshold > 0.f || cond_est)
+        launch_cond(K, P, kx, ky, refine_steps > 0 ? cond_threshold : 0.f, refine_steps > 0 ? K64 : nullptr,
+                    refine_steps > 0 ? R64 : nullptr, K, R, cond_est, st);
+    if (kx <= kSmallK)
+        launch_rowsolve<RS_FWD>(K, nullptr, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info, nullptr,
+                                nullptr, st);
+    else
+        launch_rowsolve_tiled(RS_FWD, K, nullptr, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info,
+                              nullptr, nullptr, tiles, st);
+    // iterative refinement: rho = R64 - C K64 - lambda D o C in float64, C += S^{-1} rho with the float32 factors
+    float *rho = (float *)(base + L.V);
+    for (int it = 0; it < refine_steps; ++it) {
+        launch_residual64(C, K64, R64, ex, ey, lam, mask_kind, gamma, P, kx, ky, rho, st);
+        if (kx <= kSmallK)
+            launch_rowsolve<RS_BWD_STORED>(nullptr, factors, rho, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, nullptr,
+                                           nullptr, nullptr, nullptr, st, C);
+        else
+            launch_rowsolve_tiled(RS_BWD_STORED, nullptr, factors, rho, ex, ey, lam, mask_kind, gamma, P, kx, ky, C,
+                                  nullptr, nullptr, nullptr, nullptr, tiles, st, C);
+    }
     return hipGetLastError();
 }
 
@@ -406,17 +487,30 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
     SolveWs L = solve_workspace_layout(P, kx, ky, d);
     char *base = (char *)ws;
     float *K = (float *)(base + L.K), *V = (float *)(base + L.V), *dl = (float *)(base + L.dlam);
+    const bool small = kx <= kSmallK;
     if (factors) {
-        launch_rowsolve<RS_BWD_STORED>(nullptr, factors, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, nullptr,
-                                       info, C, dl, st);
+        if (small)
+            launch_rowsolve<RS_BWD_STORED>(nullptr, factors, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, nullptr,
+                                           info, C, dl, st);
+        else
+            launch_rowsolve_tiled(RS_BWD_STORED, nullptr, factors, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V,
+                                  nullptr, info, C, dl, (float *)(base + L.tiles), st);
     } else {
         launch_gram(A, B, P, kx, ky, d, false, K, nullptr, st);
-        launch_rowsolve<RS_BWD_RECOMPUTE>(K, nullptr, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, nullptr, info,
-                                          C, dl, st);
+        if (small)
+            launch_rowsolve<RS_BWD_RECOMPUTE>(K, nullptr, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, nullptr,
+                                              info, C, dl, st);
+        else
+            launch_rowsolve_tiled(RS_BWD_RECOMPUTE, K, nullptr, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V,
+                                  nullptr, info, C, dl, (float *)(base + L.tiles), st);
     }
-    const int dblocks = (int)((d + 63) / 64);
-    hipLaunchKernelGGL((adjoint_kernel<kSmallK>), dim3((unsigned)(P * dblocks)), dim3(256), 0, st, V, C, A, B,
-                       (int)kx, (int)ky, (int)d, dblocks, dl, dlam, dA, dB);
+    if (kx <= kSmallK && ky <= kSmallK) {
+        const int dblocks = (int)((d + 63) / 64);
+        hipLaunchKernelGGL((adjoint_kernel<kSmallK>), dim3((unsigned)(P * dblocks)), dim3(256), 0, st, V, C, A, B,
+                           (int)kx, (int)ky, (int)d, dblocks, dl, dlam, dA, dB);
+    } else {
+        launch_adjoint_general(V, C, A, B, P, kx, ky, d, (float *)(base + L.W), dl, dlam, dA, dB, st);
+    }
     return hipGetLastError();
 }
 

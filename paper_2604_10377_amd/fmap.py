@@ -144,6 +144,7 @@ def fmap_solve(A: torch.Tensor, B: torch.Tensor, evals_x: torch.Tensor, evals_y:
         C = torch.empty((P, ky, kx), dtype=torch.float32, device=dev)
     if info is None:
         info = torch.empty((P, ky), dtype=torch.int32, device=dev)
+    store_factors = store_factors or refine_steps > 0  # refinement reuses the float32 factors
     if store_factors and factors is None:
         factors = torch.empty((P, fmap_factor_floats(kx, ky)), dtype=torch.float32, device=dev)
     if not store_factors:

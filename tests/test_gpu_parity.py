@@ -50,8 +50,14 @@ def _shapes(seed, b, n, k, d, bf16=False):
 
 # ----------------------------------------------------------------------------- projection
 
+# the last group takes the LDS-pipelined kernels (n % 4 == 0, k <= 64): tail stages, every
+# remainder width of k mod 16, partial and multiple 256-column blocks
+LDS_CASES = [(2, 4004, 30, 128), (3, 2048, 17, 200), (2, 640, 52, 256), (1, 1000, 64, 512), (2, 4000, 49, 256),
+             (1, 516, 16, 8), (2, 1028, 35, 260), (1, 8192, 50, 256)]
+
+
 @pytest.mark.parametrize("b,n,k,d", [(1, 1, 1, 1), (2, 37, 5, 7), (3, 1234, 30, 128), (2, 5000, 50, 256),
-                                     (1, 4097, 64, 300), (2, 999, 65, 33), (1, 20011, 120, 256)])
+                                     (1, 4097, 64, 300), (2, 999, 65, 33), (1, 20011, 120, 256)] + LDS_CASES)
 def test_project_forward(F, dev, b, n, k, d):
     import torch
     phi, mass, feat = _shapes(1, b, n, k, d)
@@ -73,7 +79,7 @@ def test_project_forward_bf16_inputs(F, dev, b, n, k, d):
 
 
 @pytest.mark.parametrize("b,n,k,d", [(1, 1, 1, 1), (2, 37, 5, 7), (3, 1234, 30, 128), (2, 5000, 50, 256),
-                                     (1, 4097, 64, 300), (2, 999, 65, 33)])
+                                     (1, 4097, 64, 300), (2, 999, 65, 33)] + LDS_CASES)
 def test_project_backward(F, dev, b, n, k, d):
     phi, mass, _ = _shapes(3, b, n, k, d)
     dA = np.random.default_rng(4).standard_normal((b, k, d)).astype(np.float32)
@@ -160,6 +166,55 @@ def test_solve_backward(F, dev, mask, stored, P, kx, ky, d):
         assert rel_fro(dA[p], ref[p]["dA"]) <= TOL, (p, rel_fro(dA[p], ref[p]["dA"]))
         assert rel_fro(dB[p], ref[p]["dB"]) <= TOL, (p, rel_fro(dB[p], ref[p]["dB"]))
         assert abs(dl[p] - ref[p]["dl"]) <= TOL * ref[p]["dl_scale"], (p, dl[p], ref[p]["dl"], ref[p]["dl_scale"])
+
+
+# Tiled row solve (k_x > 64): tile-boundary sizes, the workspace-tile variant (k_x >= 224), rectangular maps.
+# The float32 error of a k x k Cholesky grows with k; inputs keep cond(A A^T) near 30 (d = 2k) and the bar
+# for these sizes is stated per case (derived: ~sqrt(k) * 6e-8 * cond(S)).
+LARGE_CASES = [(2, 65, 65, 160, 1e-5), (2, 96, 96, 200, 1e-5), (2, 127, 127, 256, 1e-5), (1, 128, 128, 256, 1e-5),
+               (1, 150, 150, 300, 2e-5), (1, 200, 200, 400, 2e-5), (1, 223, 223, 450, 2e-5),
+               (1, 224, 224, 450, 2e-5), (1, 300, 300, 600, 3e-5), (1, 319, 319, 640, 3e-5),
+               (2, 100, 40, 200, 1e-5), (2, 30, 100, 128, 1e-5)]
+
+
+@pytest.mark.parametrize("mask", [0, 1])
+@pytest.mark.parametrize("P,kx,ky,d,tol", LARGE_CASES)
+def test_solve_large_k(F, dev, mask, P, kx, ky, d, tol):
+    A, B, ex, ey, lam = _spectral(11, P, kx, ky, d)
+    dC = np.random.default_rng(6).standard_normal((P, ky, kx)).astype(np.float32)
+    tA, tB, tex, tey, tl = (T(x, dev) for x in (A, B, ex, ey, lam))
+    C, fac, info, _ = F.fmap_solve(tA, tB, tex, tey, tl, mask, 0.5)
+    Cr = N(C)
+    ref = _oracle_solve(A, B, ex, ey, lam, mask, 0.5, dC)
+    for p in range(P):
+        assert (N(info)[p] == 0).all()
+        assert rel_fro(Cr[p], ref[p]["C"]) <= tol, (p, rel_fro(Cr[p], ref[p]["C"]))
+    m = kx * (kx + 1) // 2
+    facn = N(fac)
+    for i in (0, ky - 1):
+        Lg = _unpack_lower_colmajor(facn[0, i * m:(i + 1) * m], kx)
+        assert rel_fro(Lg, ref[0]["L"][i]) <= tol
+    for stored in (True, False):
+        dA, dB, dl = F.fmap_solve_backward(T(dC, dev), tA, tB, C, tex, tey, tl, mask, 0.5,
+                                           fac if stored else None, want_dlam=True)
+        dA, dB, dl = N(dA), N(dB), N(dl)
+        for p in range(P):
+            assert rel_fro(dA[p], ref[p]["dA"]) <= tol, (stored, p, rel_fro(dA[p], ref[p]["dA"]))
+            assert rel_fro(dB[p], ref[p]["dB"]) <= tol, (stored, p, rel_fro(dB[p], ref[p]["dB"]))
+            assert abs(dl[p] - ref[p]["dl"]) <= tol * ref[p]["dl_scale"]
+
+
+def test_solve_large_k_info_convention(F, dev):
+    """Zero pivot inside a later block column of the tiled path: info = j+1, NaN row."""
+    P, k, d = 2, 150, 300
+    A, B, ex, ey, lam = _spectral(12, P, k, k, d)
+    A[0, 100] = 0.0
+    lam[0] = 0.0
+    lam[1] = -2.0
+    C, _, info, _ = F.fmap_solve(T(A, dev), T(B, dev), T(ex, dev), T(ey, dev), T(lam, dev), 0, 0.5)
+    C, info = N(C), N(info)
+    assert (info[0] == 101).all() and np.isnan(C[0]).all()
+    assert (info[1] == -1).all() and np.isnan(C[1]).all()
 
 
 def test_solve_info_convention(F, dev):
@@ -285,3 +340,65 @@ def test_repeat_calls_are_deterministic(F, dev):
     for x, y in zip(r1, r2):
         np.testing.assert_array_equal(x, y)
     torch.cuda.synchronize()
+
+
+# ----------------------------------------------------------------------------- refinement / conditioning
+
+def _conditioned(seed, P, k, d, sigma_ratio):
+    """A with singular values geometric from 1 down to 1/sigma_ratio (cond(A A^T) = sigma_ratio^2)."""
+    rng = np.random.default_rng(seed)
+    A = np.empty((P, k, d), np.float32)
+    for p in range(P):
+        U = synth.random_orthogonal(rng, k)
+        V = synth.random_orthogonal(rng, d)[:k]
+        s = np.geomspace(1.0, 1.0 / sigma_ratio, k)
+        A[p] = (U * s[None, :]) @ V
+    B = rng.standard_normal((P, k, d)).astype(np.float32) * 0.1
+    ex = np.stack([synth.eigenvalues_linear(rng, k) for _ in range(P)]).astype(np.float32)
+    ey = np.stack([synth.eigenvalues_linear(rng, k) for _ in range(P)]).astype(np.float32)
+    return A, B, ex, ey
+
+
+@pytest.mark.parametrize("k,d,ratio", [(50, 128, 30.0), (50, 128, 300.0), (120, 256, 100.0), (200, 400, 100.0)])
+def test_condition_estimate(F, dev, k, d, ratio):
+    """1-norm estimate of cond(A A^T) against the exact value (Hager's estimate is a lower bound, within ~x3)."""
+    P = 2
+    A, B, ex, ey = _conditioned(21, P, k, d, ratio)
+    lam = np.full(P, 1e-3, np.float32)
+    _, _, _, cond = F.fmap_solve(T(A, dev), T(B, dev), T(ex, dev), T(ey, dev), T(lam, dev), 0, 0.5, want_cond=True)
+    cond = N(cond)
+    for p in range(P):
+        Kx = A[p].astype(np.float64) @ A[p].astype(np.float64).T
+        exact = np.linalg.norm(Kx, 1) * np.linalg.norm(np.linalg.inv(Kx), 1)
+        assert exact / 10 <= cond[p] <= exact * 1.05, (p, cond[p], exact)
+
+
+@pytest.mark.parametrize("k,d,ratio,lam", [(50, 128, 300.0, 1e-6), (64, 160, 1000.0, 1e-7), (150, 300, 300.0, 1e-6),
+                                           (200, 400, 300.0, 1e-6)])
+def test_refinement_reduces_error(F, dev, k, d, ratio, lam):
+    P = 2
+    A, B, ex, ey = _conditioned(22, P, k, d, ratio)
+    lam = np.full(P, lam, np.float32)
+    args = [T(A, dev), T(B, dev), T(ex, dev), T(ey, dev), T(lam, dev), 0, 0.5]
+    C0 = N(F.fmap_solve(*args)[0])
+    C1 = N(F.fmap_solve(*args, refine_steps=1)[0])
+    C2 = N(F.fmap_solve(*args, refine_steps=2)[0])
+    ref = _oracle_solve(A, B, ex, ey, lam, 0, 0.5)
+    for p in range(P):
+        e0, e1, e2 = (rel_fro(C[p], ref[p]["C"]) for C in (C0, C1, C2))
+        assert e1 <= 1.1 * e0 and e2 <= 1.1 * e1 + 1e-7, (p, e0, e1, e2)
+        assert e2 <= 1e-5, (p, e0, e1, e2)
+
+
+def test_fp64_normal_matrix_branch(F, dev):
+    """Pairs whose estimate exceeds the threshold factorise the rounded float64 product; the result stays
+    within tolerance after refinement and the estimate reports the ill-conditioning."""
+    P, k, d = 2, 40, 96
+    A, B, ex, ey = _conditioned(23, P, k, d, 3000.0)   # cond(A A^T) ~ 9e6
+    lam = np.full(P, 1e-4, np.float32)
+    args = [T(A, dev), T(B, dev), T(ex, dev), T(ey, dev), T(lam, dev), 0, 0.5]
+    C, _, info, cond = F.fmap_solve(*args, refine_steps=2, cond_fp64_threshold=1e6, want_cond=True)
+    ref = _oracle_solve(A, B, ex, ey, lam, 0, 0.5)
+    assert (N(cond) > 1e6).all()
+    for p in range(P):
+        assert rel_fro(N(C)[p], ref[p]["C"]) <= 1e-5, (p, rel_fro(N(C)[p], ref[p]["C"]))
