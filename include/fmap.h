@@ -140,6 +140,47 @@ fmap_status fmap_solve_backward(const float *dC, const float *A, const float *B,
                                 float *dA, float *dB, float *dlambda, int32_t *info, void *workspace,
                                 size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Uneven batches (shape pairs with different n and k): a plan.                */
+/* The rows of all pairs are batch dimensions (Eq. (8)); pairs of equal k are   */
+/* grouped, the projections of every shape run as one persistent launch over   */
+/* a table of work items, and the whole forward (and backward) pass is         */
+/* captured once as a HIP graph that fmap_plan_forward / _backward replay.     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const float *phi_x, *phi_y;      /* [n_x][k], [n_y][k] float32 bases                        */
+    const float *mass_x, *mass_y;    /* [n_x], [n_y]                                            */
+    const float *feat_x, *feat_y;    /* [n_x][d], [n_y][d]                                      */
+    const float *evals_x, *evals_y;  /* [k], [k]                                                */
+    const float *lambda;             /* [1] (device; read at every forward)                     */
+    float *C;                        /* [k][k] output                                           */
+    int32_t *info;                   /* [k] output, as in fmap_solve                            */
+    float *A, *B;                    /* [k][d] outputs, or NULL                                 */
+    const float *dC;                 /* [k][k] upstream gradient, or NULL (no backward)          */
+    float *dF_x, *dF_y;              /* [n_x][d], [n_y][d] backward outputs (with dC)            */
+    int64_t n_x, n_y, k;
+} fmap_pair;
+
+typedef struct fmap_plan fmap_plan;
+
+/* Builds the plan for `npairs` pairs [host array; the device pointers inside  */
+/* are captured and must stay valid while the plan lives; their contents may   */
+/* change between replays].  Allocates the plan's device buffers (this call,   */
+/* not the replays, allocates).  Autotunes the projection work-item size, the  */
+/* persistent grid and the row systems per workgroup by timing candidates on   */
+/* `stream`, unless `tune_cache_path` [host, may be NULL] holds a result for   */
+/* this workload signature (results are appended to that file).  k <= 319;     */
+/* bwd_recompute != 0 refactorises in the backward instead of storing factors. */
+fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, int32_t mask_kind, float gamma,
+                             int32_t bwd_recompute, const char *tune_cache_path, void *stream, fmap_plan **out);
+fmap_status fmap_plan_forward(fmap_plan *plan, void *stream);   /* replays the captured forward  */
+fmap_status fmap_plan_backward(fmap_plan *plan, void *stream);  /* replays the captured backward */
+/* Tuned parameters: vertices per projection work item, persistent grid size,   */
+/* row systems per workgroup, and whether they came from the cache (1) or a run. */
+fmap_status fmap_plan_tuning(const fmap_plan *plan, int32_t *chunk, int32_t *grid, int32_t *systems_per_wg,
+                             int32_t *from_cache);
+fmap_status fmap_plan_destroy(fmap_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,19 @@ SIGNATURES = {
                           _vp, _vp, _sz, _vp]),
     "fmap_solve_backward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _f32, _i64, _i64, _i64, _i64, _vp, _vp,
                                    _vp, _vp, _vp, _vp, _sz, _vp]),
+    "fmap_plan_create": (_i32, [_vp, _i32, _i64, _i32, _f32, _i32, ctypes.c_char_p, _vp, _vp]),
+    "fmap_plan_forward": (_i32, [_vp, _vp]),
+    "fmap_plan_backward": (_i32, [_vp, _vp]),
+    "fmap_plan_tuning": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "fmap_plan_destroy": (_i32, [_vp]),
 }
+
+
+class FmapPair(ctypes.Structure):
+    """struct fmap_pair: one shape pair of a plan (device pointers and sizes)."""
+    _fields_ = [(name, _vp) for name in ("phi_x", "phi_y", "mass_x", "mass_y", "feat_x", "feat_y", "evals_x",
+                                         "evals_y", "lambda_", "C", "info", "A", "B", "dC", "dF_x", "dF_y")] + \
+               [("n_x", _i64), ("n_y", _i64), ("k", _i64)]
 
 _lib = None
 

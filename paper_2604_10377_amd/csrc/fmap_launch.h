@@ -12,6 +12,30 @@ constexpr int kSmallK = 64;
 // Largest k_x of the tiled row solve (k_x + 1 rows in at most 10 tile rows of 32).
 constexpr int kMaxK = 319;
 
+// Work items of the persistent projections over uneven shapes.
+struct FwdItem {                  // partial A rows [kbase, kbase+64) x d-block over vertices [v0, v1)
+    const float *phi, *mass, *feat;
+    float *out;                   // k x d partial slot
+    int n, k, d, v0, v1, kbase, dbase;
+};
+struct BwdItem {                  // dF rows [r0, r0 + 128*rb) x columns [dbase, dbase + 256)
+    const float *phi, *mass, *dA;
+    float *dF;
+    int n, k, d, r0, rb, dbase;
+};
+struct RedItem {                  // A = sum of `nchunks` partial k x d slots
+    const float *part;
+    float *A, *A_user;
+    int nchunks, kd;
+};
+
+hipError_t launch_fwd_items(const FwdItem *items, int nitems, int kmax, int grid, hipStream_t st);
+hipError_t launch_bwd_items(const BwdItem *items, int nitems, int kmax, int grid, hipStream_t st);
+hipError_t launch_reduce_items(const RedItem *items, int nitems, hipStream_t st);
+int device_cus();
+int rowsolve_waves();
+void set_rowsolve_waves(int w);
+
 struct ProjPlan {
     int MT, NT, kblocks, dblocks, nsplit, chunk;
 };

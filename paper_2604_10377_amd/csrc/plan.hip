@@ -1,0 +1,572 @@
+// Plans for uneven batches of shape pairs (different n and k per pair).
+//
+// fmap_plan_create groups the pairs by k (the rows of all pairs of a group are
+// one batch dimension, Eq. (8)), allocates the group buffers, and builds device
+// tables of work items:
+//   - forward projection items: (shape, vertex chunk, 64-row k block, 256-column
+//     d block), run by ONE persistent launch over all shapes of all groups;
+//   - reduction items: the fixed-order sum of each shape's chunk partials;
+//   - backward projection items: (shape, rows, d block), one persistent launch;
+//   - copy items: gather eigenvalues / lambda / dC into the group buffers and
+//     scatter C / info back to the pairs.
+// It then autotunes (vertices per item, persistent grid size, row systems per
+// workgroup, backward rows per item) by timing candidates on the caller's
+// stream, or takes them from the cache file, and captures the forward and the
+// backward pass as HIP graphs on a private stream.  fmap_plan_forward /
+// _backward replay the graphs on the caller's stream: no host work, no
+// allocation, no per-pair launches.
+#include "../../include/fmap.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fmap_launch.h"
+
+namespace fmap {
+
+struct CopyItem {
+    const uint32_t *src;  // 4-byte words, copied bit for bit (floats and int32 info alike)
+    uint32_t *dst;
+    int n;
+};
+
+__global__ __launch_bounds__(256) void copy_items_kernel(const CopyItem *__restrict__ items, int nitems)
+{
+    for (int it = blockIdx.y; it < nitems; it += gridDim.y) {
+        const CopyItem w = items[it];
+        for (int e = blockIdx.x * 256 + threadIdx.x; e < w.n; e += gridDim.x * 256) w.dst[e] = w.src[e];
+    }
+}
+
+static hipError_t launch_copies(const CopyItem *items, int nitems, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_items_kernel, dim3(4, (unsigned)std::min(nitems, 65535)), dim3(256), 0, st, items, nitems);
+    return hipGetLastError();
+}
+
+}  // namespace fmap
+
+using namespace fmap;
+
+struct Bucket {
+    int64_t k = 0;
+    std::vector<int> pairs;
+    float *AB = nullptr, *dAB = nullptr, *C = nullptr, *factors = nullptr, *evx = nullptr, *evy = nullptr,
+          *lam = nullptr, *dC = nullptr;
+    int32_t *info = nullptr;
+    void *ws = nullptr;
+};
+
+struct fmap_plan {
+    std::vector<fmap_pair> pairs;
+    int64_t d = 0;
+    int mask_kind = 0;
+    float gamma = 0.5f;
+    bool recompute = false, has_bwd = false;
+    int64_t kmax = 0;
+    std::vector<Bucket> buckets;
+    std::vector<void *> allocs;
+    float *partials = nullptr;
+    FwdItem *d_fwd = nullptr;
+    int nfwd = 0;
+    RedItem *d_red = nullptr;
+    int nred = 0;
+    BwdItem *d_bwd = nullptr;
+    int nbwd = 0;
+    CopyItem *d_gf = nullptr, *d_sf = nullptr, *d_gb = nullptr;
+    int ngf = 0, nsf = 0, ngb = 0;
+    int chunk = 1024, grid_fwd = 512, grid_bwd = 512, rb = 2, waves = 4, from_cache = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t gf = nullptr, gb = nullptr;
+    hipGraphExec_t ef = nullptr, eb = nullptr;
+};
+
+namespace {
+
+template <typename T>
+hipError_t dev_alloc(fmap_plan *pl, T **p, size_t count)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    pl->allocs.push_back(q);
+    *p = (T *)q;
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t upload(fmap_plan *pl, T **dptr, const std::vector<T> &v, hipStream_t st)
+{
+    hipError_t e = dev_alloc(pl, dptr, v.size());
+    if (e != hipSuccess) return e;
+    if (v.empty()) return hipSuccess;
+    e = hipMemcpyAsync(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+template <typename S, typename D>
+CopyItem words(const S *src, D *dst, int64_t n)
+{
+    static_assert(sizeof(S) == 4 && sizeof(D) == 4, "4-byte elements");
+    return CopyItem{(const uint32_t *)src, (uint32_t *)dst, (int)n};
+}
+
+struct Shape {
+    const float *phi, *mass, *feat;
+    float *A_user, *dF;
+    int64_t n, k;
+    int bucket, slot;  // slot within the bucket's [2P] shape array
+};
+
+std::vector<Shape> shapes_of(const fmap_plan *pl)
+{
+    std::vector<Shape> sh;
+    for (int b = 0; b < (int)pl->buckets.size(); ++b) {
+        const Bucket &B = pl->buckets[b];
+        const int P = (int)B.pairs.size();
+        for (int q = 0; q < P; ++q) {
+            const fmap_pair &pr = pl->pairs[B.pairs[q]];
+            sh.push_back({pr.phi_x, pr.mass_x, pr.feat_x, pr.A, pr.dF_x, pr.n_x, B.k, b, q});
+            sh.push_back({pr.phi_y, pr.mass_y, pr.feat_y, pr.B, pr.dF_y, pr.n_y, B.k, b, P + q});
+        }
+    }
+    return sh;
+}
+
+// Forward and reduction items for a given chunk size; partial slots are laid out shape after shape.
+void build_fwd_items(const fmap_plan *pl, int chunk, std::vector<FwdItem> &fi, std::vector<RedItem> &ri,
+                     size_t *partial_floats)
+{
+    fi.clear();
+    ri.clear();
+    size_t off = 0;
+    const int64_t d = pl->d;
+    for (const Shape &s : shapes_of(pl)) {
+        const Bucket &B = pl->buckets[s.bucket];
+        const int nch = (int)((s.n + chunk - 1) / chunk);
+        const int kb = (int)((s.k + 63) / 64), db = (int)((d + 255) / 256);
+        float *part = pl->partials ? pl->partials + off : nullptr;
+        for (int c = 0; c < nch; ++c)
+            for (int kk = 0; kk < kb; ++kk)
+                for (int dd = 0; dd < db; ++dd) {
+                    FwdItem w;
+                    w.phi = s.phi;
+                    w.mass = s.mass;
+                    w.feat = s.feat;
+                    w.out = part ? part + (size_t)c * s.k * d : nullptr;
+                    w.n = (int)s.n;
+                    w.k = (int)s.k;
+                    w.d = (int)d;
+                    w.v0 = c * chunk;
+                    w.v1 = (int)std::min<int64_t>(s.n, (int64_t)(c + 1) * chunk);
+                    w.kbase = kk * 64;
+                    w.dbase = dd * 256;
+                    fi.push_back(w);
+                }
+        RedItem r;
+        r.part = part;
+        r.A = B.AB + (size_t)s.slot * s.k * d;
+        r.A_user = s.A_user;
+        r.nchunks = nch;
+        r.kd = (int)(s.k * d);
+        ri.push_back(r);
+        off += (size_t)nch * s.k * d;
+    }
+    // longest items first: the static round-robin of the persistent grid then balances the tails
+    std::stable_sort(fi.begin(), fi.end(), [](const FwdItem &a, const FwdItem &b) { return a.v1 - a.v0 > b.v1 - b.v0; });
+    *partial_floats = off;
+}
+
+void build_bwd_items(const fmap_plan *pl, int rb, std::vector<BwdItem> &bi)
+{
+    bi.clear();
+    const int64_t d = pl->d;
+    for (const Shape &s : shapes_of(pl)) {
+        const Bucket &B = pl->buckets[s.bucket];
+        const int db = (int)((d + 255) / 256);
+        for (int64_t r0 = 0; r0 < s.n; r0 += 128 * rb)
+            for (int dd = 0; dd < db; ++dd) {
+                BwdItem w;
+                w.phi = s.phi;
+                w.mass = s.mass;
+                w.dA = B.dAB + (size_t)s.slot * s.k * d;
+                w.dF = s.dF;
+                w.n = (int)s.n;
+                w.k = (int)s.k;
+                w.d = (int)d;
+                w.r0 = (int)r0;
+                w.rb = rb;
+                w.dbase = dd * 256;
+                bi.push_back(w);
+            }
+    }
+}
+
+hipError_t record_forward(fmap_plan *pl, hipStream_t st)
+{
+    hipError_t e = launch_copies(pl->d_gf, pl->ngf, st);
+    if (e == hipSuccess) e = launch_fwd_items(pl->d_fwd, pl->nfwd, (int)pl->kmax, pl->grid_fwd, st);
+    if (e == hipSuccess) e = launch_reduce_items(pl->d_red, pl->nred, st);
+    set_rowsolve_waves(pl->waves);
+    for (Bucket &B : pl->buckets) {
+        if (e != hipSuccess) break;
+        const int64_t P = (int64_t)B.pairs.size();
+        e = launch_solve(B.AB, B.AB + (size_t)P * B.k * pl->d, B.evx, B.evy, B.lam, pl->mask_kind, pl->gamma, P, B.k,
+                         B.k, pl->d, 0, 0.f, B.C, pl->recompute ? nullptr : B.factors, B.info, nullptr, B.ws, st);
+    }
+    set_rowsolve_waves(4);
+    if (e == hipSuccess) e = launch_copies(pl->d_sf, pl->nsf, st);
+    return e;
+}
+
+hipError_t record_backward(fmap_plan *pl, hipStream_t st)
+{
+    hipError_t e = launch_copies(pl->d_gb, pl->ngb, st);
+    set_rowsolve_waves(pl->waves);
+    for (Bucket &B : pl->buckets) {
+        if (e != hipSuccess) break;
+        const int64_t P = (int64_t)B.pairs.size();
+        const size_t half = (size_t)P * B.k * pl->d;
+        e = launch_solve_backward(B.dC, B.AB, B.AB + half, B.C, B.evx, B.evy, B.lam, pl->mask_kind, pl->gamma, P, B.k,
+                                  B.k, pl->d, pl->recompute ? nullptr : B.factors, B.dAB, B.dAB + half, nullptr,
+                                  nullptr, B.ws, st);
+    }
+    set_rowsolve_waves(4);
+    if (e == hipSuccess) e = launch_bwd_items(pl->d_bwd, pl->nbwd, (int)pl->kmax, pl->grid_bwd, st);
+    return e;
+}
+
+// Median time (ms) of `reps` runs of fn on st.
+template <typename Fn>
+float time_ms(hipStream_t st, Fn fn, int reps = 3)
+{
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return 1e30f;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return 1e30f;
+    }
+    fn();  // warm-up
+    std::vector<float> t;
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(a, st);
+        fn();
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        t.push_back(ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+std::string signature(const fmap_plan *pl)
+{
+    int64_t verts = 0;
+    for (const fmap_pair &p : pl->pairs) verts += p.n_x + p.n_y;
+    char buf[256];
+    std::string ks;
+    for (const Bucket &B : pl->buckets) ks += std::to_string(B.k) + "x" + std::to_string(B.pairs.size()) + ",";
+    std::snprintf(buf, sizeof buf, "gfx950 f32 d=%lld mask=%d bwd=%d verts=%lldk pairs=%zu k=", (long long)pl->d,
+                  pl->mask_kind, pl->recompute ? 1 : 0, (long long)(verts / 1000), pl->pairs.size());
+    return std::string(buf) + ks;
+}
+
+bool cache_lookup(const char *path, const std::string &sig, fmap_plan *pl)
+{
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        std::string s(line);
+        const size_t bar = s.find('|');
+        if (bar == std::string::npos || s.substr(0, bar) != sig) continue;
+        int c, gfm, w, rb, gbm;
+        // only values the tuner itself can produce: the partial slots are sized for the smallest chunk
+        if (std::sscanf(s.c_str() + bar + 1, "%d %d %d %d %d", &c, &gfm, &w, &rb, &gbm) == 5 &&
+            (c == 512 || c == 1024 || c == 2048) && gfm >= 1 && gfm <= 65535 && (w == 2 || w == 4 || w == 8) &&
+            (rb == 1 || rb == 2 || rb == 4) && gbm >= 1 && gbm <= 65535) {
+            pl->chunk = c;
+            pl->grid_fwd = gfm;
+            pl->waves = w;
+            pl->rb = rb;
+            pl->grid_bwd = gbm;
+            found = true;  // the last matching line wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &sig, const fmap_plan *pl)
+{
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s|%d %d %d %d %d\n", sig.c_str(), pl->chunk, pl->grid_fwd, pl->waves, pl->rb, pl->grid_bwd);
+    std::fclose(f);
+}
+
+void plan_free(fmap_plan *pl)
+{
+    if (!pl) return;
+    if (pl->ef) (void)hipGraphExecDestroy(pl->ef);
+    if (pl->eb) (void)hipGraphExecDestroy(pl->eb);
+    if (pl->gf) (void)hipGraphDestroy(pl->gf);
+    if (pl->gb) (void)hipGraphDestroy(pl->gb);
+    if (pl->cap) (void)hipStreamDestroy(pl->cap);
+    for (void *p : pl->allocs) (void)hipFree(p);
+    delete pl;
+}
+
+}  // namespace
+
+extern "C" {
+
+fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, int32_t mask_kind, float gamma,
+                             int32_t bwd_recompute, const char *tune_cache_path, void *stream, fmap_plan **out)
+{
+    if (!pairs || !out) return FMAP_ERR_NULL;
+    *out = nullptr;
+    if (npairs < 1 || d < 1 || d > (1 << 20)) return FMAP_ERR_SHAPE;
+    if (mask_kind != FMAP_MASK_LAPLACIAN && mask_kind != FMAP_MASK_RESOLVENT) return FMAP_ERR_VALUE;
+    if (mask_kind == FMAP_MASK_RESOLVENT && !(gamma > 0.f && gamma < 1e30f)) return FMAP_ERR_VALUE;
+    const bool bwd = pairs[0].dC != nullptr;
+    for (int i = 0; i < npairs; ++i) {
+        const fmap_pair &p = pairs[i];
+        if (!p.phi_x || !p.phi_y || !p.mass_x || !p.mass_y || !p.feat_x || !p.feat_y || !p.evals_x || !p.evals_y ||
+            !p.lambda || !p.C || !p.info)
+            return FMAP_ERR_NULL;
+        if ((p.dC != nullptr) != bwd) return FMAP_ERR_NULL;  // all pairs or none take part in the backward
+        if (bwd && (!p.dF_x || !p.dF_y)) return FMAP_ERR_NULL;
+        if (p.k < 1 || p.n_x < 1 || p.n_y < 1 || p.n_x * p.k >= ((int64_t)1 << 31) || p.n_x * d >= ((int64_t)1 << 31) ||
+            p.n_y * p.k >= ((int64_t)1 << 31) || p.n_y * d >= ((int64_t)1 << 31))
+            return FMAP_ERR_SHAPE;
+        if (p.k > kMaxK) return FMAP_ERR_UNSUPPORTED;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    fmap_plan *pl = new fmap_plan();
+    pl->pairs.assign(pairs, pairs + npairs);
+    pl->d = d;
+    pl->mask_kind = mask_kind;
+    pl->gamma = gamma;
+    pl->recompute = bwd_recompute != 0;
+    pl->has_bwd = bwd;
+    std::map<int64_t, std::vector<int>> byk;
+    for (int i = 0; i < npairs; ++i) byk[pairs[i].k].push_back(i);
+    for (auto &kv : byk) {
+        Bucket B;
+        B.k = kv.first;
+        B.pairs = kv.second;
+        pl->buckets.push_back(B);
+        pl->kmax = std::max(pl->kmax, kv.first);
+    }
+#define FMAP_TRY(x)                  \
+    do {                             \
+        if ((x) != hipSuccess) {     \
+            plan_free(pl);           \
+            return FMAP_ERR_HIP;     \
+        }                            \
+    } while (0)
+    // group buffers
+    std::vector<CopyItem> gf, sf, gb;
+    for (Bucket &B : pl->buckets) {
+        const int64_t P = (int64_t)B.pairs.size(), k = B.k;
+        FMAP_TRY(dev_alloc(pl, &B.AB, (size_t)2 * P * k * d));
+        FMAP_TRY(dev_alloc(pl, &B.C, (size_t)P * k * k));
+        FMAP_TRY(dev_alloc(pl, &B.info, (size_t)P * k));
+        FMAP_TRY(dev_alloc(pl, &B.evx, (size_t)P * k));
+        FMAP_TRY(dev_alloc(pl, &B.evy, (size_t)P * k));
+        FMAP_TRY(dev_alloc(pl, &B.lam, (size_t)P));
+        if (!pl->recompute) FMAP_TRY(dev_alloc(pl, &B.factors, (size_t)P * k * (k * (k + 1) / 2)));
+        if (bwd) {
+            FMAP_TRY(dev_alloc(pl, &B.dC, (size_t)P * k * k));
+            FMAP_TRY(dev_alloc(pl, &B.dAB, (size_t)2 * P * k * d));
+        }
+        FMAP_TRY(dev_alloc(pl, (char **)&B.ws, solve_workspace_layout(P, k, k, d).total));
+        for (int q = 0; q < (int)P; ++q) {
+            const fmap_pair &p = pairs[B.pairs[q]];
+            gf.push_back(words(p.evals_x, B.evx + (size_t)q * k, k));
+            gf.push_back(words(p.evals_y, B.evy + (size_t)q * k, k));
+            gf.push_back(words(p.lambda, B.lam + q, 1));
+            sf.push_back(words(B.C + (size_t)q * k * k, p.C, k * k));
+            sf.push_back(words(B.info + (size_t)q * k, p.info, k));
+            if (bwd) gb.push_back(words(p.dC, B.dC + (size_t)q * k * k, k * k));
+        }
+    }
+    pl->ngf = (int)gf.size();
+    pl->nsf = (int)sf.size();
+    pl->ngb = (int)gb.size();
+    FMAP_TRY(upload(pl, &pl->d_gf, gf, st));
+    FMAP_TRY(upload(pl, &pl->d_sf, sf, st));
+    FMAP_TRY(upload(pl, &pl->d_gb, gb, st));
+
+    // partial slots sized for the smallest candidate chunk
+    const int chunks[3] = {512, 1024, 2048};
+    {
+        std::vector<FwdItem> fi;
+        std::vector<RedItem> ri;
+        size_t pf = 0;
+        build_fwd_items(pl, chunks[0], fi, ri, &pf);
+        FMAP_TRY(dev_alloc(pl, &pl->partials, pf));
+    }
+    const std::string sig = signature(pl);
+    const int cus = device_cus();
+    pl->from_cache = cache_lookup(tune_cache_path, sig, pl) ? 1 : 0;
+
+    auto set_fwd = [&](int chunk) -> hipError_t {
+        std::vector<FwdItem> fi;
+        std::vector<RedItem> ri;
+        size_t pf = 0;
+        build_fwd_items(pl, chunk, fi, ri, &pf);
+        pl->nfwd = (int)fi.size();
+        pl->nred = (int)ri.size();
+        hipError_t e = upload(pl, &pl->d_fwd, fi, st);
+        if (e == hipSuccess) e = upload(pl, &pl->d_red, ri, st);
+        return e;
+    };
+    auto set_bwd = [&](int rb) -> hipError_t {
+        std::vector<BwdItem> bi;
+        build_bwd_items(pl, rb, bi);
+        pl->nbwd = (int)bi.size();
+        return upload(pl, &pl->d_bwd, bi, st);
+    };
+
+    if (!pl->from_cache) {
+        // forward projection: vertices per item x persistent grid
+        float best = 1e30f;
+        int bc = 1024, bg = 2 * cus;
+        for (int c : chunks) {
+            FMAP_TRY(set_fwd(c));
+            for (int gm : {1, 2, 4}) {
+                const int g = std::max(1, std::min(gm * cus, pl->nfwd));
+                const float t = time_ms(st, [&]() {
+                    (void)launch_fwd_items(pl->d_fwd, pl->nfwd, (int)pl->kmax, g, st);
+                    (void)launch_reduce_items(pl->d_red, pl->nred, st);
+                });
+                if (t < best) {
+                    best = t;
+                    bc = c;
+                    bg = g;
+                }
+            }
+        }
+        pl->chunk = bc;
+        pl->grid_fwd = bg;
+        // row systems per workgroup of the register row solve (groups with k <= 64)
+        FMAP_TRY(set_fwd(pl->chunk));
+        FMAP_TRY(launch_copies(pl->d_gf, pl->ngf, st));
+        FMAP_TRY(launch_fwd_items(pl->d_fwd, pl->nfwd, (int)pl->kmax, pl->grid_fwd, st));
+        FMAP_TRY(launch_reduce_items(pl->d_red, pl->nred, st));
+        best = 1e30f;
+        int bw = 4;
+        for (int w : {2, 4, 8}) {
+            const float t = time_ms(st, [&]() {
+                set_rowsolve_waves(w);
+                for (Bucket &B : pl->buckets) {
+                    if (B.k > kSmallK) continue;
+                    const int64_t P = (int64_t)B.pairs.size();
+                    (void)launch_solve(B.AB, B.AB + (size_t)P * B.k * d, B.evx, B.evy, B.lam, mask_kind, gamma, P, B.k,
+                                       B.k, d, 0, 0.f, B.C, B.factors, B.info, nullptr, B.ws, st);
+                }
+                set_rowsolve_waves(4);
+            });
+            if (t < best) {
+                best = t;
+                bw = w;
+            }
+        }
+        pl->waves = bw;
+        // backward projection: rows per item x persistent grid
+        if (bwd) {
+            best = 1e30f;
+            int brb = 2, bgb = 2 * cus;
+            for (int rb : {1, 2, 4}) {
+                FMAP_TRY(set_bwd(rb));
+                for (int gm : {1, 2, 4}) {
+                    const int g = std::max(1, std::min(gm * cus, pl->nbwd));
+                    const float t = time_ms(st, [&]() {
+                        (void)launch_bwd_items(pl->d_bwd, pl->nbwd, (int)pl->kmax, g, st);
+                    });
+                    if (t < best) {
+                        best = t;
+                        brb = rb;
+                        bgb = g;
+                    }
+                }
+            }
+            pl->rb = brb;
+            pl->grid_bwd = bgb;
+        }
+        cache_store(tune_cache_path, sig, pl);
+    }
+    FMAP_TRY(set_fwd(pl->chunk));
+    if (bwd) FMAP_TRY(set_bwd(pl->rb));
+
+    // one eager pass (sets up every kernel), then capture both passes
+    FMAP_TRY(record_forward(pl, st));
+    if (bwd) FMAP_TRY(record_backward(pl, st));
+    FMAP_TRY(hipStreamSynchronize(st));
+    FMAP_TRY(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
+    FMAP_TRY(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t rec = record_forward(pl, pl->cap);
+    hipError_t endc = hipStreamEndCapture(pl->cap, &pl->gf);
+    FMAP_TRY(rec);
+    FMAP_TRY(endc);
+    FMAP_TRY(hipGraphInstantiate(&pl->ef, pl->gf, nullptr, nullptr, 0));
+    if (bwd) {
+        FMAP_TRY(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+        rec = record_backward(pl, pl->cap);
+        endc = hipStreamEndCapture(pl->cap, &pl->gb);
+        FMAP_TRY(rec);
+        FMAP_TRY(endc);
+        FMAP_TRY(hipGraphInstantiate(&pl->eb, pl->gb, nullptr, nullptr, 0));
+    }
+#undef FMAP_TRY
+    *out = pl;
+    return FMAP_OK;
+}
+
+fmap_status fmap_plan_forward(fmap_plan *plan, void *stream)
+{
+    if (!plan || !plan->ef) return FMAP_ERR_NULL;
+    return hipGraphLaunch(plan->ef, (hipStream_t)stream) == hipSuccess ? FMAP_OK : FMAP_ERR_HIP;
+}
+
+fmap_status fmap_plan_backward(fmap_plan *plan, void *stream)
+{
+    if (!plan) return FMAP_ERR_NULL;
+    if (!plan->eb) return FMAP_ERR_UNSUPPORTED;  // created without dC
+    return hipGraphLaunch(plan->eb, (hipStream_t)stream) == hipSuccess ? FMAP_OK : FMAP_ERR_HIP;
+}
+
+fmap_status fmap_plan_tuning(const fmap_plan *plan, int32_t *chunk, int32_t *grid, int32_t *systems_per_wg,
+                             int32_t *from_cache)
+{
+    if (!plan) return FMAP_ERR_NULL;
+    if (chunk) *chunk = plan->chunk;
+    if (grid) *grid = plan->grid_fwd;
+    if (systems_per_wg) *systems_per_wg = plan->waves;
+    if (from_cache) *from_cache = plan->from_cache;
+    return FMAP_OK;
+}
+
+fmap_status fmap_plan_destroy(fmap_plan *plan)
+{
+    if (!plan) return FMAP_ERR_NULL;
+    plan_free(plan);
+    return FMAP_OK;
+}
+
+}  // extern "C"

@@ -29,31 +29,18 @@ __device__ __forceinline__ float load_elem<float>(const float *p, size_t i) { re
 template <>
 __device__ __forceinline__ float load_elem<uint16_t>(const uint16_t *p, size_t i) { return bf16_to_f32(p[i]); }
 
+// One (shape, vertex range, k-block, column block) of the forward projection:
+// partial A rows [kbase, kbase + MT*32) x columns [dbase4 + wave*NT*32, ...)
+// over vertices [v0, v1), written to O (row-major k x d).
 template <typename T, int MT, int NT, int U>
-__global__ __launch_bounds__(256) void proj_fwd_kernel(const T *__restrict__ phi, const float *__restrict__ mass,
-                                                       const T *__restrict__ feat, int n, int k, int d, int nsplit,
-                                                       int chunk, int kblocks, int dblocks,
-                                                       float *__restrict__ out)
+__device__ __forceinline__ void proj_fwd_tile(const T *__restrict__ P, const float *__restrict__ Mv,
+                                              const T *__restrict__ F, int k, int d, int v0, int v1, int kbase,
+                                              int dbase4, float *__restrict__ O)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, l32 = lane & 31;
-    int bid = blockIdx.x;
-    const int db = bid % dblocks;
-    bid /= dblocks;
-    const int kb = bid % kblocks;
-    bid /= kblocks;
-    const int split = bid % nsplit;
-    const int s = bid / nsplit;
-
-    const int v0 = split * chunk;
-    const int v1 = min(n, v0 + chunk);
-    const int kbase = kb * (MT * 32);
-    const int dbase = (db * 4 + wave) * (NT * 32);
+    const int dbase = dbase4 + wave * (NT * 32);
     if (dbase >= d) return;  // whole wave idle (narrow d)
-
-    const T *P = phi + (size_t)s * n * k;
-    const T *F = feat + (size_t)s * n * d;
-    const float *Mv = mass + (size_t)s * n;
 
     int rows[MT], cols[NT];
     bool rok[MT], cok[NT];
@@ -125,7 +112,6 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(const T *__restrict__ phi
             for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma32x32x2(a[mt], b[nt], acc[mt][nt]);
     }
 
-    float *O = out + ((size_t)s * nsplit + split) * (size_t)k * d;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -135,6 +121,37 @@ __global__ __launch_bounds__(256) void proj_fwd_kernel(const T *__restrict__ phi
                 const int row = kbase + mt * 32 + acc32_row(r, lane);
                 if (row < k && cok[nt]) O[(size_t)row * d + cols[nt]] = acc[mt][nt][r];
             }
+}
+
+template <typename T, int MT, int NT, int U>
+__global__ __launch_bounds__(256) void proj_fwd_kernel(const T *__restrict__ phi, const float *__restrict__ mass,
+                                                       const T *__restrict__ feat, int n, int k, int d, int nsplit,
+                                                       int chunk, int kblocks, int dblocks,
+                                                       float *__restrict__ out)
+{
+    int bid = blockIdx.x;
+    const int db = bid % dblocks;
+    bid /= dblocks;
+    const int kb = bid % kblocks;
+    bid /= kblocks;
+    const int split = bid % nsplit;
+    const int s = bid / nsplit;
+    const int v0 = split * chunk;
+    const int v1 = min(n, v0 + chunk);
+    proj_fwd_tile<T, MT, NT, U>(phi + (size_t)s * n * k, mass + (size_t)s * n, feat + (size_t)s * n * d, k, d, v0, v1,
+                                kb * (MT * 32), db * 4 * (NT * 32),
+                                out + ((size_t)s * nsplit + split) * (size_t)k * d);
+}
+
+// Persistent forward over a table of work items (uneven shapes): each workgroup
+// takes items blockIdx.x, blockIdx.x + gridDim.x, ...
+template <int MT, int NT, int U>
+__global__ __launch_bounds__(256) void proj_fwd_items_kernel(const FwdItem *__restrict__ items, int nitems)
+{
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const FwdItem w = items[it];
+        proj_fwd_tile<float, MT, NT, U>(w.phi, w.mass, w.feat, w.k, w.d, w.v0, w.v1, w.kbase, w.dbase, w.out);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -513,26 +530,16 @@ constexpr int BWD_KC = 64;
 
 __host__ __device__ constexpr int bwd_stride(int nt) { return (nt * 32) % 64 == 32 ? nt * 32 : nt * 32 + 32; }
 
+// RB consecutive blocks of 128 vertices starting at vertex r0 of one shape, for
+// the column block [dbase, dbase + NT*32).  Must be called by all 256 threads.
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void proj_bwd_kernel(const T *__restrict__ phi, const float *__restrict__ mass,
-                                                       const float *__restrict__ dA, int n, int k, int d,
-                                                       int rgroups, int RB, int dblocks, float *__restrict__ dF)
+__device__ __forceinline__ void proj_bwd_rows(float *sG, const T *__restrict__ P, const float *__restrict__ Mv,
+                                              const float *__restrict__ G, float *__restrict__ O, int n, int k, int d,
+                                              int r0, int RB, int dbase)
 {
-    extern __shared__ float sG[];  // [min(k,KC) rounded to even][bwd_stride(NT)]
     constexpr int LD = bwd_stride(NT);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, l32 = lane & 31;
-    int bid = blockIdx.x;
-    const int db = bid % dblocks;
-    bid /= dblocks;
-    const int rg = bid % rgroups;
-    const int s = bid / rgroups;
-    const int dbase = db * (NT * 32);
-
-    const T *P = phi + (size_t)s * n * k;
-    const float *G = dA + (size_t)s * k * d;
-    float *O = dF + (size_t)s * n * d;
-
     int cols[NT];
     bool cok[NT];
 #pragma unroll
@@ -541,7 +548,6 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const T *__restrict__ phi
         cok[nt] = cols[nt] < d;
     }
     const int nchunks = (k + BWD_KC - 1) / BWD_KC;
-
     auto stage = [&](int j0, int kc) {
         const int kc2 = (kc + 1) & ~1;
         for (int e = threadIdx.x; e < kc2 * NT * 32; e += 256) {
@@ -550,16 +556,16 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const T *__restrict__ phi
             sG[jj * LD + cc] = (jj < kc && col < d) ? G[(size_t)(j0 + jj) * d + col] : 0.f;
         }
     };
+    __syncthreads();  // sG may still be read by a previous call
     if (nchunks == 1) {
         stage(0, k);
         __syncthreads();
     }
-
     for (int rb = 0; rb < RB; ++rb) {
-        const int row0 = ((rg * RB + rb) * 4 + wave) * 32;
+        const int row0 = r0 + (rb * 4 + wave) * 32;
         const int row = row0 + l32;
         const bool rok = row < n;
-        const float m = rok ? mass[(size_t)s * n + row] : 0.f;
+        const float m = rok ? Mv[row] : 0.f;
         f32x16 acc[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[nt] = zero16();
@@ -596,6 +602,32 @@ __global__ __launch_bounds__(256) void proj_bwd_kernel(const T *__restrict__ phi
                     if (rr < n && cok[nt]) O[(size_t)rr * d + cols[nt]] = acc[nt][r];
                 }
         }
+    }
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void proj_bwd_kernel(const T *__restrict__ phi, const float *__restrict__ mass,
+                                                       const float *__restrict__ dA, int n, int k, int d,
+                                                       int rgroups, int RB, int dblocks, float *__restrict__ dF)
+{
+    extern __shared__ float sG[];  // [min(k,KC) rounded to even][bwd_stride(NT)]
+    int bid = blockIdx.x;
+    const int db = bid % dblocks;
+    bid /= dblocks;
+    const int rg = bid % rgroups;
+    const int s = bid / rgroups;
+    proj_bwd_rows<T, NT>(sG, phi + (size_t)s * n * k, mass + (size_t)s * n, dA + (size_t)s * k * d,
+                         dF + (size_t)s * n * d, n, k, d, rg * RB * 128, RB, db * (NT * 32));
+}
+
+// Persistent backward over a table of work items (uneven shapes).
+template <int NT>
+__global__ __launch_bounds__(256) void proj_bwd_items_kernel(const BwdItem *__restrict__ items, int nitems)
+{
+    extern __shared__ float sG[];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BwdItem w = items[it];
+        proj_bwd_rows<float, NT>(sG, w.phi, w.mass, w.dA, w.dF, w.n, w.k, w.d, w.r0, w.rb, w.dbase);
     }
 }
 
@@ -723,6 +755,46 @@ static void launch_fwd_dt(const void *phi, const float *mass, const void *feat, 
     else if (p.MT == 1) launch_fwd_t<T, 1, 2>(phi, mass, feat, batch, n, k, d, p, out, st);
     else if (p.NT == 1) launch_fwd_t<T, 2, 1>(phi, mass, feat, batch, n, k, d, p, out, st);
     else launch_fwd_t<T, 2, 2>(phi, mass, feat, batch, n, k, d, p, out, st);
+}
+
+// Per-shape reduction of partial slots (uneven shapes), fixed chunk order.
+__global__ __launch_bounds__(256) void reduce_items_kernel(const RedItem *__restrict__ items, int nitems)
+{
+    for (int it = blockIdx.y; it < nitems; it += gridDim.y) {
+        const RedItem w = items[it];
+        for (int e = blockIdx.x * 256 + threadIdx.x; e < w.kd; e += gridDim.x * 256) {
+            float acc = 0.f;
+            for (int c = 0; c < w.nchunks; ++c) acc += w.part[(size_t)c * w.kd + e];
+            w.A[e] = acc;
+            if (w.A_user) w.A_user[e] = acc;
+        }
+    }
+}
+
+int device_cus() { return device_cu_count(); }
+
+hipError_t launch_fwd_items(const FwdItem *items, int nitems, int kmax, int grid, hipStream_t st)
+{
+    if (kmax <= 32)
+        hipLaunchKernelGGL((proj_fwd_items_kernel<1, 2, 8>), dim3(grid), dim3(256), 0, st, items, nitems);
+    else
+        hipLaunchKernelGGL((proj_fwd_items_kernel<2, 2, 8>), dim3(grid), dim3(256), 0, st, items, nitems);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_items(const BwdItem *items, int nitems, int kmax, int grid, hipStream_t st)
+{
+    const int kc = kmax < BWD_KC ? kmax : BWD_KC;
+    const size_t lds = (size_t)((kc + 1) & ~1) * bwd_stride(8) * sizeof(float);
+    hipLaunchKernelGGL((proj_bwd_items_kernel<8>), dim3(grid), dim3(256), lds, st, items, nitems);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_items(const RedItem *items, int nitems, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_items_kernel, dim3(16, (unsigned)(nitems < 65535 ? nitems : 65535)), dim3(256), 0, st,
+                       items, nitems);
+    return hipGetLastError();
 }
 
 static hipError_t launch_reduce(const float *part, int nsplit, int64_t batch, int64_t k, int64_t d, float *A,

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
     float *x = L + kx * (kx + 1) / 2;                // kx
     float *z = x + kx;                               // kx
     __shared__ float s_red[8];
-    __shared__ int s_fail, s_j;
+    __shared__ int s_fail;
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float *Kp = K + (size_t)p * kx * kx;
     for (int e = tid; e < kx * kx; e += 512) {

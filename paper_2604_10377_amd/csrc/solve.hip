@@ -117,12 +117,16 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     const float *__restrict__ Cfwd, float *__restrict__ dlam_part, const float *addend)
 {
     static_assert(KMAX % 4 == 0 && KMAX <= 64, "register row length");
-    __shared__ __align__(16) float s_bc[4][KMAX];
-    __shared__ float s_L[4][KMAX * (KMAX + 1) / 2];  // rows of L, packed (row r at r(r+1)/2)
+    // per wave: broadcast vector (KMAX) + rows of L packed (row r at r(r+1)/2); W = systems per workgroup
+    constexpr int PER_WAVE = KMAX + KMAX * (KMAX + 1) / 2;
+    extern __shared__ __align__(16) float s_rs[];
     const int j = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int rgroups = (ky + 3) >> 2;
+    const int W = blockDim.x >> 6;
+    float *s_bcw = s_rs + w * PER_WAVE;
+    float *s_Lw = s_bcw + KMAX;
+    const int rgroups = (ky + W - 1) / W;
     const int p = blockIdx.x / rgroups;
-    const int i = (blockIdx.x % rgroups) * 4 + w;
+    const int i = (blockIdx.x % rgroups) * W + w;
     if (i >= ky) return;  // wave-uniform; no block-level barrier below
     const int T = kx * (kx + 1) / 2;
     const bool jok = j < kx;
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     float yv = 0.f, myinv = 0.f;
 
     if (MODE != RS_BWD_STORED) {
-        float *bc = s_bc[w];
+        float *bc = s_bcw;
 #pragma unroll
         for (int c = 0; c < KMAX; ++c) {
             if (c < kx && fail == 0) {
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     float cv = NAN;
     if (fail == 0) {
         // stage the rows of L, then take column j of L into registers
-        float *Lr = s_L[w];
+        float *Lr = s_Lw;
         const int rowoff = j * (j + 1) / 2;
 #pragma unroll
         for (int q = 0; q < KMAX; ++q)
@@ -423,16 +427,33 @@ static void launch_gram(const float *A, const float *B, int64_t P, int64_t kx, i
                        tkx, tky, with_R ? 1 : 0, K, R);
 }
 
+// Row systems (waves) per workgroup of the register row solve; the plan's
+// autotuner overrides it for the launches it records.
+static thread_local int g_rowsolve_waves = 4;
+int rowsolve_waves() { return g_rowsolve_waves; }
+void set_rowsolve_waves(int w) { g_rowsolve_waves = (w == 1 || w == 2 || w == 4 || w == 8) ? w : 4; }
+
 template <int MODE>
 static void launch_rowsolve(const float *K, const float *Lin, const float *rhs, const float *ex, const float *ey,
                             const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky,
                             float *out, float *Lout, int *info, const float *Cfwd, float *dlam_part, hipStream_t st,
                             const float *addend = nullptr)
 {
-    const unsigned grid = (unsigned)(P * ((ky + 3) / 4));
-#define FMAP_RS(KM)                                                                                            \
-    hipLaunchKernelGGL((rowsolve_kernel<KM, MODE>), dim3(grid), dim3(256), 0, st, K, Lin, rhs, ex, ey, lam,    \
-                       mask_kind, gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part, addend)
+    const int W = rowsolve_waves();
+    const unsigned grid = (unsigned)(P * ((ky + W - 1) / W));
+#define FMAP_RS(KM)                                                                                             \
+    do {                                                                                                        \
+        static bool attr = false;                                                                               \
+        if (!attr) {                                                                                            \
+            (void)hipFuncSetAttribute((const void *)rowsolve_kernel<KM, MODE>,                                  \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,                               \
+                                      (int)(8 * (KM + KM * (KM + 1) / 2) * sizeof(float)));                     \
+            attr = true;                                                                                        \
+        }                                                                                                       \
+        hipLaunchKernelGGL((rowsolve_kernel<KM, MODE>), dim3(grid), dim3(64 * W),                                \
+                           (size_t)W * (KM + KM * (KM + 1) / 2) * sizeof(float), st, K, Lin, rhs, ex, ey, lam,   \
+                           mask_kind, gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part, addend);        \
+    } while (0)
     if (kx <= 8) FMAP_RS(8);
     else if (kx <= 16) FMAP_RS(16);
     else if (kx <= 24) FMAP_RS(24);

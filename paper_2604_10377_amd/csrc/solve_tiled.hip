@@ -214,8 +214,10 @@ __global__ __launch_bounds__(512) void rowsolve_tiles_kernel(
                     for (int t = 0; t < 16; ++t)
                         nv = mfma32x32x2(X[l32 * TLD + 2 * t + half], s_minv[l32 * TLD + 2 * t + half], nv);
                     __builtin_amdgcn_wave_barrier();
+                    // with stored factors the tile's other rows are final L rows: only the appended row moves
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) X[acc32_row(r, lane) * TLD + l32] = nv[r];
+                    for (int r = 0; r < 16; ++r)
+                        if (!STORED || acc32_row(r, lane) == ar) X[acc32_row(r, lane) * TLD + l32] = nv[r];
                 }
                 if (STORED && AR == pstep && wave == 0) {
                     // appended row inside the diagonal tile: y_c = sum_t Minv[c][t] s_t
@@ -259,7 +261,8 @@ __global__ __launch_bounds__(512) void rowsolve_tiles_kernel(
                     for (int t = 0; t < 16; ++t)
                         acc = mfma32x32x2(-LI[l32 * TLD + 2 * t + half], LJ[l32 * TLD + 2 * t + half], acc);
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) X[acc32_row(r, lane) * TLD + l32] = acc[r];
+                    for (int r = 0; r < 16; ++r)
+                        if (!STORED || acc32_row(r, lane) == ar) X[acc32_row(r, lane) * TLD + l32] = acc[r];
                 }
             }
             // y of this block column (the appended row) is final

@@ -225,3 +225,89 @@ class FmapSolveFn(torch.autograd.Function):
 def functional_map(feat, phi, mass, evals, lam, mask_kind=FMAP_MASK_LAPLACIAN, gamma=0.5, bwd="stored"):
     """Differentiable batched functional map; returns (C [P,k,k], info [P,k])."""
     return FmapSolveFn.apply(feat, phi, mass, evals, lam, mask_kind, gamma, bwd)
+
+
+# ---------------------------------------------------------------------------- uneven batches
+
+class FmapPlan:
+    """Captured forward (and backward) pass over shape pairs of different n and k.
+
+    `pairs` is a sequence of dicts with device tensors phi_x [n_x, k], phi_y [n_y, k],
+    mass_x [n_x], mass_y [n_y], feat_x [n_x, d], feat_y [n_y, d], evals_x [k],
+    evals_y [k] and lam [1] (all float32, one device).  The plan owns the outputs
+    C[i] [k, k] and info[i] [k] (and, with backward=True, the upstream gradient
+    slots dC[i] [k, k] and the results dF_x[i], dF_y[i]).  The input tensors are
+    captured by address: update them in place between replays, never rebind.
+    """
+
+    def __init__(self, pairs, mask_kind: int = FMAP_MASK_LAPLACIAN, gamma: float = 0.5, *, backward: bool = True,
+                 recompute: bool = False, tune_cache: Optional[str] = None, want_AB: bool = False):
+        if len(pairs) == 0:
+            raise ValueError("a plan needs at least one pair")
+        dev = pairs[0]["phi_x"].device
+        d = pairs[0]["feat_x"].shape[1]
+        self.device, self.d = dev, d
+        self.inputs = [dict(p) for p in pairs]
+        self.C, self.info, self.A, self.B, self.dC, self.dF_x, self.dF_y = [], [], [], [], [], [], []
+        arr = (_lib.FmapPair * len(pairs))()
+        for i, p in enumerate(self.inputs):
+            nx, k = p["phi_x"].shape
+            ny = p["phi_y"].shape[0]
+            _need(p["phi_x"], "phi_x", torch.float32, (nx, k), dev)
+            _need(p["phi_y"], "phi_y", torch.float32, (ny, k), dev)
+            _need(p["mass_x"], "mass_x", torch.float32, (nx,), dev)
+            _need(p["mass_y"], "mass_y", torch.float32, (ny,), dev)
+            _need(p["feat_x"], "feat_x", torch.float32, (nx, d), dev)
+            _need(p["feat_y"], "feat_y", torch.float32, (ny, d), dev)
+            _need(p["evals_x"], "evals_x", torch.float32, (k,), dev)
+            _need(p["evals_y"], "evals_y", torch.float32, (k,), dev)
+            _need(p["lam"], "lam", torch.float32, (1,), dev)
+            self.C.append(torch.empty((k, k), dtype=torch.float32, device=dev))
+            self.info.append(torch.empty((k,), dtype=torch.int32, device=dev))
+            self.A.append(torch.empty((k, d), dtype=torch.float32, device=dev) if want_AB else None)
+            self.B.append(torch.empty((k, d), dtype=torch.float32, device=dev) if want_AB else None)
+            self.dC.append(torch.zeros((k, k), dtype=torch.float32, device=dev) if backward else None)
+            self.dF_x.append(torch.empty((nx, d), dtype=torch.float32, device=dev) if backward else None)
+            self.dF_y.append(torch.empty((ny, d), dtype=torch.float32, device=dev) if backward else None)
+            e = arr[i]
+            for name in ("phi_x", "phi_y", "mass_x", "mass_y", "feat_x", "feat_y", "evals_x", "evals_y"):
+                setattr(e, name, p[name].data_ptr())
+            e.lambda_ = p["lam"].data_ptr()
+            e.C, e.info = self.C[i].data_ptr(), self.info[i].data_ptr()
+            e.A = self.A[i].data_ptr() if want_AB else None
+            e.B = self.B[i].data_ptr() if want_AB else None
+            if backward:
+                e.dC, e.dF_x, e.dF_y = self.dC[i].data_ptr(), self.dF_x[i].data_ptr(), self.dF_y[i].data_ptr()
+            e.n_x, e.n_y, e.k = nx, ny, k
+        handle = ctypes.c_void_p()
+        cache = None if tune_cache is None else str(tune_cache).encode()
+        _lib.check("fmap_plan_create", _lib.lib().fmap_plan_create(
+            ctypes.cast(arr, ctypes.c_void_p), len(pairs), d, int(mask_kind), float(gamma), int(bool(recompute)),
+            cache, _stream(dev), ctypes.byref(handle)))
+        self._h = handle
+
+    def forward(self):
+        """Replays the captured forward on the current stream; returns the list of C."""
+        _lib.check("fmap_plan_forward", _lib.lib().fmap_plan_forward(self._h, _stream(self.device)))
+        return self.C
+
+    def backward(self):
+        """Replays the captured backward (reads dC[i], writes dF_x[i], dF_y[i])."""
+        _lib.check("fmap_plan_backward", _lib.lib().fmap_plan_backward(self._h, _stream(self.device)))
+        return self.dF_x, self.dF_y
+
+    def tuning(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(4)]
+        _lib.check("fmap_plan_tuning", _lib.lib().fmap_plan_tuning(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(chunk=v[0].value, grid=v[1].value, systems_per_wg=v[2].value, from_cache=bool(v[3].value))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check("fmap_plan_destroy", _lib.lib().fmap_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -115,3 +115,49 @@ def test_solve_backward_validation(L):
     assert sb(mask=9) == 3
     assert sb(ws=NULL) == 5
     assert sb(wsb=16) == 5
+
+
+def _pairs(n=2, k=8, **over):
+    arr = (_lib.FmapPair * n)()
+    for e in arr:
+        for name, _ in _lib.FmapPair._fields_[:16]:
+            setattr(e, name, 0x1000)
+        e.A = e.B = None
+        e.dC = e.dF_x = e.dF_y = None
+        e.n_x, e.n_y, e.k = 100, 120, k
+    for key, val in over.items():
+        setattr(arr[-1], key, val)
+    return arr
+
+
+def _create(L, arr, npairs=None, d=16, mask=0, gamma=0.5):
+    h = ctypes.c_void_p()
+    n = len(arr) if npairs is None else npairs
+    st = L.fmap_plan_create(ctypes.cast(arr, ctypes.c_void_p), n, d, mask, gamma, 0, None, None, ctypes.byref(h))
+    assert not h.value  # nothing is created on a validation error
+    return st
+
+
+def test_plan_validation(L):
+    h = ctypes.c_void_p()
+    assert L.fmap_plan_create(NULL, 2, 16, 0, 0.5, 0, None, None, ctypes.byref(h)) == 1
+    assert L.fmap_plan_create(ctypes.cast(_pairs(), ctypes.c_void_p), 2, 16, 0, 0.5, 0, None, None, NULL) == 1
+    assert _create(L, _pairs(), npairs=0) == 2
+    assert _create(L, _pairs(), d=0) == 2
+    assert _create(L, _pairs(), mask=4) == 3
+    assert _create(L, _pairs(), mask=1, gamma=-1.0) == 3
+    assert _create(L, _pairs(phi_y=None)) == 1
+    assert _create(L, _pairs(info=None)) == 1
+    assert _create(L, _pairs(k=0)) == 2
+    assert _create(L, _pairs(n_x=0)) == 2
+    assert _create(L, _pairs(k=L.fmap_max_k() + 1)) == 6
+    # backward slots: all pairs or none, and dF with dC
+    assert _create(L, _pairs(dC=0x1000, dF_x=0x1000, dF_y=0x1000)) == 1
+    arr = _pairs()
+    for e in arr:
+        e.dC, e.dF_x = 0x1000, 0x1000
+    assert _create(L, arr) == 1
+    assert L.fmap_plan_forward(NULL, None) == 1
+    assert L.fmap_plan_backward(NULL, None) == 1
+    assert L.fmap_plan_tuning(NULL, NULL, NULL, NULL, NULL) == 1
+    assert L.fmap_plan_destroy(NULL) == 1

@@ -1,0 +1,149 @@
+"""GPU parity of the uneven-batch plan (pairs with different n and k) against the FP64 oracle.
+
+Every pair's C, info, A, B and, after the backward replay, dF_x and dF_y are
+compared with the oracle run on that pair alone: relative Frobenius error
+<= 1e-5 (float32 arrays), info bit-exact.  Graph replays are repeated with
+inputs rewritten in place and unrelated eager work in between; every replay is
+checked.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_10377_amd import synth
+from tests.conftest import rel_fro
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def F(dev):
+    from paper_2604_10377_amd import fmap
+    return fmap
+
+
+def _device_pairs(pairs, dev):
+    import torch
+    out = []
+    for p in pairs:
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+        out.append(dict(phi_x=t(p.phi_x), phi_y=t(p.phi_y), mass_x=t(p.mass_x), mass_y=t(p.mass_y),
+                        feat_x=t(p.feat_x), feat_y=t(p.feat_y), evals_x=t(p.evals_x), evals_y=t(p.evals_y),
+                        lam=t(np.asarray([p.lam]))))
+    return out
+
+
+def _oracle(p, mask, gamma, feat_x=None, feat_y=None):
+    fx = p.feat_x if feat_x is None else feat_x
+    fy = p.feat_y if feat_y is None else feat_y
+    A, B, D, C, info = oracle.forward_pair(p.phi_x, p.mass_x, fx, p.phi_y, p.mass_y, fy, p.evals_x, p.evals_y,
+                                           p.lam, mask, gamma)
+    dA, dB, _ = oracle.solve_backward(A, B, C, D, p.lam, p.dC)
+    return dict(A=A, B=B, C=C, info=info, dFx=oracle.project_backward(p.phi_x, p.mass_x, dA),
+                dFy=oracle.project_backward(p.phi_y, p.mass_y, dB))
+
+
+def _check(plan, pairs, refs, with_bwd=True, with_AB=False):
+    for i, (p, r) in enumerate(zip(pairs, refs)):
+        tag = f"pair {i} (n_x={p.n_x}, n_y={p.n_y}, k={p.k})"
+        assert rel_fro(plan.C[i].cpu().numpy(), r["C"]) <= TOL, tag
+        assert np.array_equal(plan.info[i].cpu().numpy(), r["info"]), tag
+        if with_AB:
+            assert rel_fro(plan.A[i].cpu().numpy(), r["A"]) <= TOL, tag
+            assert rel_fro(plan.B[i].cpu().numpy(), r["B"]) <= TOL, tag
+        if with_bwd:
+            assert rel_fro(plan.dF_x[i].cpu().numpy(), r["dFx"]) <= TOL, tag
+            assert rel_fro(plan.dF_y[i].cpu().numpy(), r["dFy"]) <= TOL, tag
+
+
+# k values cover both row-solve kernels (<= 64 in registers, > 64 tiled); n is ragged;
+# d = 200 leaves a partial 256-column block
+RAGGED = dict(pairs=7, d=200, n_lo=300, n_hi=3100, ks=(17, 30, 64, 80))
+
+
+@pytest.mark.parametrize("mask,recompute", [(synth.MASK_LAPLACIAN, False), (synth.MASK_RESOLVENT, True)])
+def test_plan_ragged_forward_backward(F, dev, mask, recompute):
+    import torch
+    pairs = synth.workload_ragged(**RAGGED)
+    assert len({p.k for p in pairs}) >= 3
+    print("plan ragged:", [(p.n_x, p.n_y, p.k) for p in pairs], "mask", mask, "recompute", recompute, flush=True)
+    dpairs = _device_pairs(pairs, dev)
+    plan = F.FmapPlan(dpairs, mask, 0.5, backward=True, recompute=recompute, want_AB=True)
+    for i, p in enumerate(pairs):
+        plan.dC[i].copy_(torch.from_numpy(p.dC))
+    plan.forward()
+    plan.backward()
+    torch.cuda.synchronize()
+    _check(plan, pairs, [_oracle(p, mask, 0.5) for p in pairs], with_AB=True)
+    plan.close()
+
+
+def test_plan_replays_follow_inputs(F, dev):
+    """Three replays; between them the features are rewritten in place and eager work runs."""
+    import torch
+    pairs = synth.workload_ragged(pairs=4, d=128, n_lo=500, n_hi=2000, ks=(30, 50))
+    dpairs = _device_pairs(pairs, dev)
+    plan = F.FmapPlan(dpairs, synth.MASK_LAPLACIAN, 0.5, backward=True)
+    for i, p in enumerate(pairs):
+        plan.dC[i].copy_(torch.from_numpy(p.dC))
+    rng = np.random.default_rng(5)
+    for rep in range(3):
+        print("replay", rep, flush=True)
+        fx = [(p.feat_x * (1.0 + 0.5 * rep) + 0.1 * rng.standard_normal(p.feat_x.shape)).astype(np.float32)
+              for p in pairs]
+        fy = [(p.feat_y + 0.1 * rng.standard_normal(p.feat_y.shape)).astype(np.float32) for p in pairs]
+        for i in range(len(pairs)):
+            dpairs[i]["feat_x"].copy_(torch.from_numpy(fx[i]))
+            dpairs[i]["feat_y"].copy_(torch.from_numpy(fy[i]))
+        x = torch.randn(512, 512, device=dev)
+        (x @ x).sum().item()  # unrelated eager work and a synchronisation between replays
+        plan.forward()
+        plan.backward()
+        torch.cuda.synchronize()
+        _check(plan, pairs, [_oracle(p, synth.MASK_LAPLACIAN, 0.5, fx[i], fy[i]) for i, p in enumerate(pairs)])
+    plan.close()
+
+
+def test_plan_tuning_cache_round_trip(F, dev, tmp_path):
+    """A second plan on the same workload takes the tuned parameters from the cache and gives identical C."""
+    import torch
+    pairs = synth.workload_ragged(pairs=3, d=64, n_lo=200, n_hi=900, ks=(20, 40))
+    dpairs = _device_pairs(pairs, dev)
+    cache = tmp_path / "tune.txt"
+    p1 = F.FmapPlan(dpairs, synth.MASK_RESOLVENT, 0.5, backward=False, tune_cache=cache)
+    t1 = p1.tuning()
+    assert not t1["from_cache"]
+    assert t1["chunk"] in (512, 1024, 2048) and t1["systems_per_wg"] in (2, 4, 8) and t1["grid"] >= 1
+    assert cache.read_text().count("\n") == 1
+    p2 = F.FmapPlan(dpairs, synth.MASK_RESOLVENT, 0.5, backward=False, tune_cache=cache)
+    t2 = p2.tuning()
+    assert t2["from_cache"] and {k: t2[k] for k in ("chunk", "grid", "systems_per_wg")} == \
+        {k: t1[k] for k in ("chunk", "grid", "systems_per_wg")}
+    p1.forward()
+    p2.forward()
+    torch.cuda.synchronize()
+    for i, p in enumerate(pairs):
+        assert torch.equal(p1.C[i], p2.C[i])
+        assert rel_fro(p1.C[i].cpu().numpy(), _oracle(p, synth.MASK_RESOLVENT, 0.5)["C"]) <= TOL
+    with pytest.raises(F.FmapError):
+        p1.backward()  # created without backward slots
+    p1.close()
+    p2.close()
+
+
+def test_plan_single_pair_matches_batched_entry_points(F, dev):
+    """A one-pair plan gives the same C as fmap_project + fmap_solve (same kernels, same order)."""
+    import torch
+    b = synth.make_batch("t", 91, 1, 2345, 50, 256, mask=synth.MASK_RESOLVENT)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    dp = [dict(phi_x=t(b.phi[0]), phi_y=t(b.phi[1]), mass_x=t(b.mass[0]), mass_y=t(b.mass[1]), feat_x=t(b.feat[0]),
+               feat_y=t(b.feat[1]), evals_x=t(b.evals[0]), evals_y=t(b.evals[1]), lam=t(b.lam[:1]))]
+    plan = F.FmapPlan(dp, synth.MASK_RESOLVENT, 0.5, backward=False)
+    plan.forward()
+    AB = F.fmap_project(t(b.phi), t(b.mass), t(b.feat))
+    C, _, info, _ = F.fmap_solve(AB[:1], AB[1:], t(b.evals[:1]), t(b.evals[1:]), t(b.lam), synth.MASK_RESOLVENT, 0.5)
+    torch.cuda.synchronize()
+    assert rel_fro(plan.C[0].cpu().numpy(), C[0].cpu().numpy()) <= 1e-6
+    assert torch.equal(plan.info[0], info[0])
+    plan.close()
