@@ -37,8 +37,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="headline", choices=["headline", "plain", "mixed", "large"])
-    ap.add_argument("--bwd", default="stored", choices=["stored", "recompute"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "plain", "mixed", "large", "ragged"])
+    ap.add_argument("--bwd", default=None, choices=["stored", "recompute"],
+                    help="backward mode (default: recompute for the large workload, stored otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
@@ -58,19 +59,25 @@ def make_workload(name: str):
     return synth.workload_large()
 
 
+# solve options per workload: the mixed-precision workload runs one float64-residual
+# refinement step and forms A A^T in float64 when its condition estimate exceeds 1e6
+SOLVE_OPTS = {"mixed": dict(refine_steps=1, cond_fp64_threshold=1e6)}
+
+
 class Step:
     """Preallocated buffers and the four library calls of one forward + backward pass."""
 
-    def __init__(self, F, dev, b, inputs, bwd="stored"):
+    def __init__(self, F, dev, b, inputs, bwd="stored", refine_steps=0, cond_fp64_threshold=0.0):
         import torch
         self.F, self.b, self.bwd = F, b, bwd
+        self.refine, self.cond_thr = refine_steps, cond_fp64_threshold
         P, n, k, d = b.pairs, b.n, b.k, b.d
         self.phi, self.mass, self.feat, self.ex, self.ey, self.lam, self.dC = inputs
         self.AB = torch.empty((2 * P, k, d), dtype=torch.float32, device=dev)
         self.C = torch.empty((P, k, k), dtype=torch.float32, device=dev)
         self.info = torch.empty((P, k), dtype=torch.int32, device=dev)
         self.fac = (torch.empty((P, F.fmap_factor_floats(k, k)), dtype=torch.float32, device=dev)
-                    if bwd == "stored" else None)
+                    if bwd == "stored" or refine_steps > 0 else None)
         self.dAB = torch.empty_like(self.AB)
         self.dF = torch.empty((2 * P, n, d), dtype=torch.float32, device=dev)
         dt = F.FMAP_BF16 if self.phi.dtype == torch.bfloat16 else F.FMAP_F32
@@ -84,12 +91,14 @@ class Step:
     def solve(self):
         P, b = self.b.pairs, self.b
         self.F.fmap_solve(self.AB[:P], self.AB[P:], self.ex, self.ey, self.lam, b.mask, b.gamma, C=self.C,
-                          factors=self.fac, info=self.info, workspace=self.wss, store_factors=self.bwd == "stored")
+                          factors=self.fac, info=self.info, workspace=self.wss, store_factors=self.fac is not None,
+                          refine_steps=self.refine, cond_fp64_threshold=self.cond_thr)
 
     def solve_backward(self):
         P, b = self.b.pairs, self.b
         self.F.fmap_solve_backward(self.dC, self.AB[:P], self.AB[P:], self.C, self.ex, self.ey, self.lam, b.mask,
-                                   b.gamma, self.fac, dA=self.dAB[:P], dB=self.dAB[P:], workspace=self.wss)
+                                   b.gamma, self.fac if self.bwd == "stored" else None, dA=self.dAB[:P],
+                                   dB=self.dAB[P:], workspace=self.wss)
 
     def project_backward(self):
         self.F.fmap_project_backward(self.phi, self.mass, self.dAB, dF=self.dF)
@@ -170,6 +179,126 @@ def accuracy(b, step, pairs=(0, 1)):
     return {k: float(f"{v:.3e}") for k, v in worst.items()} | {"pairs": list(pairs)}
 
 
+def ragged_costs(pairs, d):
+    """Algorithmic (flops, bytes) of one forward + backward pass over an uneven batch, summed per pair."""
+    from types import SimpleNamespace
+    tot = {"fwd": [0.0, 0.0], "bwd": [0.0, 0.0]}
+    for p in pairs:
+        for n in (p.n_x, p.n_y):
+            c = phase_costs(SimpleNamespace(pairs=1, n=n, k=p.k, d=d), False)
+            # phase_costs counts a pair (two shapes of n vertices): halve the projection terms per shape
+            tot["fwd"][0] += c["project"][0] / 2
+            tot["fwd"][1] += c["project"][1] / 2
+            tot["bwd"][0] += c["project_backward"][0] / 2
+            tot["bwd"][1] += c["project_backward"][1] / 2
+        c = phase_costs(SimpleNamespace(pairs=1, n=0, k=p.k, d=d), False)
+        tot["fwd"][0] += c["solve"][0]
+        tot["fwd"][1] += c["solve"][1]
+        tot["bwd"][0] += c["solve_backward"][0]
+        tot["bwd"][1] += c["solve_backward"][1]
+    return tot
+
+
+def bench_ragged(args, F, dev):
+    """Uneven batch through one plan: captured forward + backward graphs, replayed K times."""
+    import tempfile
+
+    import torch
+    from paper_2604_10377_amd import synth
+    pairs = synth.workload_ragged()
+    d = 256
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    dp = [dict(phi_x=t(p.phi_x), phi_y=t(p.phi_y), mass_x=t(p.mass_x), mass_y=t(p.mass_y), feat_x=t(p.feat_x),
+               feat_y=t(p.feat_y), evals_x=t(p.evals_x), evals_y=t(p.evals_y), lam=t(np.asarray([p.lam])))
+          for p in pairs]
+    bwd = args.bwd or "stored"
+    cache = os.path.join(tempfile.gettempdir(), "fmap_tune_cache.txt")
+    t0 = time.perf_counter()
+    plan = F.FmapPlan(dp, synth.MASK_LAPLACIAN, 0.5, backward=True, recompute=(bwd == "recompute"),
+                      tune_cache=cache)
+    create_s = time.perf_counter() - t0
+    for i, p in enumerate(pairs):
+        plan.dC[i].copy_(torch.from_numpy(p.dC))
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        plan.forward()
+        plan.backward()
+
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            step()
+        torch.cuda.synchronize()
+        print(f"profiled {args.profile_steps} plan steps of the ragged workload", flush=True)
+        return
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    # forward and backward graphs timed separately
+    pass_ms = {}
+    for name, fn in (("fwd", plan.forward), ("bwd", plan.backward)):
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(20):
+            fn()
+        z.record(stream)
+        torch.cuda.synchronize()
+        pass_ms[name] = a.elapsed_time(z) / 20
+    costs = ragged_costs(pairs, d)
+    dom = max(pass_ms, key=pass_ms.get)
+    roof = roofline_entry(costs[dom][0], costs[dom][1], pass_ms[dom] * 1e-3, FP32_PEAK_TFLOPS)
+    roof["kernel"] = f"plan {dom} pass (graph: persistent projection items + grouped solves)"
+    roof["traffic"] = None
+    roof["pass_us"] = {k: round(v * 1e3, 2) for k, v in pass_ms.items()}
+    t_roof = sum(max(f / (FP32_PEAK_TFLOPS * 1e12), by / (HBM_PEAK_GBS * 1e9)) for f, by in costs.values())
+    roof["step_roofline_us"] = round(t_roof * 1e6, 2)
+    roof["step_frac"] = round(t_roof * 1e3 / ms, 4)
+    # accuracy of sampled pairs
+    import oracle
+    worst = {"C": 0.0, "dF": 0.0}
+    rel = lambda x, r: float(np.linalg.norm(x - r) / np.linalg.norm(r))
+    for i in (0, len(pairs) - 1):
+        p = pairs[i]
+        A, B, D, Cr, _ = oracle.forward_pair(p.phi_x, p.mass_x, p.feat_x, p.phi_y, p.mass_y, p.feat_y, p.evals_x,
+                                             p.evals_y, p.lam, synth.MASK_LAPLACIAN, 0.5)
+        dA, dB, _ = oracle.solve_backward(A, B, Cr, D, p.lam, p.dC)
+        worst["C"] = max(worst["C"], rel(plan.C[i].cpu().numpy(), Cr))
+        worst["dF"] = max(worst["dF"], rel(plan.dF_x[i].cpu().numpy(), oracle.project_backward(p.phi_x, p.mass_x, dA)),
+                          rel(plan.dF_y[i].cpu().numpy(), oracle.project_backward(p.phi_y, p.mass_y, dB)))
+    ks = sorted({p.k for p in pairs})
+    out = {
+        "metric": "functional map solves/sec (fwd+bwd), uneven batch",
+        "value": round(len(pairs) / (ms * 1e-3), 1),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ragged-k30..120-d256", "pairs": len(pairs), "n_range": [min(min(p.n_x, p.n_y)
+                   for p in pairs), max(max(p.n_x, p.n_y) for p in pairs)], "k_values": ks,
+                   "k_counts": {str(k): sum(p.k == k for p in pairs) for k in ks}, "d": d, "mask": "laplacian",
+                   "backward": bwd, "graph": True},
+        "tuning": plan.tuning() | {"create_s": round(create_s, 2)},
+        "roofline": roof,
+        "cpu_baseline": None,
+        "accuracy_vs_oracle": {k: float(f"{v:.3e}") for k, v in worst.items()} | {"pairs": [0, len(pairs) - 1]},
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -181,6 +310,10 @@ def main():
     from paper_2604_10377_amd import fmap as F
 
     dev = torch.device("cuda:0")
+    if args.workload == "ragged":
+        return bench_ragged(args, F, dev)
+    if args.bwd is None:
+        args.bwd = "recompute" if args.workload == "large" else "stored"
     b = make_workload(args.workload)
     bf16 = b.phi_bf16 is not None
     P = b.pairs
@@ -197,7 +330,7 @@ def main():
 
     base = upload()
     sets = [base] + [tuple(x.clone() for x in base) for _ in range(2)]
-    steps = [Step(F, dev, b, s, args.bwd) for s in sets]
+    steps = [Step(F, dev, b, s, args.bwd, **SOLVE_OPTS.get(args.workload, {})) for s in sets]
     stream = torch.cuda.current_stream(dev)
 
     if args.profile_steps:
@@ -286,7 +419,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": b.name, "pairs": P, "n": b.n, "k": b.k, "d": b.d,
                    "mask": "resolvent" if b.mask == 1 else "laplacian", "lambda": float(b.lam[0]),
-                   "backward": args.bwd, "graph": not args.no_graph},
+                   "backward": args.bwd, "graph": not args.no_graph, **SOLVE_OPTS.get(args.workload, {})},
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy_vs_oracle": acc,

@@ -32,6 +32,17 @@ struct RedItem {                  // A = sum of `nchunks` partial k x d slots
 hipError_t launch_fwd_items(const FwdItem *items, int nitems, int kmax, int grid, hipStream_t st);
 hipError_t launch_bwd_items(const BwdItem *items, int nitems, int kmax, int grid, hipStream_t st);
 hipError_t launch_reduce_items(const RedItem *items, int nitems, hipStream_t st);
+// Fixed-order sum of split-K partials [batch][nsplit][k][d] into A [batch][k][d].
+hipError_t launch_reduce(const float *part, int nsplit, int64_t batch, int64_t k, int64_t d, float *A, hipStream_t st);
+// bf16 forward projection on the bf16 matrix cores (k % 8 == 0, k <= 256, d % 8 == 0, n % 4 == 0).
+bool bf16_fwd_shape_ok(int64_t n, int64_t k, int64_t d);
+int bf16_fwd_nsplit(int64_t batch, int64_t n, int64_t k, int64_t d);
+// bf16-basis backward projection on the bf16 matrix cores (k % 8 == 0, k <= 256).
+bool bf16_bwd_shape_ok(int64_t n, int64_t k, int64_t d);
+hipError_t launch_project_backward_bf16(const uint16_t *phi, const float *mass, const float *dA, int64_t batch,
+                                        int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st);
+hipError_t launch_project_bf16(const uint16_t *phi, const float *mass, const uint16_t *feat, int64_t batch, int64_t n,
+                               int64_t k, int64_t d, float *A, void *ws, hipStream_t st);
 int device_cus();
 int rowsolve_waves();
 void set_rowsolve_waves(int w);

@@ -19,6 +19,7 @@
 // the k range, so a lane walks along its own basis row.
 #include "fmap_device.h"
 #include "fmap_launch.h"
+#include "fmap_lds.h"
 
 namespace fmap {
 
@@ -179,35 +180,6 @@ constexpr int P_TILE = 8 * 256;               // basis tile: up to 8 KB (k <= 64
 constexpr int M_TILE = 256;                   // masses: one 1 KB load window
 constexpr int STAGE_FLOATS = F_TILE + P_TILE + M_TILE;
 constexpr size_t FWD_LDS_BYTES = (size_t)FNST * STAGE_FLOATS * sizeof(float);
-
-typedef __attribute__((address_space(3))) void lds_void_t;
-typedef __attribute__((address_space(1))) void glb_void_t;
-
-__device__ __forceinline__ void dma16(const float *g, float *lds_base)
-{
-    __builtin_amdgcn_global_load_lds((glb_void_t *)g, (lds_void_t *)lds_base, 16, 0, 0);
-}
-
-// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding).
-template <int N>
-__device__ __forceinline__ void wait_vmcnt()
-{
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
-
-// Workgroup barrier for the LDS pipelines: waits for this wave's LDS operations
-// only (lgkmcnt), not for the direct global->LDS loads still in flight for later
-// stages (a __syncthreads() would drain vmcnt and serialise the pipeline).  The
-// loads of the stage about to be read were retired by an explicit vmcnt wait
-// before the barrier.
-__device__ __forceinline__ void lds_barrier()
-{
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt unconstrained
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
 
 __device__ __forceinline__ f32x4 mfma16x16x4(float a, float b, f32x4 c)
 {
@@ -697,6 +669,10 @@ size_t project_workspace_bytes(int64_t batch, int64_t n, int64_t k, int64_t d, i
         const int64_t nl = lds_fwd_nsplit(batch, n, d);
         if (nl > ns) ns = nl;
     }
+    if (dtype == 1 && bf16_fwd_shape_ok(n, k, d)) {
+        const int64_t nb = bf16_fwd_nsplit(batch, n, k, d);
+        if (nb > ns) ns = nb;
+    }
     if (ns <= 1) return 0;
     return (size_t)batch * ns * k * d * sizeof(float);
 }
@@ -786,6 +762,12 @@ hipError_t launch_bwd_items(const BwdItem *items, int nitems, int kmax, int grid
 {
     const int kc = kmax < BWD_KC ? kmax : BWD_KC;
     const size_t lds = (size_t)((kc + 1) & ~1) * bwd_stride(8) * sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)proj_bwd_items_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(BWD_KC * bwd_stride(8) * sizeof(float)));
+        attr_set = true;
+    }
     hipLaunchKernelGGL((proj_bwd_items_kernel<8>), dim3(grid), dim3(256), lds, st, items, nitems);
     return hipGetLastError();
 }
@@ -797,7 +779,7 @@ hipError_t launch_reduce_items(const RedItem *items, int nitems, hipStream_t st)
     return hipGetLastError();
 }
 
-static hipError_t launch_reduce(const float *part, int nsplit, int64_t batch, int64_t k, int64_t d, float *A,
+hipError_t launch_reduce(const float *part, int nsplit, int64_t batch, int64_t k, int64_t d, float *A,
                                 hipStream_t st)
 {
     const int64_t total = batch * k * d;
@@ -819,6 +801,8 @@ hipError_t launch_project(const void *phi, const float *mass, const void *feat, 
         if (e != hipSuccess || ns <= 1) return e;
         return launch_reduce((const float *)ws, ns, batch, k, d, A, st);
     }
+    if (dtype == 1 && bf16_fwd_shape_ok(n, k, d) && aligned16(phi) && aligned16(mass) && aligned16(feat))
+        return launch_project_bf16((const uint16_t *)phi, mass, (const uint16_t *)feat, batch, n, k, d, A, ws, st);
     ProjPlan p = plan_project(batch, n, k, d, dtype);
     float *out = p.nsplit > 1 ? (float *)ws : A;
     if (dtype == 0) launch_fwd_dt<float>(phi, mass, feat, batch, n, k, d, p, out, st);
@@ -841,6 +825,12 @@ static void launch_bwd_t(const void *phi, const float *mass, const float *dA, in
     const unsigned grid = (unsigned)(batch * rgroups * dblocks);
     const int kc = (int)(k < BWD_KC ? k : BWD_KC);
     const size_t lds = (size_t)((kc + 1) & ~1) * bwd_stride(NT) * sizeof(float);
+    static bool attr_set = false;  // up to 64 x 288 floats (72 KB) for NT = 8
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)proj_bwd_kernel<T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(BWD_KC * bwd_stride(NT) * sizeof(float)));
+        attr_set = true;
+    }
     hipLaunchKernelGGL((proj_bwd_kernel<T, NT>), dim3(grid), dim3(256), lds, st, (const T *)phi, mass, dA, (int)n,
                        (int)k, (int)d, rgroups, RB, dblocks, dF);
 }
@@ -877,6 +867,8 @@ hipError_t launch_project_backward(const void *phi, const float *mass, int32_t d
                            (const float *)phi, mass, dA, (int)n, (int)k, (int)d, ns, dblocks, dF);
         return hipGetLastError();
     }
+    if (dtype == 1 && bf16_bwd_shape_ok(n, k, d) && aligned16(phi))
+        return launch_project_backward_bf16((const uint16_t *)phi, mass, dA, batch, n, k, d, dF, st);
     if (dtype == 0) {
         if (d <= 128) launch_bwd_t<float, 4>(phi, mass, dA, batch, n, k, d, dF, st);
         else launch_bwd_t<float, 8>(phi, mass, dA, batch, n, k, d, dF, st);

@@ -78,6 +78,40 @@ def test_project_forward_bf16_inputs(F, dev, b, n, k, d):
         assert rel_fro(A[s], oracle.project(phi[s], mass[s], feat[s])) <= TOL
 
 
+# bf16 matrix-core forward (k % 8 == 0, k <= 256, d % 8 == 0, n % 4 == 0): every row-slab
+# width (k <= 64, <= 128, <= 256), partial row and column blocks, a 4-vertex tail stage,
+# the smallest k, and the mixed-precision workload's shape.  basis x mass is split into
+# two bf16 parts (product error <= 2^-16 relative), so the float32 bar applies.
+BF16_MFMA_CASES = [(2, 4000, 200, 384), (1, 2048, 128, 256), (2, 1024, 64, 520), (1, 3000, 8, 16),
+                   (3, 4004, 96, 136), (2, 132, 256, 64), (1, 50000, 200, 384)]
+
+
+@pytest.mark.parametrize("b,n,k,d", BF16_MFMA_CASES)
+def test_project_forward_bf16_matrix_cores(F, dev, b, n, k, d):
+    import torch
+    print("bf16 mfma projection", b, n, k, d, flush=True)
+    phi, mass, feat = _shapes(6, b, n, k, d, bf16=True)
+    A = N(F.fmap_project(T(phi, dev, torch.bfloat16), T(mass, dev), T(feat, dev, torch.bfloat16)))
+    for s in range(b):
+        err = rel_fro(A[s], oracle.project(phi[s], mass[s], feat[s]))
+        assert err <= TOL, (s, err)
+
+
+# bf16 matrix-core backward (k % 8 == 0, k <= 256): dA is split into two bf16 parts, so the
+# float32 bar applies; partial column blocks, ragged n, smallest and largest k.
+@pytest.mark.parametrize("b,n,k,d", [(2, 4000, 200, 384), (1, 1000, 8, 20), (3, 777, 256, 130), (2, 3001, 64, 128),
+                                     (1, 50000, 200, 384)])
+def test_project_backward_bf16_matrix_cores(F, dev, b, n, k, d):
+    import torch
+    print("bf16 mfma projection backward", b, n, k, d, flush=True)
+    phi, mass, _ = _shapes(7, b, n, k, d, bf16=True)
+    dA = np.random.default_rng(8).standard_normal((b, k, d)).astype(np.float32)
+    dF = N(F.fmap_project_backward(T(phi, dev, torch.bfloat16), T(mass, dev), T(dA, dev)))
+    for s in range(b):
+        err = rel_fro(dF[s], oracle.project_backward(phi[s], mass[s], dA[s]))
+        assert err <= TOL, (s, err)
+
+
 @pytest.mark.parametrize("b,n,k,d", [(1, 1, 1, 1), (2, 37, 5, 7), (3, 1234, 30, 128), (2, 5000, 50, 256),
                                      (1, 4097, 64, 300), (2, 999, 65, 33)] + LDS_CASES)
 def test_project_backward(F, dev, b, n, k, d):
@@ -402,3 +436,38 @@ def test_fp64_normal_matrix_branch(F, dev):
     assert (N(cond) > 1e6).all()
     for p in range(P):
         assert rel_fro(N(C)[p], ref[p]["C"]) <= 1e-5, (p, rel_fro(N(C)[p], ref[p]["C"]))
+
+
+BF16_PATH_TOL = 2e-3  # stated bar of the bf16-projection path (C and dF against the oracle on the same bf16 inputs)
+
+
+def test_mixed_precision_pipeline(F, dev):
+    """bf16 projections, float32 row solves with one float64-residual refinement step and the float64
+    normal matrix above a condition estimate of 1e6, backward through the bf16 projection: per-pair C and
+    dF against the oracle fed the same bf16-rounded inputs (reduced n; k, d and the spectra of the
+    mixed-precision workload)."""
+    import torch
+    b = synth.workload_mixed(pairs=2, n=6000)
+    P = b.pairs
+    phi = torch.from_numpy(b.phi_bf16.view(np.int16)).to(dev).view(torch.bfloat16)
+    feat = torch.from_numpy(b.feat_bf16.view(np.int16)).to(dev).view(torch.bfloat16)
+    mass = T(b.mass, dev)
+    AB = F.fmap_project(phi, mass, feat)
+    C, fac, info, cond = F.fmap_solve(AB[:P], AB[P:], T(b.evals_x, dev), T(b.evals_y, dev), T(b.lam, dev), b.mask,
+                                      b.gamma, refine_steps=1, cond_fp64_threshold=1e6, want_cond=True)
+    dAB = torch.empty_like(AB)
+    F.fmap_solve_backward(T(b.dC, dev), AB[:P], AB[P:], C, T(b.evals_x, dev), T(b.evals_y, dev), T(b.lam, dev),
+                          b.mask, b.gamma, fac, dA=dAB[:P], dB=dAB[P:])
+    dF = N(F.fmap_project_backward(phi, mass, dAB))
+    C, info = N(C), N(info)
+    ph, fe = b.phi_consumed(), b.feat_consumed()
+    for p in range(P):
+        A, B, D, Cr, ir = oracle.forward_pair(ph[p], b.mass[p], fe[p], ph[P + p], b.mass[P + p], fe[P + p],
+                                              b.evals_x[p], b.evals_y[p], float(b.lam[p]), b.mask, b.gamma)
+        dA, dB, _ = oracle.solve_backward(A, B, Cr, D, float(b.lam[p]), b.dC[p])
+        errs = (rel_fro(C[p], Cr), rel_fro(dF[p], oracle.project_backward(ph[p], b.mass[p], dA)),
+                rel_fro(dF[P + p], oracle.project_backward(ph[P + p], b.mass[P + p], dB)))
+        print("mixed pair", p, "errors C, dF_x, dF_y:", errs, "cond", float(N(cond)[p]), flush=True)
+        assert np.array_equal(info[p], ir)
+        assert max(errs) <= BF16_PATH_TOL
+        assert errs[0] <= 1e-4  # the refinement step leaves the projection's float32 sums as the error
