@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many eager steps (for rocprofv3), no JSON")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run 3 plain device copies of 256 MiB (calibrates the HBM byte counters), no JSON")
     return ap.parse_args()
 
 
@@ -138,6 +140,35 @@ def roofline_entry(flops, nbytes, seconds, mfma_peak_tflops):
     ach = nbytes / seconds / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4)}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "headline_hbm_traffic.txt")
+KERNEL_OF_PHASE = {"project": "proj_fwd_lds_kernel<3, 2>", "project_backward": "proj_bwd_lds_kernel"}
+
+
+def measured_traffic(phase: str, workload: str):
+    """HBM bytes per launch of the phase's main kernel from the committed byte-counter summary.
+
+    None unless the summary covers this workload and the kernel source still has the hash the
+    counters were taken with (a changed kernel voids them)."""
+    import hashlib
+    if workload != "headline" or phase not in KERNEL_OF_PHASE or not os.path.exists(TRAFFIC_FILE):
+        return None
+    lines = open(TRAFFIC_FILE).read().splitlines()
+    src = [ln for ln in lines if ln.startswith("source: ")]
+    if not src:
+        return None
+    rel, _, want = src[0][len("source: "):].split()[:3]
+    have = hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()[:16]
+    if have != want:
+        return None
+    name = KERNEL_OF_PHASE[phase]
+    for ln in lines:
+        if ln.startswith(name + " ") or ln.startswith("void " + name + " "):
+            read_mb, write_mb = (float(x) for x in ln.split()[-2:])
+            return {"bytes": round((read_mb + write_mb) * 1e6), "read_MB": read_mb, "write_MB": write_mb,
+                    "kernel": name, "source_sha256": want}
+    return None
 
 
 def cpu_baseline(b, seconds: float):
@@ -310,6 +341,14 @@ def main():
     from paper_2604_10377_amd import fmap as F
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copied 3 x 256 MiB", flush=True)
+        return
     if args.workload == "ragged":
         return bench_ragged(args, F, dev)
     if args.bwd is None:
@@ -394,7 +433,10 @@ def main():
     roof = roofline_entry(costs[dom][0], costs[dom][1], phase_ms[dom] * 1e-3, pk)
     roof["kernel"] = "fmap_project (split-K partial + fixed-order reduce)" if dom == "project" else \
         "fmap_project_backward"
-    roof["traffic"] = None
+    tr = measured_traffic(dom, args.workload)
+    roof["traffic"] = None if tr is None else tr["bytes"]
+    if tr is not None:
+        roof["traffic_detail"] = tr | {"algorithmic_bytes": round(costs[dom][1])}
     roof["phase_us"] = {k: round(v * 1e3, 2) for k, v in phase_ms.items()}
     t_roof = sum(max(f / (((peak if nme == "project" else FP32_PEAK_TFLOPS)) * 1e12), by / (HBM_PEAK_GBS * 1e9))
                  for nme, (f, by) in costs.items())

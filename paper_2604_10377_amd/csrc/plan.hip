@@ -252,7 +252,14 @@ float time_ms(hipStream_t st, Fn fn, int reps = 3)
         (void)hipEventDestroy(a);
         return 1e30f;
     }
+    (void)hipGetLastError();
     fn();  // warm-up
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();  // a candidate that cannot launch is skipped, and its error cleared
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return 1e30f;
+    }
     std::vector<float> t;
     for (int r = 0; r < reps; ++r) {
         (void)hipEventRecord(a, st);
@@ -295,7 +302,7 @@ bool cache_lookup(const char *path, const std::string &sig, fmap_plan *pl)
         int c, gfm, w, rb, gbm;
         // only values the tuner itself can produce: the partial slots are sized for the smallest chunk
         if (std::sscanf(s.c_str() + bar + 1, "%d %d %d %d %d", &c, &gfm, &w, &rb, &gbm) == 5 &&
-            (c == 512 || c == 1024 || c == 2048) && gfm >= 1 && gfm <= 65535 && (w == 2 || w == 4 || w == 8) &&
+            (c == 512 || c == 1024 || c == 2048) && gfm >= 1 && gfm <= 65535 && (w == 1 || w == 2 || w == 4) &&
             (rb == 1 || rb == 2 || rb == 4) && gbm >= 1 && gbm <= 65535) {
             pl->chunk = c;
             pl->grid_fwd = gfm;
@@ -471,7 +478,7 @@ fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, 
         FMAP_TRY(launch_reduce_items(pl->d_red, pl->nred, st));
         best = 1e30f;
         int bw = 4;
-        for (int w : {2, 4, 8}) {
+        for (int w : {1, 2, 4}) {
             const float t = time_ms(st, [&]() {
                 set_rowsolve_waves(w);
                 for (Bucket &B : pl->buckets) {

@@ -309,7 +309,7 @@ void launch_cond(const float *K, int64_t P, int64_t kx, int64_t ky, float thresh
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void *)cond_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(((size_t)kMaxK * (kMaxK + 1) / 2 + 2 * kMaxK) * sizeof(float)));
+                                  (int)(((size_t)kMaxCondK * (kMaxCondK + 1) / 2 + 2 * kMaxCondK) * sizeof(float)));
         attr = true;
     }
     hipLaunchKernelGGL(cond_kernel, dim3((unsigned)P), dim3(512), lds, st, K, (int)kx, threshold, K64, R64, Kout, Rout,

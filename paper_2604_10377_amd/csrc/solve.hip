@@ -431,7 +431,7 @@ static void launch_gram(const float *A, const float *B, int64_t P, int64_t kx, i
 // autotuner overrides it for the launches it records.
 static thread_local int g_rowsolve_waves = 4;
 int rowsolve_waves() { return g_rowsolve_waves; }
-void set_rowsolve_waves(int w) { g_rowsolve_waves = (w == 1 || w == 2 || w == 4 || w == 8) ? w : 4; }
+void set_rowsolve_waves(int w) { g_rowsolve_waves = (w == 1 || w == 2 || w == 4) ? w : 4; }  // <= launch bound
 
 template <int MODE>
 static void launch_rowsolve(const float *K, const float *Lin, const float *rhs, const float *ex, const float *ey,
@@ -441,19 +441,11 @@ static void launch_rowsolve(const float *K, const float *Lin, const float *rhs, 
 {
     const int W = rowsolve_waves();
     const unsigned grid = (unsigned)(P * ((ky + W - 1) / W));
+    // dynamic LDS: W x (KM + KM(KM+1)/2) floats, at most 4 x 2144 floats (34 KB)
 #define FMAP_RS(KM)                                                                                             \
-    do {                                                                                                        \
-        static bool attr = false;                                                                               \
-        if (!attr) {                                                                                            \
-            (void)hipFuncSetAttribute((const void *)rowsolve_kernel<KM, MODE>,                                  \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,                               \
-                                      (int)(8 * (KM + KM * (KM + 1) / 2) * sizeof(float)));                     \
-            attr = true;                                                                                        \
-        }                                                                                                       \
-        hipLaunchKernelGGL((rowsolve_kernel<KM, MODE>), dim3(grid), dim3(64 * W),                                \
-                           (size_t)W * (KM + KM * (KM + 1) / 2) * sizeof(float), st, K, Lin, rhs, ex, ey, lam,   \
-                           mask_kind, gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part, addend);        \
-    } while (0)
+    hipLaunchKernelGGL((rowsolve_kernel<KM, MODE>), dim3(grid), dim3(64 * W),                                    \
+                       (size_t)W * (KM + KM * (KM + 1) / 2) * sizeof(float), st, K, Lin, rhs, ex, ey, lam, mask_kind, \
+                       gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part, addend)
     if (kx <= 8) FMAP_RS(8);
     else if (kx <= 16) FMAP_RS(16);
     else if (kx <= 24) FMAP_RS(24);

@@ -114,7 +114,7 @@ def test_plan_tuning_cache_round_trip(F, dev, tmp_path):
     p1 = F.FmapPlan(dpairs, synth.MASK_RESOLVENT, 0.5, backward=False, tune_cache=cache)
     t1 = p1.tuning()
     assert not t1["from_cache"]
-    assert t1["chunk"] in (512, 1024, 2048) and t1["systems_per_wg"] in (2, 4, 8) and t1["grid"] >= 1
+    assert t1["chunk"] in (512, 1024, 2048) and t1["systems_per_wg"] in (1, 2, 4) and t1["grid"] >= 1
     assert cache.read_text().count("\n") == 1
     p2 = F.FmapPlan(dpairs, synth.MASK_RESOLVENT, 0.5, backward=False, tune_cache=cache)
     t2 = p2.tuning()
