@@ -130,6 +130,29 @@ def phase_costs(b, bf16: bool):
             "solve_backward": (adj_flops, adj_bytes), "project_backward": (pbwd_flops, pbwd_bytes)}
 
 
+def matrix_peak(phase: str, b, bf16: bool):
+    """(TFLOP/s of useful products, note) for the matrix cores the library dispatches for this phase.
+
+    The bf16 paths run the bf16 matrix cores (2500 TFLOP/s dense) with more than one bf16 product per
+    useful product: basis x mass (forward) or dA (backward) split in two, or, for float32 operands,
+    both operands split in three with six products kept.  Shapes outside those paths use the float32
+    matrix cores (157.3 TFLOP/s)."""
+    n, k, d = b.n, b.k, b.d
+    if phase == "project":
+        if bf16 and k % 8 == 0 and 8 <= k <= 256 and d % 8 == 0 and n % 4 == 0 and n >= 128:
+            return BF16_PEAK_TFLOPS / 2, "bf16 matrix cores, 2 bf16 products per product"
+        if not bf16 and k % 2 == 0 and 4 <= k <= 64 and d % 4 == 0 and n % 4 == 0 and n >= 128:
+            return BF16_PEAK_TFLOPS / 6, "bf16 matrix cores, float32 emulated with 6 bf16 products"
+        return FP32_PEAK_TFLOPS, "float32 matrix cores"
+    if phase == "project_backward":
+        if bf16 and k % 8 == 0 and 8 <= k <= 256:
+            return BF16_PEAK_TFLOPS / 2, "bf16 matrix cores, 2 bf16 products per product"
+        if not bf16 and k % 2 == 0 and 2 <= k <= 64:
+            return BF16_PEAK_TFLOPS / 6, "bf16 matrix cores, float32 emulated with 6 bf16 products"
+        return FP32_PEAK_TFLOPS, "float32 matrix cores"
+    return FP32_PEAK_TFLOPS, "float32"
+
+
 def roofline_entry(flops, nbytes, seconds, mfma_peak_tflops):
     t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
     t_mfma = flops / (mfma_peak_tflops * 1e12)
@@ -143,7 +166,7 @@ def roofline_entry(flops, nbytes, seconds, mfma_peak_tflops):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "headline_hbm_traffic.txt")
-KERNEL_OF_PHASE = {"project": "proj_fwd_lds_kernel<3, 2>", "project_backward": "proj_bwd_lds_kernel"}
+KERNEL_OF_PHASE = {"project": "proj_fwd_x3_kernel", "project_backward": "proj_bwd_mc_kernel<float, 3, 3, 2>"}
 
 
 def measured_traffic(phase: str, workload: str):
@@ -427,19 +450,18 @@ def main():
         torch.cuda.synchronize()
         phase_ms[name] = a.elapsed_time(z) / reps
     costs = phase_costs(b, bf16)
-    peak = BF16_PEAK_TFLOPS if bf16 else FP32_PEAK_TFLOPS
+    peaks = {nme: matrix_peak(nme, b, bf16) for nme in costs}
     dom = max(("project", "project_backward"), key=lambda nme: phase_ms[nme])
-    pk = peak if dom == "project" else FP32_PEAK_TFLOPS
-    roof = roofline_entry(costs[dom][0], costs[dom][1], phase_ms[dom] * 1e-3, pk)
-    roof["kernel"] = "fmap_project (split-K partial + fixed-order reduce)" if dom == "project" else \
+    roof = roofline_entry(costs[dom][0], costs[dom][1], phase_ms[dom] * 1e-3, peaks[dom][0])
+    roof["matrix_path"] = peaks[dom][1]
+    roof["kernel"] = "fmap_project (split-K partials + fixed-order reduce)" if dom == "project" else \
         "fmap_project_backward"
     tr = measured_traffic(dom, args.workload)
     roof["traffic"] = None if tr is None else tr["bytes"]
     if tr is not None:
         roof["traffic_detail"] = tr | {"algorithmic_bytes": round(costs[dom][1])}
     roof["phase_us"] = {k: round(v * 1e3, 2) for k, v in phase_ms.items()}
-    t_roof = sum(max(f / (((peak if nme == "project" else FP32_PEAK_TFLOPS)) * 1e12), by / (HBM_PEAK_GBS * 1e9))
-                 for nme, (f, by) in costs.items())
+    t_roof = sum(max(f / (peaks[nme][0] * 1e12), by / (HBM_PEAK_GBS * 1e9)) for nme, (f, by) in costs.items())
     roof["step_roofline_us"] = round(t_roof * 1e6, 2)
     roof["step_frac"] = round(t_roof * 1e3 / ms, 4)
 

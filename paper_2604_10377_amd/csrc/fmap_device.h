@@ -41,6 +41,22 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+// Sum over the 64 lanes, returned wave-uniform.  Within each 16-lane row the DPP steps
+// (xor 1, xor 2 via quad permutes, then rotations by 4 and 8) leave the row sum in every lane;
+// the four row sums are combined with readlanes.  No LDS round trips, unlike a shuffle butterfly.
+__device__ __forceinline__ float wave_sum_uniform(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xF, 0xF, false));  // row_ror:4
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xF, 0xF, false));  // row_ror:8
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
 __device__ __forceinline__ double wave_sum_f64(double v)
 {
 #pragma unroll

@@ -41,6 +41,16 @@ int bf16_fwd_nsplit(int64_t batch, int64_t n, int64_t k, int64_t d);
 bool bf16_bwd_shape_ok(int64_t n, int64_t k, int64_t d);
 hipError_t launch_project_backward_bf16(const uint16_t *phi, const float *mass, const float *dA, int64_t batch,
                                         int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st);
+// float32 forward projection on the bf16 matrix cores, operands split into three bf16 parts
+// (k even, 4 <= k <= 64, d % 4 == 0, n % 4 == 0).
+bool f32_split_fwd_shape_ok(int64_t n, int64_t k, int64_t d);
+int f32_split_fwd_nsplit(int64_t batch, int64_t n, int64_t d);
+hipError_t launch_project_f32_split(const float *phi, const float *mass, const float *feat, int64_t batch, int64_t n,
+                                    int64_t k, int64_t d, float *A, void *ws, hipStream_t st);
+// float32 backward projection on the bf16 matrix cores, operands split into three bf16 parts (k even, k <= 64).
+bool f32_split_bwd_shape_ok(int64_t n, int64_t k, int64_t d);
+hipError_t launch_project_backward_f32_split(const float *phi, const float *mass, const float *dA, int64_t batch,
+                                             int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st);
 hipError_t launch_project_bf16(const uint16_t *phi, const float *mass, const uint16_t *feat, int64_t batch, int64_t n,
                                int64_t k, int64_t d, float *A, void *ws, hipStream_t st);
 int device_cus();
@@ -73,6 +83,10 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
                                  int64_t kx, int64_t ky, int64_t d, const float *factors, float *dA, float *dB,
                                  float *dlam, int32_t *info, void *ws, hipStream_t st);
 
+// Row solves with stored factors (reverse mode, refinement correction) by streaming triangular solves.
+void launch_trisolve_stored(const float *Lin, const float *rhs, const float *ex, const float *ey, const float *lam,
+                            int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, int *info,
+                            const float *Cfwd, float *dlam_part, const float *addend, hipStream_t st);
 void launch_rowsolve_tiled(int mode, const float *K, const float *Lin, const float *rhs, const float *ex,
                            const float *ey, const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx,
                            int64_t ky, float *out, float *Lout, int *info, const float *Cfwd, float *dlam_part,

@@ -673,6 +673,10 @@ size_t project_workspace_bytes(int64_t batch, int64_t n, int64_t k, int64_t d, i
         const int64_t nb = bf16_fwd_nsplit(batch, n, k, d);
         if (nb > ns) ns = nb;
     }
+    if (dtype == 0 && f32_split_fwd_shape_ok(n, k, d)) {
+        const int64_t nx = f32_split_fwd_nsplit(batch, n, d);
+        if (nx > ns) ns = nx;
+    }
     if (ns <= 1) return 0;
     return (size_t)batch * ns * k * d * sizeof(float);
 }
@@ -793,6 +797,8 @@ hipError_t launch_reduce(const float *part, int nsplit, int64_t batch, int64_t k
 hipError_t launch_project(const void *phi, const float *mass, const void *feat, int32_t dtype, int64_t batch, int64_t n,
                           int64_t k, int64_t d, float *A, void *ws, hipStream_t st)
 {
+    if (dtype == 0 && f32_split_fwd_shape_ok(n, k, d) && aligned16(phi) && aligned16(mass) && aligned16(feat))
+        return launch_project_f32_split((const float *)phi, mass, (const float *)feat, batch, n, k, d, A, ws, st);
     if (lds_fwd_shape_ok(n, k, d, dtype) && aligned16(phi) && aligned16(mass) && aligned16(feat)) {
         const int ns = lds_fwd_nsplit(batch, n, d);
         float *out = ns > 1 ? (float *)ws : A;
@@ -854,6 +860,8 @@ static int lds_bwd_nsplit(int64_t batch, int64_t n, int64_t d)
 hipError_t launch_project_backward(const void *phi, const float *mass, int32_t dtype, const float *dA, int64_t batch,
                                    int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st)
 {
+    if (dtype == 0 && f32_split_bwd_shape_ok(n, k, d) && ((uintptr_t)phi & 7) == 0 && ((uintptr_t)dF & 15) == 0)
+        return launch_project_backward_f32_split((const float *)phi, mass, dA, batch, n, k, d, dF, st);
     if (lds_bwd_shape_ok(n, k, d, dtype) && aligned16(phi) && aligned16(mass)) {
         static bool attr_set = false;
         if (!attr_set) {
@@ -867,7 +875,7 @@ hipError_t launch_project_backward(const void *phi, const float *mass, int32_t d
                            (const float *)phi, mass, dA, (int)n, (int)k, (int)d, ns, dblocks, dF);
         return hipGetLastError();
     }
-    if (dtype == 1 && bf16_bwd_shape_ok(n, k, d) && aligned16(phi))
+    if (dtype == 1 && bf16_bwd_shape_ok(n, k, d) && aligned16(phi) && aligned16(dF))
         return launch_project_backward_bf16((const uint16_t *)phi, mass, dA, batch, n, k, d, dF, st);
     if (dtype == 0) {
         if (d <= 128) launch_bwd_t<float, 4>(phi, mass, dA, batch, n, k, d, dF, st);

@@ -1,0 +1,802 @@
+// Projections (Eq. 1 and its adjoint) on the bf16 matrix cores.
+//
+// Forward projection A = Phi^T diag(M) F with bfloat16 basis and
+// features on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16, float32
+// accumulation).
+//
+// The contraction runs over vertices, and Phi [n][k] and F [n][d] are both
+// vertex-major, so the 8 K slots (vertices) that one lane feeds a matrix-core
+// step are a row apart in memory.  The operands are transposed in registers: a
+// lane reads 4 consecutive entries of each of 8 vertex rows from LDS
+// (ds_read_b64) and repacks them into 4 operands of 8 vertices each.
+//   * basis side: each pair of vertices is packed by the float32 -> bf16
+//     conversion of basis x mass (v_cvt_pk_bf16_f32 takes the two vertices), so
+//     the transpose rides on the conversion;
+//   * feature side: one v_perm_b32 per operand register.
+// basis x mass is not a bf16 number: it is split into hi = bf16(p) and
+// lo = bf16(p - hi) and both parts are multiplied (two matrix-core steps), so
+// the products keep ~16 significant bits (relative error <= 2^-16) and the
+// only roundings of substance are the bf16 inputs themselves.  A single bf16
+// rounding of the product would add a relative error near 2^-8/sqrt(3) to A
+// for incoherent data, as large as the whole error budget of this path.
+//
+// Workgroup = 4 waves = KW row slabs of 64 basis rows x (4/KW) column slabs of
+// 128 feature columns; KW = 4 covers k <= 256 with one 128-column block of d,
+// so the feature matrix is read exactly once and the basis once per column
+// block.  The column blocks of one vertex chunk are given consecutive
+// workgroup ids on the same XCD, so their basis reads meet in that XCD's L2.
+// Stages of 32 vertices (one matrix-core K step) arrive by direct global->LDS
+// loads in a ring of 3, two stages ahead; every wave issues a fixed number of
+// loads per stage (addresses clamped, never masked) so the vmcnt waits are
+// exact.  The vertex sum is split into chunks whose float32 partials are added
+// in a fixed order by the reduction kernel of the float32 path.
+#include "fmap_device.h"
+#include "fmap_launch.h"
+#include "fmap_lds.h"
+
+namespace fmap {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int BS = 32;    // vertices per stage = K of one bf16 matrix-core step
+constexpr int BNST = 3;   // stages in the ring
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
+{
+    const bf16x2_t v = __builtin_convertvector((f32x2_t){lo, hi}, bf16x2_t);  // round to nearest even
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ f32x4 mfma16x16x32bf16(u32x4_t a, u32x4_t b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                     c, 0, 0, 0);
+}
+
+// bf16 number t (0..3) of a 64-bit group, as float32
+__device__ __forceinline__ float bf16_at(uint2 x, int t)
+{
+    const uint32_t w = (t < 2) ? x.x : x.y;
+    return __uint_as_float((t & 1) ? (w & 0xffff0000u) : (w << 16));
+}
+
+template <int KW>
+struct Bf16Fwd {
+    static constexpr int DWG = 128 * (4 / KW);   // feature columns per workgroup
+    static constexpr int NF = DWG / 16;          // 1 KB feature windows per stage (32 rows x DWG bf16)
+    static constexpr int FLB = KW == 1 ? 10 : 7; // loads per wave per stage (>= (NP + NF + 1) / 4)
+    static constexpr int NPMAX = KW * 4;         // basis windows for k <= 64 KW
+};
+
+template <int KW>
+__global__ __launch_bounds__(256, KW == 4 ? 2 : 1) void proj_fwd_bf16_kernel(const uint16_t *__restrict__ phi,
+                                                            const float *__restrict__ mass,
+                                                            const uint16_t *__restrict__ feat, int n, int k, int d,
+                                                            int nsplit, int dblocks, int ntiles,
+                                                            float *__restrict__ out)
+{
+    using C = Bf16Fwd<KW>;
+    extern __shared__ __align__(16) float smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ks = wave % KW, dsl = wave / KW;
+    const int m16 = lane & 15, g4 = lane >> 4;
+
+    // workgroup id -> (tile j, column block db); XCD = id % 8, and the column blocks
+    // of one tile take ids q*8 + x for consecutive q on the same XCD x
+    const int bid = blockIdx.x;
+    const int xs = bid & 7, q = bid >> 3;
+    const int db = q % dblocks;
+    const int j = (q / dblocks) * 8 + xs;
+    if (j >= ntiles) return;  // whole workgroup, before any barrier
+    const int split = j % nsplit, s = j / nsplit;
+    const int dbase = db * C::DWG;
+
+    const int nst_all = (n + BS - 1) / BS;
+    const int st0 = (int)(((long)split * nst_all) / nsplit), st1 = (int)(((long)(split + 1) * nst_all) / nsplit);
+    const int vbeg = st0 * BS, vend = min(n, st1 * BS);
+    const int nst = st1 - st0;
+
+    const uint16_t *P = phi + (size_t)s * n * k;
+    const uint16_t *F = feat + (size_t)s * n * d;
+    const float *Mv = mass + (size_t)s * n;
+
+    const int np = (k + 15) / 16;  // 1 KB basis windows per stage (32 rows x k bf16)
+    const int stage_bytes = (np + C::NF + 1) * 1024;
+    char *ring = reinterpret_cast<char *>(smem);
+    for (int e = tid * 16; e < BNST * stage_bytes; e += 256 * 16)
+        *reinterpret_cast<f32x4 *>(ring + e) = f32x4{0, 0, 0, 0};
+    __syncthreads();
+
+    constexpr int LPR = C::DWG / 8;  // lanes per feature row in a window (16 B = 8 bf16 each)
+    auto issue = [&](int t) {
+        char *S = ring + (t % BNST) * stage_bytes;
+        const int v = vbeg + t * BS;
+        const int rows = min(BS, vend - v);
+        const int pvalid = rows * k;  // basis entries of the stage that exist (multiple of 8)
+#pragma unroll
+        for (int qq = 0; qq < C::FLB; ++qq) {
+            const int item = qq * 4 + wave;
+            if (item < C::NF) {
+                const int r = min(item * (64 / LPR) + lane / LPR, rows - 1);
+                const int col = min(dbase + (lane % LPR) * 8, d - 8);
+                dma16(reinterpret_cast<const float *>(F + (size_t)(v + r) * d + col),
+                      reinterpret_cast<float *>(S + np * 1024 + item * 1024));
+            } else if (item < C::NF + np) {
+                const int w = item - C::NF;
+                const int off = min(w * 512 + 8 * lane, pvalid - 8);
+                dma16(reinterpret_cast<const float *>(P + (size_t)v * k + off),
+                      reinterpret_cast<float *>(S + w * 1024));
+            } else {
+                const int off = min(4 * lane, ((rows + 3) & ~3) - 4);
+                dma16(Mv + v + off, reinterpret_cast<float *>(S + (np + C::NF) * 1024));
+            }
+        }
+    };
+
+    f32x4 acc[4][8];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
+
+    const int r4 = min(ks * 64 + 4 * m16, k - 4);  // rows beyond k read (and later drop) the last 4
+
+    for (int t = 0; t < BNST - 1 && t < nst; ++t) issue(t);
+    for (int t = 0; t < nst; ++t) {
+        if (t + BNST - 1 < nst) issue(t + BNST - 1);
+        if (t + 2 < nst) wait_vmcnt<2 * C::FLB>();
+        else if (t + 1 < nst) wait_vmcnt<C::FLB>();
+        else wait_vmcnt<0>();
+        lds_barrier();
+        const char *S = ring + (t % BNST) * stage_bytes;
+        const uint16_t *Ps = reinterpret_cast<const uint16_t *>(S);
+        const uint16_t *Fs = reinterpret_cast<const uint16_t *>(S + np * 1024);
+        const float *Ms = reinterpret_cast<const float *>(S + (np + C::NF) * 1024);
+        const int vrem = vend - (vbeg + t * BS);  // vertices of this stage that exist
+
+        // masses of this lane's 8 vertices (zero past the end)
+        const f32x4 m0 = *reinterpret_cast<const f32x4 *>(Ms + 8 * g4);
+        const f32x4 m1 = *reinterpret_cast<const f32x4 *>(Ms + 8 * g4 + 4);
+        float mv[8] = {m0[0], m0[1], m0[2], m0[3], m1[0], m1[1], m1[2], m1[3]};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mv[i] = (8 * g4 + i < vrem) ? mv[i] : 0.f;
+
+        // feature operands: tile h*4+tt holds columns dsl*128 + h*64 + 4*m16 + tt of vertices 8*g4..+7
+        u32x4_t B[8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int cb = dsl * 128 + h * 64 + 4 * m16;
+            uint2 y[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) y[i] = *reinterpret_cast<const uint2 *>(Fs + (8 * g4 + i) * C::DWG + cb);
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const uint32_t lo = (tt < 2) ? y[2 * jj].x : y[2 * jj].y;
+                    const uint32_t hi = (tt < 2) ? y[2 * jj + 1].x : y[2 * jj + 1].y;
+                    B[h * 4 + tt][jj] = __builtin_amdgcn_perm(hi, lo, (tt & 1) ? 0x07060302u : 0x05040100u);
+                }
+        }
+        // basis operands: rows r4..r4+3 x vertices 8*g4..8*g4+7, scaled by mass, as hi + lo
+        uint2 x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = *reinterpret_cast<const uint2 *>(Ps + (8 * g4 + i) * k + r4);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            u32x4_t Ah, Al;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const float p0 = bf16_at(x[2 * jj], a) * mv[2 * jj], p1 = bf16_at(x[2 * jj + 1], a) * mv[2 * jj + 1];
+                const uint32_t hi = pack_bf16(p0, p1);
+                Ah[jj] = hi;
+                Al[jj] = pack_bf16(p0 - __uint_as_float(hi << 16), p1 - __uint_as_float(hi & 0xffff0000u));
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) acc[a][b] = mfma16x16x32bf16(Ah, B[b], acc[a][b]);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) acc[a][b] = mfma16x16x32bf16(Al, B[b], acc[a][b]);
+        }
+        lds_barrier();  // the slot is refilled by the next iteration's issue
+    }
+
+    // D layout: lane (m16, g4), register r -> matrix-core row 4*g4 + r, column m16.
+    // Row R of tile a is basis row ks*64 + 4R + a; column N of tile (h, tt) is
+    // feature column dbase + dsl*128 + h*64 + 4N + tt.
+    float *O = out + (size_t)j * k * d;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = ks * 64 + 4 * (4 * g4 + r) + a;
+            if (row >= k) continue;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                    const int col = dbase + dsl * 128 + h * 64 + 4 * m16 + tt;
+                    if (col < d) O[(size_t)row * d + col] = acc[a][h * 4 + tt][r];
+                }
+        }
+}
+
+static int bf16_kw(int64_t k) { return k <= 64 ? 1 : (k <= 128 ? 2 : 4); }
+
+bool bf16_fwd_shape_ok(int64_t n, int64_t k, int64_t d)
+{
+    return k >= 8 && k <= 256 && k % 8 == 0 && d >= 8 && d % 8 == 0 && n % 4 == 0 && n >= 4 * BS;
+}
+
+int bf16_fwd_nsplit(int64_t batch, int64_t n, int64_t k, int64_t d)
+{
+    const int kw = bf16_kw(k);
+    const int64_t dblocks = (d + 128 * (4 / kw) - 1) / (128 * (4 / kw));
+    const int64_t stages = (n + BS - 1) / BS;
+    const int per_cu = kw == 1 ? 1 : 2;  // workgroups per CU that fit the LDS ring
+    int64_t ns = (per_cu * device_cus()) / (batch * dblocks);
+    if (ns > stages / 4) ns = stages / 4;  // keep >= 4 stages per chunk
+    if (ns < 1) ns = 1;
+    return (int)ns;
+}
+
+template <int KW>
+static hipError_t dispatch_bf16(const uint16_t *phi, const float *mass, const uint16_t *feat, int64_t batch,
+                                int64_t n, int64_t k, int64_t d, int ns, float *out, hipStream_t st)
+{
+    using C = Bf16Fwd<KW>;
+    const int np = (int)((k + 15) / 16);
+    const size_t lds = (size_t)BNST * (np + C::NF + 1) * 1024;
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)proj_fwd_bf16_kernel<KW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)((size_t)BNST * (C::NPMAX + C::NF + 1) * 1024));
+        attr_set = true;
+    }
+    const int dblocks = (int)((d + C::DWG - 1) / C::DWG);
+    const int ntiles = (int)(batch * ns);
+    const unsigned grid = (unsigned)(8 * dblocks * ((ntiles + 7) / 8));
+    hipLaunchKernelGGL((proj_fwd_bf16_kernel<KW>), dim3(grid), dim3(256), lds, st, phi, mass, feat, (int)n, (int)k,
+                       (int)d, ns, dblocks, ntiles, out);
+    return hipGetLastError();
+}
+
+// Partials go to `ws` ([batch][nsplit][k][d]) when nsplit > 1, else straight to A.
+hipError_t launch_project_bf16(const uint16_t *phi, const float *mass, const uint16_t *feat, int64_t batch, int64_t n,
+                               int64_t k, int64_t d, float *A, void *ws, hipStream_t st)
+{
+    const int ns = bf16_fwd_nsplit(batch, n, k, d);
+    float *out = ns > 1 ? (float *)ws : A;
+    hipError_t e;
+    switch (bf16_kw(k)) {
+    case 1: e = dispatch_bf16<1>(phi, mass, feat, batch, n, k, d, ns, out, st); break;
+    case 2: e = dispatch_bf16<2>(phi, mass, feat, batch, n, k, d, ns, out, st); break;
+    default: e = dispatch_bf16<4>(phi, mass, feat, batch, n, k, d, ns, out, st); break;
+    }
+    if (e != hipSuccess || ns <= 1) return e;
+    return launch_reduce(out, ns, batch, k, d, A, st);
+}
+
+// ---------------------------------------------------------------------------
+// Backward projection dF = diag(M) Phi dA on the bf16 matrix cores, for a bf16
+// basis (an exact operand) or a float32 basis.
+//
+// The float32 matrix rate of this GPU is 1/16 of its bf16 rate, so float32
+// products are emulated: x = h + m + l with h, m, l bf16 (each the rounding of
+// what is left), and the six products whose part indices sum to at most 2
+// (hh, hm, mh, hl, lh, mm) are accumulated in float32.  The dropped terms are
+// below 2^-24 relative, the float32 level; the six bf16 steps cost 6/16 of the
+// matrix time of the float32 step.  With a bf16 basis, dA alone is split
+// (hi + lo: 2^-16 relative).
+//
+// The contraction runs over k, contiguous in a basis row, so a lane's 8 K
+// slots are one row segment of its vertex: one 16-byte load (bf16) or two
+// (float32), no transpose.  dA^T is staged once per workgroup in LDS as its bf16
+// parts in [column][k] layout, so each operand is one ds_read_b128.  The roles
+// are chosen so that a lane ends up holding 4 consecutive columns of one vertex:
+// the results leave as 16-byte stores, with the mass applied in float32.
+//
+// Workgroup = 8 waves, one 128-column block of d; a wave owns 32 vertices (2
+// tiles of 16) x 128 columns (8 tiles).  Workgroups walk contiguous ranges of
+// 256-vertex tiles (the staging is amortised over them), with the next tile's
+// basis rows loaded during the current tile.  The column blocks of one vertex
+// range take consecutive ids of one residue class mod 8 (one XCD), so the
+// basis rows they share come from HBM once and from that XCD's L2 afterwards.
+// ---------------------------------------------------------------------------
+constexpr int BB_COLS = 128;   // columns per workgroup
+constexpr int BB_VT = 256;     // vertices per workgroup tile (8 waves x 32)
+
+__host__ __device__ constexpr int bwdmc_stride(int ks) { return ks * 64 + 16; }  // bytes per LDS row (k padded)
+__host__ __device__ constexpr size_t bwdmc_lds(int pd, int ks) { return (size_t)pd * BB_COLS * bwdmc_stride(ks); }
+
+// x (two values per dword) as NP bf16 parts, each the rounding of what the previous parts left
+template <int NP>
+__device__ __forceinline__ void split_pack(float x0, float x1, uint32_t *out)
+{
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const uint32_t h = pack_bf16(x0, x1);
+        out[p] = h;
+        if (p + 1 < NP) {
+            x0 -= __uint_as_float(h << 16);
+            x1 -= __uint_as_float(h & 0xffff0000u);
+        }
+    }
+}
+
+template <typename T> struct RowSeg;  // 8 consecutive basis entries of one vertex row
+template <> struct RowSeg<uint16_t> { u32x4_t v; };
+template <> struct RowSeg<float> { f32x4 lo, hi; };
+
+// Loads are unconditional, from addresses clamped into the row; slots past k are zeroed only when
+// the operand is formed.  (A branch around each load, or a select right after it, would make the
+// compiler wait for the loads at that point and so defeat the prefetch of the next tile.)
+// bf16 rows: k % 8 == 0, so a lane's 8 slots starting at kk all exist or none do.
+__device__ __forceinline__ RowSeg<uint16_t> load_seg_bf16(const uint16_t *row, int kk, int k)
+{
+    RowSeg<uint16_t> r;
+    r.v = *reinterpret_cast<const u32x4_t *>(row + min(kk, k - 8));
+    return r;
+}
+// float32 rows need only be 8-byte aligned (k even): four pairs
+__device__ __forceinline__ RowSeg<float> load_seg_f32(const float *row, int kk, int k)
+{
+    RowSeg<float> r;
+    float2 q[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = *reinterpret_cast<const float2 *>(row + min(kk + 2 * i, k - 2));
+    r.lo = f32x4{q[0].x, q[0].y, q[1].x, q[1].y};
+    r.hi = f32x4{q[2].x, q[2].y, q[3].x, q[3].y};
+    return r;
+}
+
+// the basis operand parts of one row segment starting at slot kk (slots >= k are zero)
+template <int PP>
+__device__ __forceinline__ void seg_parts(const RowSeg<uint16_t> &r, int kk, int k, u32x4_t *B)
+{
+    B[0] = (kk < k) ? r.v : u32x4_t{0, 0, 0, 0};
+}
+template <int PP>
+__device__ __forceinline__ void seg_parts(const RowSeg<float> &r, int kk, int k, u32x4_t *B)
+{
+    const float x[8] = {r.lo[0], r.lo[1], r.lo[2], r.lo[3], r.hi[0], r.hi[1], r.hi[2], r.hi[3]};
+    uint32_t w[4][PP];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool ok = kk + 2 * i < k;  // k even: both values of the pair exist or neither
+        split_pack<PP>(ok ? x[2 * i] : 0.f, ok ? x[2 * i + 1] : 0.f, w[i]);
+    }
+#pragma unroll
+    for (int p = 0; p < PP; ++p) B[p] = u32x4_t{w[0][p], w[1][p], w[2][p], w[3][p]};
+}
+
+template <typename T, int PP, int PD, int KS>
+__global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict__ phi, const float *__restrict__ mass,
+                                                           const float *__restrict__ dA, int n, int k, int d,
+                                                           int vsplit, int dblocks, int ntasks,
+                                                           float *__restrict__ dF)
+{
+    constexpr int STRIDE = bwdmc_stride(KS);
+    extern __shared__ __align__(16) float smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m16 = lane & 15, g4 = lane >> 4;
+    const int bid = blockIdx.x;
+    const int xs = bid & 7, q = bid >> 3;
+    const int db = q % dblocks;
+    const int j = (q / dblocks) * 8 + xs;
+    if (j >= ntasks) return;  // whole workgroup, before any barrier
+    const int vs = j % vsplit, s = j / vsplit;
+    const int dbase = db * BB_COLS;
+
+    const T *P = phi + (size_t)s * n * k;
+    const float *Mv = mass + (size_t)s * n;
+    const float *G = dA + (size_t)s * k * d;
+    float *O = dF + (size_t)s * n * d;
+
+    // dA^T parts for columns [dbase, dbase + 128), rows < 32 KS (zero past k and d)
+    char *parts = reinterpret_cast<char *>(smem);
+    for (int e = tid; e < KS * 32 * BB_COLS; e += 512) {
+        const int jj = e / BB_COLS, c = e - jj * BB_COLS;
+        const float v = (jj < k && dbase + c < d) ? G[(size_t)jj * d + dbase + c] : 0.f;
+        uint32_t w[PD];
+        split_pack<PD>(v, 0.f, w);
+#pragma unroll
+        for (int p = 0; p < PD; ++p)
+            *reinterpret_cast<uint16_t *>(parts + (size_t)p * BB_COLS * STRIDE + c * STRIDE + 2 * jj) = (uint16_t)w[p];
+    }
+    __syncthreads();
+
+    const int ntile = (n + BB_VT - 1) / BB_VT;
+    const int t0 = (int)(((long)vs * ntile) / vsplit), t1 = (int)(((long)(vs + 1) * ntile) / vsplit);
+    const bool vec = (d & 3) == 0;
+
+    // basis row segments of a tile: [k step][vertex tile of 16]; rows past n are clamped (never stored)
+    RowSeg<T> buf0[KS][2], buf1[KS][2];
+    float m0[2], m1[2];
+    auto load_tile = [&](int vt, RowSeg<T> (&r)[KS][2], float (&mv)[2]) {
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int v = min(vt * BB_VT + wave * 32 + nt * 16 + m16, n - 1);
+            mv[nt] = Mv[v];
+            const T *row = P + (size_t)v * k;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if constexpr (PP == 1)
+                    r[ks][nt] = load_seg_bf16(row, ks * 32 + 8 * g4, k);
+                else
+                    r[ks][nt] = load_seg_f32(row, ks * 32 + 8 * g4, k);
+            }
+        }
+    };
+    auto compute_store = [&](int vt, const RowSeg<T> (&cur)[KS][2], const float (&mv)[2]) {
+        f32x4 acc[8][2];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            u32x4_t B[2][PP];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) seg_parts<PP>(cur[ks][nt], ks * 32 + 8 * g4, k, B[nt]);
+#pragma unroll
+            for (int mp = 0; mp < 8; mp += 2) {
+                u32x4_t A[2][PD];
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int p = 0; p < PD; ++p)
+                        A[h][p] = *reinterpret_cast<const u32x4_t *>(parts + (size_t)p * BB_COLS * STRIDE +
+                                                                    ((mp + h) * 16 + m16) * STRIDE +
+                                                                    2 * (ks * 32 + 8 * g4));
+                // four independent accumulators between dependent matrix-core steps
+#pragma unroll
+                for (int i = 0; i < PP; ++i)
+#pragma unroll
+                    for (int jp = 0; jp < PD; ++jp)
+                        if (i + jp <= 2) {
+#pragma unroll
+                            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                                for (int nt = 0; nt < 2; ++nt)
+                                    acc[mp + h][nt] = mfma16x16x32bf16(A[h][jp], B[nt][i], acc[mp + h][nt]);
+                        }
+                // keep the scheduler from hoisting every tile's LDS operands at once (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // D layout: register r of lane (m16, g4) is column 4*g4 + r of the column tile, vertex m16
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int v = vt * BB_VT + wave * 32 + nt * 16 + m16;
+            if (v >= n) continue;
+            float *row = O + (size_t)v * d;
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt) {
+                const int col = dbase + mt * 16 + 4 * g4;
+                const f32x4 val = acc[mt][nt] * mv[nt];
+                if (vec) {
+                    if (col < d) *reinterpret_cast<f32x4 *>(row + col) = val;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (col + r < d) row[col + r] = val[r];
+                }
+            }
+        }
+    };
+    // two tiles per trip: the buffers swap roles without register copies.  The prefetches are
+    // unconditional (the last tile is loaded again at the end of the range): a conditional load
+    // would make the compiler wait for all outstanding loads where the paths join.
+    if (t0 >= t1) return;
+    load_tile(t0, buf0, m0);
+    for (int vt = t0; vt < t1; vt += 2) {
+        load_tile(min(vt + 1, t1 - 1), buf1, m1);
+        compute_store(vt, buf0, m0);
+        if (vt + 1 >= t1) break;
+        load_tile(min(vt + 2, t1 - 1), buf0, m0);
+        compute_store(vt + 1, buf1, m1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward projection with float32 basis and features on the bf16 matrix cores:
+// both operands split into three bf16 parts, six products kept (float32 level,
+// as in the backward above), for k <= 64.
+//
+// Workgroup = 4 waves; a wave owns all 64 (padded) basis rows x 64 feature
+// columns, so a workgroup covers a 256-column block.  Stages of 32 vertices
+// (one K step) arrive by direct global->LDS loads in a ring of 2 (80 KB, two
+// workgroups per CU), the next stage in flight during the current one.  Per
+// stage a lane reads 4 basis rows (two ds_read_b64: rows are only 8-byte
+// aligned for k = 50) and 4 feature columns (one ds_read_b128) of each of its
+// 8 vertices; the three-way split packs two vertices per register, which is
+// the transpose.  Basis row 4R + a of the slab is matrix-core row R of tile a,
+// feature column 4N + t of the wave's 64 is column N of tile t.
+// ---------------------------------------------------------------------------
+constexpr int XS = 32;      // vertices per stage
+constexpr int XNST = 2;     // stages in the ring
+constexpr int XFL = 11;     // loads per wave per stage: 8 feature rows, 2 basis windows, 1 mass window
+
+__host__ __device__ constexpr int x3_np(int k) { return (k + 7) / 8; }  // 1 KB basis windows (32 rows x k floats)
+__host__ __device__ constexpr int x3_stage_bytes(int k) { return (32 + x3_np(k)) * 1024 + 256; }
+
+__global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__restrict__ phi,
+                                                           const float *__restrict__ mass,
+                                                           const float *__restrict__ feat, int n, int k, int d,
+                                                           int nsplit, int dblocks, int ntiles,
+                                                           float *__restrict__ out)
+{
+    extern __shared__ __align__(16) float smem[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int m16 = lane & 15, g4 = lane >> 4;
+    const int bid = blockIdx.x;
+    const int xs = bid & 7, q = bid >> 3;
+    const int db = q % dblocks;
+    const int j = (q / dblocks) * 8 + xs;
+    if (j >= ntiles) return;  // whole workgroup, before any barrier
+    const int split = j % nsplit, s = j / nsplit;
+    const int dbase = db * 256;
+
+    const int nst_all = (n + XS - 1) / XS;
+    const int st0 = (int)(((long)split * nst_all) / nsplit), st1 = (int)(((long)(split + 1) * nst_all) / nsplit);
+    const int vbeg = st0 * XS, vend = min(n, st1 * XS);
+    const int nst = st1 - st0;
+
+    const float *P = phi + (size_t)s * n * k;
+    const float *F = feat + (size_t)s * n * d;
+    const float *Mv = mass + (size_t)s * n;
+
+    const int np = x3_np(k);
+    const int stage_bytes = x3_stage_bytes(k);  // [feature rows 32 KB][basis np KB][mass 256 B]
+    char *ring = reinterpret_cast<char *>(smem);
+    for (int e = tid * 16; e < XNST * stage_bytes; e += 256 * 16)
+        *reinterpret_cast<f32x4 *>(ring + e) = f32x4{0, 0, 0, 0};
+    __syncthreads();
+
+    // Load roles, the same count (XFL = 11) for every wave and stage: feature rows 8*wave .. +7, basis
+    // windows wave and wave + 4 (clamped to the last window), one mass window.  Full stages use
+    // per-lane offsets fixed at entry plus a uniform base; only the last stage of a chunk, which
+    // may hold fewer rows, clamps row indices.
+    const int fcol = min(dbase + 4 * lane, d - 4);  // feature column of this lane (d % 4 == 0)
+    const int pw0 = min(wave, np - 1), pw1 = min(wave + 4, np - 1);
+    const int poff0 = min(pw0 * 256 + 4 * lane, XS * k - 4), poff1 = min(pw1 * 256 + 4 * lane, XS * k - 4);
+    auto issue = [&](int t) {
+        char *S = ring + (t % XNST) * stage_bytes;
+        const int v = vbeg + t * XS;
+        const int rows = min(XS, vend - v);  // a multiple of 4 (n % 4 == 0)
+        if (rows == XS) {
+            const float *Fv = F + (size_t)(v + 8 * wave) * d + fcol;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) dma16(Fv + (size_t)i * d, reinterpret_cast<float *>(S + (8 * wave + i) * 1024));
+            const float *Pv = P + (size_t)v * k;
+            dma16(Pv + poff0, reinterpret_cast<float *>(S + (32 + pw0) * 1024));
+            dma16(Pv + poff1, reinterpret_cast<float *>(S + (32 + pw1) * 1024));
+            __builtin_amdgcn_global_load_lds((glb_void_t *)(Mv + v + (lane & 31)), (lds_void_t *)(S + (32 + np) * 1024),
+                                             4, 0, 0);
+        } else {
+            const int pvalid = rows * k;  // a multiple of 4
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int r = min(8 * wave + i, rows - 1);
+                dma16(F + (size_t)(v + r) * d + fcol, reinterpret_cast<float *>(S + (8 * wave + i) * 1024));
+            }
+            const float *Pv = P + (size_t)v * k;
+            dma16(Pv + min(poff0, pvalid - 4), reinterpret_cast<float *>(S + (32 + pw0) * 1024));
+            dma16(Pv + min(poff1, pvalid - 4), reinterpret_cast<float *>(S + (32 + pw1) * 1024));
+            __builtin_amdgcn_global_load_lds((glb_void_t *)(Mv + v + min(lane, rows - 1)),
+                                             (lds_void_t *)(S + (32 + np) * 1024), 4, 0, 0);
+        }
+    };
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[a][t] = f32x4{0, 0, 0, 0};
+    // rows 4*m16 .. +3 as two pairs, each clamped into the row on its own (k even): a pair past k
+    // reads the last pair and its results are dropped, while rows below k keep their own data
+    const int r01 = min(4 * m16, k - 2), r23 = min(4 * m16 + 2, k - 2);
+    const int cw = wave * 64 + 4 * m16;  // this lane's 4 feature columns within the block
+
+    if (nst > 0) issue(0);
+    for (int t = 0; t < nst; ++t) {
+        if (t + 1 < nst) {
+            issue(t + 1);
+            wait_vmcnt<XFL>();
+        } else {
+            wait_vmcnt<0>();
+        }
+        lds_barrier();
+        const char *S = ring + (t % XNST) * stage_bytes;
+        const float *Fs = reinterpret_cast<const float *>(S);
+        const float *Ps = reinterpret_cast<const float *>(S + 32 * 1024);
+        const float *Ms = reinterpret_cast<const float *>(S + (32 + np) * 1024);
+        const int vrem = vend - (vbeg + t * XS);
+
+        const f32x4 m0 = *reinterpret_cast<const f32x4 *>(Ms + 8 * g4);
+        const f32x4 m1 = *reinterpret_cast<const f32x4 *>(Ms + 8 * g4 + 4);
+        float mv[8] = {m0[0], m0[1], m0[2], m0[3], m1[0], m1[1], m1[2], m1[3]};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mv[i] = (8 * g4 + i < vrem) ? mv[i] : 0.f;
+
+        // basis x mass, rows r4..r4+3 of vertices 8*g4..+7, as three bf16 parts per tile
+        u32x4_t A[4][3];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            float x[2][4];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float *row = Ps + (8 * g4 + 2 * jj + h) * k;
+                const float2 lo = *reinterpret_cast<const float2 *>(row + r01);
+                const float2 hi = *reinterpret_cast<const float2 *>(row + r23);
+                const float m = mv[2 * jj + h];
+                x[h][0] = lo.x * m;
+                x[h][1] = lo.y * m;
+                x[h][2] = hi.x * m;
+                x[h][3] = hi.y * m;
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                uint32_t w[3];
+                split_pack<3>(x[0][a], x[1][a], w);
+#pragma unroll
+                for (int p = 0; p < 3; ++p) A[a][p][jj] = w[p];
+            }
+        }
+        // feature columns cw..cw+3 of the same vertices
+        f32x4 y[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) y[i] = *reinterpret_cast<const f32x4 *>(Fs + (8 * g4 + i) * 256 + cw);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            u32x4_t B[3];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                uint32_t w[3];
+                split_pack<3>(y[2 * jj][tt], y[2 * jj + 1][tt], w);
+#pragma unroll
+                for (int p = 0; p < 3; ++p) B[p][jj] = w[p];
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int jp = 0; jp < 3; ++jp)
+                    if (i + jp <= 2) {
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) acc[a][tt] = mfma16x16x32bf16(A[a][i], B[jp], acc[a][tt]);
+                    }
+        }
+        lds_barrier();  // the slot is refilled by the next iteration's issue
+    }
+
+    // lane (m16, g4), register r: matrix-core row 4*g4 + r -> basis row 4(4*g4 + r) + a; column m16 -> 4*m16 + tt
+    float *O = out + (size_t)j * k * d;
+    const int col = dbase + cw;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int row = 16 * g4 + 4 * r + a;
+            if (row >= k || col >= d) continue;
+            const f32x4 v = f32x4{acc[a][0][r], acc[a][1][r], acc[a][2][r], acc[a][3][r]};
+            *reinterpret_cast<f32x4 *>(O + (size_t)row * d + col) = v;  // d % 4 == 0: all 4 columns exist
+        }
+}
+
+bool f32_split_fwd_shape_ok(int64_t n, int64_t k, int64_t d)
+{
+    return k >= 4 && k <= 64 && k % 2 == 0 && d % 4 == 0 && n % 4 == 0 && n >= 4 * XS;
+}
+
+int f32_split_fwd_nsplit(int64_t batch, int64_t n, int64_t d)
+{
+    const int64_t dblocks = (d + 255) / 256;
+    const int64_t stages = (n + XS - 1) / XS;
+    int64_t ns = (2 * device_cus()) / (batch * dblocks);  // two workgroups per CU
+    if (ns > stages / 4) ns = stages / 4;                  // keep >= 4 stages per chunk
+    if (ns < 1) ns = 1;
+    return (int)ns;
+}
+
+hipError_t launch_project_f32_split(const float *phi, const float *mass, const float *feat, int64_t batch, int64_t n,
+                                    int64_t k, int64_t d, float *A, void *ws, hipStream_t st)
+{
+    const int ns = f32_split_fwd_nsplit(batch, n, d);
+    float *out = ns > 1 ? (float *)ws : A;
+    const size_t lds = (size_t)XNST * x3_stage_bytes((int)k);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)proj_fwd_x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)((size_t)XNST * x3_stage_bytes(64)));
+        attr_set = true;
+    }
+    const int dblocks = (int)((d + 255) / 256);
+    const int ntiles = (int)(batch * ns);
+    const unsigned grid = (unsigned)(8 * dblocks * ((ntiles + 7) / 8));
+    hipLaunchKernelGGL(proj_fwd_x3_kernel, dim3(grid), dim3(256), lds, st, phi, mass, feat, (int)n, (int)k, (int)d,
+                       ns, dblocks, ntiles, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || ns <= 1) return e;
+    return launch_reduce(out, ns, batch, k, d, A, st);
+}
+
+static int bwdmc_ks(int64_t k) { return (int)((k + 31) / 32); }
+
+bool bf16_bwd_shape_ok(int64_t n, int64_t k, int64_t d)
+{
+    return k >= 8 && k <= 256 && k % 8 == 0 && n >= 1 && d >= 1;
+}
+
+bool f32_split_bwd_shape_ok(int64_t n, int64_t k, int64_t d)
+{
+    return k >= 2 && k <= 64 && k % 2 == 0 && n >= 1 && d >= 1;
+}
+
+// vertex ranges per (shape, column block): the fewest that fill whole rounds of the
+// resident workgroup slots (>= 95% of the last round busy), at most one range per tile
+static int bwdmc_vsplit(int64_t batch, int64_t dblocks, int64_t ntile, int per_cu)
+{
+    const int64_t slots = (int64_t)device_cus() * per_cu, base = batch * dblocks;
+    int best = 1;
+    double best_e = 0.0;
+    for (int64_t v = 1; v <= ntile && v <= 64; ++v) {
+        const int64_t tot = base * v, rounds = (tot + slots - 1) / slots;
+        const double e = (double)tot / (double)(rounds * slots);
+        if (e >= 0.95) return (int)v;
+        if (e > best_e + 1e-9) {
+            best_e = e;
+            best = (int)v;
+        }
+    }
+    return best;
+}
+
+template <typename T, int PP, int PD, int KS>
+static hipError_t dispatch_bwdmc(const T *phi, const float *mass, const float *dA, int64_t batch, int64_t n, int64_t k,
+                                 int64_t d, float *dF, hipStream_t st)
+{
+    const size_t lds = bwdmc_lds(PD, KS);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)proj_bwd_mc_kernel<T, PP, PD, KS>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr_set = true;
+    }
+    const int dblocks = (int)((d + BB_COLS - 1) / BB_COLS);
+    const int64_t ntile = (n + BB_VT - 1) / BB_VT;
+    const int per_cu = lds <= 80 * 1024 ? 2 : 1;
+    const int vsplit = bwdmc_vsplit(batch, dblocks, ntile, per_cu);
+    const int ntasks = (int)(batch * vsplit);
+    const unsigned grid = (unsigned)(8 * dblocks * ((ntasks + 7) / 8));
+    hipLaunchKernelGGL((proj_bwd_mc_kernel<T, PP, PD, KS>), dim3(grid), dim3(512), lds, st, phi, mass, dA, (int)n,
+                       (int)k, (int)d, vsplit, dblocks, ntasks, dF);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_backward_bf16(const uint16_t *phi, const float *mass, const float *dA, int64_t batch,
+                                        int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st)
+{
+    switch (bwdmc_ks(k)) {
+    case 1: return dispatch_bwdmc<uint16_t, 1, 2, 1>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 2: return dispatch_bwdmc<uint16_t, 1, 2, 2>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 3: return dispatch_bwdmc<uint16_t, 1, 2, 3>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 4: return dispatch_bwdmc<uint16_t, 1, 2, 4>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 5: return dispatch_bwdmc<uint16_t, 1, 2, 5>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 6: return dispatch_bwdmc<uint16_t, 1, 2, 6>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 7: return dispatch_bwdmc<uint16_t, 1, 2, 7>(phi, mass, dA, batch, n, k, d, dF, st);
+    default: return dispatch_bwdmc<uint16_t, 1, 2, 8>(phi, mass, dA, batch, n, k, d, dF, st);
+    }
+}
+
+hipError_t launch_project_backward_f32_split(const float *phi, const float *mass, const float *dA, int64_t batch,
+                                             int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st)
+{
+    if (bwdmc_ks(k) == 1) return dispatch_bwdmc<float, 3, 3, 1>(phi, mass, dA, batch, n, k, d, dF, st);
+    return dispatch_bwdmc<float, 3, 3, 2>(phi, mass, dA, batch, n, k, d, dF, st);
+}
+
+}  // namespace fmap

@@ -139,28 +139,83 @@ __global__ __launch_bounds__(256) void residual64_kernel(const float *__restrict
 
 // ---------------------------------------------------------------------------
 // Condition estimate of K = A A^T per pair (one 512-thread workgroup).
+//
+// ||K||_1 is the largest row sum of |K| (K is symmetric), summed along rows so
+// that the loads are coalesced.  The Cholesky factor of K is formed in LDS
+// (packed lower, row-major), right-looking: the column is scaled, then the
+// trailing triangle is updated with its entries spread evenly over the 512
+// threads.  Hager's iteration then runs in one wave with the vectors in
+// registers (lane j holds rows j, j + 64, ...): the forward substitution goes
+// column by column (y_c final, rows below updated) and the back substitution
+// row by row (x_c final, rows above updated), so neither needs a reduction.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int pk(int r, int c) { return r * (r + 1) / 2 + c; }  // packed lower, row-major
 
-// x := K^{-1} x with the packed factor in LDS (one wave; x in LDS).
-__device__ void chol_solve_wave(const float *L, float *x, int k)
+constexpr int CNS = kMaxCondK / 64;  // register slots per lane (k <= 256)
+
+// row c's entry of a slotted vector (c wave-uniform), without runtime indexing of the register array
+__device__ __forceinline__ float slot_value(const float (&v)[CNS], int c)
+{
+    const int l = c & 63, s = c >> 6;
+    float r = readlane(v[0], l);
+#pragma unroll
+    for (int t = 1; t < CNS; ++t) {
+        const float x = readlane(v[t], l);
+        r = (s == t) ? x : r;
+    }
+    return r;
+}
+
+// v := K^{-1} v with the packed factor L and the reciprocal pivots Dinv in LDS (one wave).  Columns
+// go in groups of 8: a group's LDS reads are issued together, then its 8 dependent steps run on
+// registers only.
+constexpr int CG = 8;
+__device__ void chol_solve_regs(const float *L, const float *Dinv, float (&v)[CNS], int k)
 {
     const int lane = threadIdx.x & 63;
-    // L y = x (column oriented): y_c final at step c
-    for (int c = 0; c < k; ++c) {
-        const float yc = x[c] / L[pk(c, c)];
-        __builtin_amdgcn_wave_barrier();
-        for (int r = c + 1 + lane; r < k; r += 64) x[r] -= L[pk(r, c)] * yc;
-        if (lane == 0) x[c] = yc;
-        __builtin_amdgcn_wave_barrier();
+    for (int c0 = 0; c0 < k; c0 += CG) {  // L y = v, columns ascending
+        float lv[CG][CNS], inv[CG];
+#pragma unroll
+        for (int t = 0; t < CG; ++t) {
+            const int c = min(c0 + t, k - 1);
+            inv[t] = Dinv[c];
+#pragma unroll
+            for (int s = 0; s < CNS; ++s) {
+                const int r = lane + 64 * s;
+                lv[t][s] = (r > c && r < k) ? L[pk(r, c)] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < CG; ++t) {
+            const int c = c0 + t;
+            if (c < k) {
+                const float yc = slot_value(v, c) * inv[t];
+#pragma unroll
+                for (int s = 0; s < CNS; ++s) v[s] = (lane + 64 * s == c) ? yc : v[s] - lv[t][s] * yc;
+            }
+        }
     }
-    // L^T z = y (row oriented): z_c = (y_c - sum_{r>c} L_rc z_r) / L_cc
-    for (int c = k - 1; c >= 0; --c) {
-        float s = 0.f;
-        for (int r = c + 1 + lane; r < k; r += 64) s += L[pk(r, c)] * x[r];
-        s = wave_sum(s);
-        if (lane == 0) x[c] = (x[c] - s) / L[pk(c, c)];
-        __builtin_amdgcn_wave_barrier();
+    for (int c1 = k - 1; c1 >= 0; c1 -= CG) {  // L^T x = y, columns descending
+        float lv[CG][CNS], inv[CG];
+#pragma unroll
+        for (int t = 0; t < CG; ++t) {
+            const int c = max(c1 - t, 0);
+            inv[t] = Dinv[c];
+#pragma unroll
+            for (int s = 0; s < CNS; ++s) {
+                const int r = lane + 64 * s;
+                lv[t][s] = (r < c) ? L[pk(c, r)] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < CG; ++t) {
+            const int c = c1 - t;
+            if (c >= 0) {
+                const float xc = slot_value(v, c) * inv[t];
+#pragma unroll
+                for (int s = 0; s < CNS; ++s) v[s] = (lane + 64 * s == c) ? xc : v[s] - lv[t][s] * xc;
+            }
+        }
     }
 }
 
@@ -170,9 +225,8 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
                                                    float *__restrict__ cond_est)
 {
     extern __shared__ float sm[];
-    float *L = sm;                                   // packed lower, kx(kx+1)/2
-    float *x = L + kx * (kx + 1) / 2;                // kx
-    float *z = x + kx;                               // kx
+    float *L = sm;                     // packed lower, kx(kx+1)/2
+    float *Dinv = L + kx * (kx + 1) / 2;  // reciprocal pivots, kx
     __shared__ float s_red[8];
     __shared__ int s_fail;
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -181,23 +235,22 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
         const int r = e / kx, c = e - r * kx;
         if (c <= r) L[pk(r, c)] = Kp[e];
     }
-    // ||K||_1 = max column sum of |K|
-    float cmax = 0.f;
-    for (int c = tid; c < kx; c += 512) {
+    // ||K||_1 = max row sum of |K| (symmetric), one wave per row at a time
+    float rmax = 0.f;
+    for (int r = wave; r < kx; r += 8) {
         float s = 0.f;
-        for (int r = 0; r < kx; ++r) s += fabsf(Kp[(size_t)r * kx + c]);
-        cmax = fmaxf(cmax, s);
+        for (int c = lane; c < kx; c += 64) s += fabsf(Kp[(size_t)r * kx + c]);
+        rmax = fmaxf(rmax, wave_sum(s));
     }
-    cmax = wave_max(cmax);
-    if (lane == 0) s_red[wave] = cmax;
+    if (lane == 0) s_red[wave] = rmax;
     if (tid == 0) s_fail = 0;
     __syncthreads();
     float knorm = s_red[0];
     for (int w = 1; w < 8; ++w) knorm = fmaxf(knorm, s_red[w]);
-    // right-looking Cholesky in LDS, one column per step
+    // right-looking Cholesky in LDS
     for (int c = 0; c < kx; ++c) {
         const float piv = L[pk(c, c)];
-        if (!(piv > 0.f) || !isfinite(piv)) {
+        if (!(piv > 0.f) || !isfinite(piv)) {  // uniform: every thread reads the same pivot
             if (tid == 0) s_fail = 1;
             break;
         }
@@ -206,43 +259,58 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
         if (tid == 0) L[pk(c, c)] = lc;
         for (int r = c + 1 + tid; r < kx; r += 512) L[pk(r, c)] /= lc;
         __syncthreads();
+        // trailing triangle rows (c, kx), columns (c, r]: the m x m square walked in steps of 512 entries
         const int m = kx - c - 1;
-        for (int e = tid; e < m * (m + 1) / 2; e += 512) {
-            int rr = (int)((sqrtf(8.f * e + 1.f) - 1.f) * 0.5f);
-            while (rr * (rr + 1) / 2 > e) --rr;
-            while ((rr + 1) * (rr + 2) / 2 <= e) ++rr;
-            const int cc = e - rr * (rr + 1) / 2;
-            const int r = c + 1 + rr, q = c + 1 + cc;
-            L[pk(r, q)] -= L[pk(r, c)] * L[pk(q, c)];
+        if (m > 0) {
+            int rr = tid / m, qq = tid - rr * m;
+            const int dr = 512 / m, dq = 512 - dr * m;
+            for (; rr < m; rr += dr, qq += dq) {
+                if (qq >= m) {
+                    qq -= m;
+                    ++rr;
+                    if (rr >= m) break;
+                }
+                if (qq <= rr) {
+                    const int r = c + 1 + rr, q = c + 1 + qq;
+                    L[pk(r, q)] -= L[pk(r, c)] * L[pk(q, c)];
+                }
+            }
         }
         __syncthreads();
     }
     __syncthreads();
+    for (int c = tid; c < kx; c += 512) Dinv[c] = 1.f / L[pk(c, c)];
+    __syncthreads();
     float est = INFINITY;
     if (s_fail == 0) {
         if (wave == 0) {
-            // Hager: b = 1/n; up to 5 sweeps of x = K^{-1} b, xi = sign(x), z = K^{-1} xi
-            for (int r = lane; r < kx; r += 64) x[r] = 1.f / kx;
-            __builtin_amdgcn_wave_barrier();
+            // Hager: b = 1/n; up to 5 sweeps of x = K^{-1} b, xi = sign(x), z = K^{-1} xi, b = e_argmax|z|
+            float x[CNS], z[CNS];
+#pragma unroll
+            for (int s = 0; s < CNS; ++s) x[s] = (lane + 64 * s < kx) ? 1.f / kx : 0.f;
             float e1 = 0.f;
             for (int it = 0; it < 5; ++it) {
-                chol_solve_wave(L, x, kx);
-                float s = 0.f;
-                for (int r = lane; r < kx; r += 64) s += fabsf(x[r]);
-                s = wave_sum(s);
-                if (it > 0 && s <= e1) break;
-                e1 = s;
-                for (int r = lane; r < kx; r += 64) z[r] = x[r] >= 0.f ? 1.f : -1.f;
-                __builtin_amdgcn_wave_barrier();
-                chol_solve_wave(L, z, kx);
-                // j = argmax |z|, compare with z^T b (b is the previous probe, stored implicitly)
+                chol_solve_regs(L, Dinv, x, kx);
+                float a = 0.f;
+#pragma unroll
+                for (int s = 0; s < CNS; ++s) a += (lane + 64 * s < kx) ? fabsf(x[s]) : 0.f;
+                a = wave_sum(a);
+                if (it > 0 && a <= e1) break;
+                e1 = a;
+#pragma unroll
+                for (int s = 0; s < CNS; ++s) z[s] = (lane + 64 * s < kx) ? (x[s] >= 0.f ? 1.f : -1.f) : 0.f;
+                chol_solve_regs(L, Dinv, z, kx);
+                // j = argmax |z| (the smallest index on ties)
                 float best = -1.f;
                 int bj = 0;
-                for (int r = lane; r < kx; r += 64)
-                    if (fabsf(z[r]) > best) {
-                        best = fabsf(z[r]);
+#pragma unroll
+                for (int s = 0; s < CNS; ++s) {
+                    const int r = lane + 64 * s;
+                    if (r < kx && fabsf(z[s]) > best) {
+                        best = fabsf(z[s]);
                         bj = r;
                     }
+                }
 #pragma unroll
                 for (int off = 32; off >= 1; off >>= 1) {
                     const float ob = __shfl_xor(best, off, 64);
@@ -252,15 +320,19 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
                         bj = oj;
                     }
                 }
-                for (int r = lane; r < kx; r += 64) x[r] = (r == bj) ? 1.f : 0.f;
-                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int s = 0; s < CNS; ++s) x[s] = (lane + 64 * s == bj) ? 1.f : 0.f;
             }
             // Higham's extra probe: b_i = (-1)^i (1 + i/(n-1)); estimate 2 ||K^{-1} b||_1 / (3n)
-            for (int r = lane; r < kx; r += 64) z[r] = ((r & 1) ? -1.f : 1.f) * (1.f + (kx > 1 ? (float)r / (kx - 1) : 0.f));
-            __builtin_amdgcn_wave_barrier();
-            chol_solve_wave(L, z, kx);
+#pragma unroll
+            for (int s = 0; s < CNS; ++s) {
+                const int r = lane + 64 * s;
+                z[s] = r < kx ? ((r & 1) ? -1.f : 1.f) * (1.f + (kx > 1 ? (float)r / (kx - 1) : 0.f)) : 0.f;
+            }
+            chol_solve_regs(L, Dinv, z, kx);
             float s2 = 0.f;
-            for (int r = lane; r < kx; r += 64) s2 += fabsf(z[r]);
+#pragma unroll
+            for (int s = 0; s < CNS; ++s) s2 += (lane + 64 * s < kx) ? fabsf(z[s]) : 0.f;
             s2 = wave_sum(s2) * 2.f / (3.f * kx);
             if (lane == 0) s_red[0] = fmaxf(e1, s2) * knorm;
         }
@@ -305,11 +377,11 @@ void launch_residual64(const float *C, const double *K64, const double *R64, con
 void launch_cond(const float *K, int64_t P, int64_t kx, int64_t ky, float threshold, const double *K64,
                  const double *R64, float *Kout, float *Rout, float *cond_est, hipStream_t st)
 {
-    const size_t lds = ((size_t)kx * (kx + 1) / 2 + 2 * kx) * sizeof(float);
+    const size_t lds = ((size_t)kx * (kx + 1) / 2 + kx) * sizeof(float);
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void *)cond_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(((size_t)kMaxCondK * (kMaxCondK + 1) / 2 + 2 * kMaxCondK) * sizeof(float)));
+                                  (int)(((size_t)kMaxCondK * (kMaxCondK + 1) / 2 + kMaxCondK) * sizeof(float)));
         attr = true;
     }
     hipLaunchKernelGGL(cond_kernel, dim3((unsigned)P), dim3(512), lds, st, K, (int)kx, threshold, K64, R64, Kout, Rout,

@@ -486,8 +486,8 @@ hipError_t launch_solve(const float *A, const float *B, const float *ex, const f
             launch_rowsolve<RS_BWD_STORED>(nullptr, factors, rho, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, nullptr,
                                            nullptr, nullptr, nullptr, st, C);
         else
-            launch_rowsolve_tiled(RS_BWD_STORED, nullptr, factors, rho, ex, ey, lam, mask_kind, gamma, P, kx, ky, C,
-                                  nullptr, nullptr, nullptr, nullptr, tiles, st, C);
+            launch_trisolve_stored(factors, rho, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, nullptr, nullptr, nullptr,
+                                   C, st);
     }
     return hipGetLastError();
 }
@@ -506,8 +506,7 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
             launch_rowsolve<RS_BWD_STORED>(nullptr, factors, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, nullptr,
                                            info, C, dl, st);
         else
-            launch_rowsolve_tiled(RS_BWD_STORED, nullptr, factors, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V,
-                                  nullptr, info, C, dl, (float *)(base + L.tiles), st);
+            launch_trisolve_stored(factors, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, info, C, dl, nullptr, st);
     } else {
         launch_gram(A, B, P, kx, ky, d, false, K, nullptr, st);
         if (small)

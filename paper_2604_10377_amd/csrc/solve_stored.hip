@@ -1,0 +1,198 @@
+// Row solves with stored float32 factors for 64 < k_x <= 319: the reverse
+// mode's S_i v_i = g_i and the refinement correction S_i delta_i = rho_i
+// (Eqs. (6), (7) with the factor of Eq. (5) kept from the forward pass).
+//
+// With the factor known, a system is two triangular solves over k_x^2/2
+// stored floats, so the work is streaming the factor, once per substitution.
+// One wave per system; lane j holds rows j, j + 64, ... (NS slots).  The factor
+// is packed lower, column-major, so column c is contiguous: the forward
+// substitution L y = r goes column by column (y_c = r_c / L_cc, then the rows
+// below subtract L_qc y_c), the back substitution L^T x = y is a dot product
+// of column c with the finished x_q (q > c) and a wave reduction.  Columns
+// stream through registers in groups of 8, the next group loaded while the
+// current one is used (two buffers swapped by unrolling, unconditional loads
+// from clamped addresses, masking only where the values are used).
+#include "fmap_device.h"
+#include "fmap_launch.h"
+
+namespace fmap {
+
+namespace {
+
+constexpr int SG = 8;  // columns per prefetch group
+
+__device__ __forceinline__ int pcol(int c, int k) { return c * k - (c * (c - 1)) / 2; }
+
+// row c's value of a slotted vector (c wave-uniform): every slot is read at lane c % 64 and the
+// scalar results selected, so no register array is ever indexed by a runtime value
+template <int NS>
+__device__ __forceinline__ float row_value(const float (&v)[NS], int c)
+{
+    const int l = c & 63, s = c >> 6;
+    float r = readlane(v[0], l);
+#pragma unroll
+    for (int t = 1; t < NS; ++t) {
+        const float x = readlane(v[t], l);
+        r = (s == t) ? x : r;
+    }
+    return r;
+}
+
+}  // namespace
+
+template <int NS>
+__global__ __launch_bounds__(256) void trisolve_stored_kernel(const float *__restrict__ Lin,
+                                                             const float *__restrict__ rhs,
+                                                             const float *__restrict__ ex, const float *__restrict__ ey,
+                                                             const float *__restrict__ lam, int mask_kind, float gamma,
+                                                             int kx, int ky, int nsys, float *out,
+                                                             int *__restrict__ info, const float *__restrict__ Cfwd,
+                                                             float *__restrict__ dlam_part, const float *addend)
+{
+    const int j = threadIdx.x & 63;
+    const int sys = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (sys >= nsys) return;  // wave-uniform; no block-level barrier below
+    const int p = sys / ky, i = sys - p * ky;
+    const float *Lp = Lin + (size_t)sys * (kx * (kx + 1) / 2);
+    const int ng = (kx + SG - 1) / SG;
+
+    // validity of lambda and of the resolvent normaliser (as in the forward solve)
+    const float lamv = lam[p];
+    int fail = 0;
+    if (!(lamv >= 0.f) || !isfinite(lamv)) fail = -1;
+    MaskParams mp;
+    mp.kind = mask_kind;
+    mp.gamma = gamma;
+    mp.inv_scale = 1.f;
+    if (mask_kind == 1) {
+        float mx = -INFINITY;
+        for (int q = j; q < kx; q += 64) mx = fmaxf(mx, ex[(size_t)p * kx + q]);
+        for (int q = j; q < ky; q += 64) mx = fmaxf(mx, ey[(size_t)p * ky + q]);
+        mx = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_max(mx))));
+        if ((!(mx > 0.f) || !isfinite(mx)) && fail == 0) fail = -2;
+        mp.inv_scale = 1.f / mx;
+    }
+    fail = __builtin_amdgcn_readfirstlane(fail);
+
+    float y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int q = j + 64 * s;
+        y[s] = q < kx ? rhs[(size_t)sys * kx + q] : 0.f;
+    }
+
+    float ga[SG][NS], gb[SG][NS];
+    // group g of columns into buf: element (q, c) for the lane's rows, address clamped into column c
+    auto load_group = [&](int g, float (&buf)[SG][NS]) {
+#pragma unroll
+        for (int t = 0; t < SG; ++t) {
+            const int c = min(g * SG + t, kx - 1);
+            const float *col = Lp + pcol(c, kx) - c;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) buf[t][s] = col[min(max(j + 64 * s, c), kx - 1)];
+        }
+    };
+
+    // forward substitution, columns ascending
+    auto fwd_group = [&](int g, const float (&buf)[SG][NS]) {
+#pragma unroll
+        for (int t = 0; t < SG; ++t) {
+            const int c = g * SG + t;
+            if (c < kx && fail == 0) {
+                const float dg = row_value<NS>(buf[t], c);
+                if (!(dg > 0.f) || !isfinite(dg)) {
+                    fail = c + 1;
+                } else {
+                    const float yc = row_value<NS>(y, c) * __builtin_amdgcn_rcpf(dg);
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        const int q = j + 64 * s;
+                        y[s] = (q == c) ? yc : ((q > c && q < kx) ? y[s] - buf[t][s] * yc : y[s]);
+                    }
+                }
+            }
+        }
+    };
+    // back substitution, columns descending: x_c = (y_c - sum_{q > c} L_qc x_q) / L_cc (x overwrites y)
+    auto bwd_group = [&](int g, const float (&buf)[SG][NS]) {
+#pragma unroll
+        for (int t = SG - 1; t >= 0; --t) {
+            const int c = g * SG + t;
+            if (c < kx) {
+                float part = 0.f;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int q = j + 64 * s;
+                    part += (q > c && q < kx) ? buf[t][s] * y[s] : 0.f;
+                }
+                const float dot = wave_sum_uniform(part);
+                const float dg = row_value<NS>(buf[t], c);
+                const float xc = (row_value<NS>(y, c) - dot) * __builtin_amdgcn_rcpf(dg);
+#pragma unroll
+                for (int s = 0; s < NS; ++s) y[s] = (j + 64 * s == c) ? xc : y[s];
+            }
+        }
+    };
+
+    if (fail == 0) {
+        load_group(0, ga);
+        for (int g = 0; g < ng; g += 2) {
+            load_group(min(g + 1, ng - 1), gb);
+            fwd_group(g, ga);
+            if (g + 1 >= ng) break;
+            load_group(min(g + 2, ng - 1), ga);
+            fwd_group(g + 1, gb);
+        }
+        fail = __builtin_amdgcn_readfirstlane(fail);
+    }
+    if (fail == 0) {
+        const int g0 = ng - 1;
+        load_group(g0, ga);
+        for (int g = g0; g >= 0; g -= 2) {
+            load_group(max(g - 1, 0), gb);
+            bwd_group(g, ga);
+            if (g - 1 < 0) break;
+            load_group(max(g - 2, 0), ga);
+            bwd_group(g - 1, gb);
+        }
+    }
+
+    const float muy = ey[(size_t)p * ky + i];
+    float term = 0.f;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int q = j + 64 * s;
+        if (q < kx) {
+            const size_t o = (size_t)sys * kx + q;
+            const float v = fail == 0 ? y[s] : NAN;
+            out[o] = addend ? addend[o] + v : v;  // addend: refinement correction c += delta (in place)
+            if (dlam_part) term += v * mask_entry(muy, ex[(size_t)p * kx + q], mp) * Cfwd[o];
+        }
+    }
+    if (info && j == 0) info[sys] = fail;
+    if (dlam_part) {
+        const float sum = wave_sum(term);
+        if (j == 0) dlam_part[sys] = -sum;
+    }
+}
+
+void launch_trisolve_stored(const float *Lin, const float *rhs, const float *ex, const float *ey, const float *lam,
+                            int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, int *info,
+                            const float *Cfwd, float *dlam_part, const float *addend, hipStream_t st)
+{
+    const int nsys = (int)(P * ky);
+    const dim3 grid((unsigned)((nsys + 3) / 4)), block(256);
+#define FMAP_TS(NS)                                                                                              \
+    hipLaunchKernelGGL((trisolve_stored_kernel<NS>), grid, block, 0, st, Lin, rhs, ex, ey, lam, mask_kind, gamma, \
+                       (int)kx, (int)ky, nsys, out, info, Cfwd, dlam_part, addend)
+    switch ((kx + 63) / 64) {
+    case 1: FMAP_TS(1); break;
+    case 2: FMAP_TS(2); break;
+    case 3: FMAP_TS(3); break;
+    case 4: FMAP_TS(4); break;
+    default: FMAP_TS(5); break;
+    }
+#undef FMAP_TS
+}
+
+}  // namespace fmap

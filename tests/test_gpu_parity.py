@@ -54,10 +54,13 @@ def _shapes(seed, b, n, k, d, bf16=False):
 # remainder width of k mod 16, partial and multiple 256-column blocks
 LDS_CASES = [(2, 4004, 30, 128), (3, 2048, 17, 200), (2, 640, 52, 256), (1, 1000, 64, 512), (2, 4000, 49, 256),
              (1, 516, 16, 8), (2, 1028, 35, 260), (1, 8192, 50, 256)]
+# float32 operands split for the bf16 matrix cores (k even <= 64, n % 4 == 0, d % 4 == 0): most cases
+# above, plus the smallest k with a partial second column block and a narrow block at k = 62
+SPLIT_CASES = [(2, 1028, 4, 260), (1, 2052, 62, 36)]
 
 
 @pytest.mark.parametrize("b,n,k,d", [(1, 1, 1, 1), (2, 37, 5, 7), (3, 1234, 30, 128), (2, 5000, 50, 256),
-                                     (1, 4097, 64, 300), (2, 999, 65, 33), (1, 20011, 120, 256)] + LDS_CASES)
+                                     (1, 4097, 64, 300), (2, 999, 65, 33), (1, 20011, 120, 256)] + LDS_CASES + SPLIT_CASES)
 def test_project_forward(F, dev, b, n, k, d):
     import torch
     phi, mass, feat = _shapes(1, b, n, k, d)
@@ -113,7 +116,7 @@ def test_project_backward_bf16_matrix_cores(F, dev, b, n, k, d):
 
 
 @pytest.mark.parametrize("b,n,k,d", [(1, 1, 1, 1), (2, 37, 5, 7), (3, 1234, 30, 128), (2, 5000, 50, 256),
-                                     (1, 4097, 64, 300), (2, 999, 65, 33)] + LDS_CASES)
+                                     (1, 4097, 64, 300), (2, 999, 65, 33)] + LDS_CASES + SPLIT_CASES)
 def test_project_backward(F, dev, b, n, k, d):
     phi, mass, _ = _shapes(3, b, n, k, d)
     dA = np.random.default_rng(4).standard_normal((b, k, d)).astype(np.float32)
