@@ -108,8 +108,9 @@ class Step:
     def run(self):
         self.project()
         self.solve()
-        self.solve_backward()
-        self.project_backward()
+        if self.dC is not None:
+            self.solve_backward()
+            self.project_backward()
 
 
 def phase_costs(b, bf16: bool):
@@ -219,17 +220,22 @@ def accuracy(b, step, pairs=(0, 1)):
     import oracle
     P = b.pairs
     C = step.C.cpu().numpy()
-    dF = step.dF.cpu().numpy()
+    dF = None if b.dC is None else step.dF.cpu().numpy()
     phi, feat = b.phi_consumed(), b.feat_consumed()
     worst = {"C": 0.0, "dF": 0.0}
     rel = lambda x, r: float(np.linalg.norm(x - r) / np.linalg.norm(r))
+    pairs = tuple(p for p in pairs if p < P)
     for p in pairs:
         A, B, D, Cr, _ = oracle.forward_pair(phi[p], b.mass[p], feat[p], phi[P + p], b.mass[P + p], feat[P + p],
                                              b.evals[p], b.evals[P + p], float(b.lam[p]), b.mask, b.gamma)
-        dA, dB, _ = oracle.solve_backward(A, B, Cr, D, float(b.lam[p]), b.dC[p])
         worst["C"] = max(worst["C"], rel(C[p], Cr))
+        if b.dC is None:
+            continue  # forward-only workload
+        dA, dB, _ = oracle.solve_backward(A, B, Cr, D, float(b.lam[p]), b.dC[p])
         worst["dF"] = max(worst["dF"], rel(dF[p], oracle.project_backward(phi[p], b.mass[p], dA)),
                           rel(dF[P + p], oracle.project_backward(phi[P + p], b.mass[P + p], dB)))
+    if b.dC is None:
+        worst.pop("dF")
     return {k: float(f"{v:.3e}") for k, v in worst.items()} | {"pairs": list(pairs)}
 
 
@@ -388,10 +394,11 @@ def main():
             phi = torch.from_numpy(b.phi).to(dev)
             feat = torch.from_numpy(b.feat).to(dev)
         t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
-        return (phi, t(b.mass), feat, t(b.evals_x), t(b.evals_y), t(b.lam), t(b.dC))
+        return (phi, t(b.mass), feat, t(b.evals_x), t(b.evals_y), t(b.lam), None if b.dC is None else t(b.dC))
 
     base = upload()
-    sets = [base] + [tuple(x.clone() for x in base) for _ in range(2)]
+    sets = [base] + [tuple(None if x is None else x.clone() for x in base) for _ in range(2)]
+    fwd_only = b.dC is None  # the plain workload is a forward solve
     steps = [Step(F, dev, b, s, args.bwd, **SOLVE_OPTS.get(args.workload, {})) for s in sets]
     stream = torch.cuda.current_stream(dev)
 
@@ -434,7 +441,8 @@ def main():
     # (one graph holding `reps` back-to-back calls of the phase, rotating input sets)
     reps = 30
     phase_ms = {}
-    for name in ("project", "solve", "solve_backward", "project_backward"):
+    phases = ("project", "solve") if fwd_only else ("project", "solve", "solve_backward", "project_backward")
+    for name in phases:
         fns = [getattr(s, name) for s in steps]
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
@@ -449,9 +457,9 @@ def main():
         z.record(rs)
         torch.cuda.synchronize()
         phase_ms[name] = a.elapsed_time(z) / reps
-    costs = phase_costs(b, bf16)
+    costs = {nme: c for nme, c in phase_costs(b, bf16).items() if nme in phase_ms}
     peaks = {nme: matrix_peak(nme, b, bf16) for nme in costs}
-    dom = max(("project", "project_backward"), key=lambda nme: phase_ms[nme])
+    dom = max([nme for nme in ("project", "project_backward") if nme in phase_ms], key=lambda nme: phase_ms[nme])
     roof = roofline_entry(costs[dom][0], costs[dom][1], phase_ms[dom] * 1e-3, peaks[dom][0])
     roof["matrix_path"] = peaks[dom][1]
     roof["kernel"] = "fmap_project (split-K partials + fixed-order reduce)" if dom == "project" else \
@@ -466,10 +474,10 @@ def main():
     roof["step_frac"] = round(t_roof * 1e3 / ms, 4)
 
     acc = accuracy(b, steps[0])
-    cpu = None if args.no_cpu_baseline else cpu_baseline(b, args.cpu_seconds)
+    cpu = None if (args.no_cpu_baseline or fwd_only) else cpu_baseline(b, args.cpu_seconds)
     out = {
         "metric": "functional map solves/sec (fwd+bwd) at k=50,d=256,batch 32" if args.workload == "headline"
-        else f"functional map solves/sec (fwd+bwd), {b.name}",
+        else f"functional map solves/sec ({'fwd' if fwd_only else 'fwd+bwd'}), {b.name}",
         "value": round(P / (ms * 1e-3), 1),
         "unit": "solves/s",
         "n_gpus": 1,

@@ -413,8 +413,10 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict
     const bool vec = (d & 3) == 0;
 
     // basis row segments of a tile: [k step][vertex tile of 16]; rows past n are clamped (never stored)
-    RowSeg<T> buf0[KS][2], buf1[KS][2];
-    float m0[2], m1[2];
+    // raw row segments per buffer: 16 registers per k step (float32) or 8 (bf16)
+    constexpr int NBUF = (KS * (PP == 1 ? 8 : 16) <= 36) ? 3 : 2;
+    RowSeg<T> buf0[KS][2], buf1[KS][2], buf2[NBUF == 3 ? KS : 1][2];
+    float m0[2], m1[2], m2[2];
     auto load_tile = [&](int vt, RowSeg<T> (&r)[KS][2], float (&mv)[2]) {
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
@@ -487,17 +489,33 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict
             }
         }
     };
-    // two tiles per trip: the buffers swap roles without register copies.  The prefetches are
-    // unconditional (the last tile is loaded again at the end of the range): a conditional load
-    // would make the compiler wait for all outstanding loads where the paths join.
+    // The buffers rotate by unrolling (no register copies).  The prefetches are unconditional (the
+    // last tile is loaded again at the end of the range): a conditional load would make the
+    // compiler wait for all outstanding loads where the paths join.  With three buffers the loads
+    // of tile t+2 are issued before the stores of tile t, so they do not queue behind its writes.
     if (t0 >= t1) return;
-    load_tile(t0, buf0, m0);
-    for (int vt = t0; vt < t1; vt += 2) {
-        load_tile(min(vt + 1, t1 - 1), buf1, m1);
-        compute_store(vt, buf0, m0);
-        if (vt + 1 >= t1) break;
-        load_tile(min(vt + 2, t1 - 1), buf0, m0);
-        compute_store(vt + 1, buf1, m1);
+    if constexpr (NBUF == 3) {
+        load_tile(t0, buf0, m0);
+        load_tile(min(t0 + 1, t1 - 1), buf1, m1);
+        for (int vt = t0; vt < t1; vt += 3) {
+            load_tile(min(vt + 2, t1 - 1), buf2, m2);
+            compute_store(vt, buf0, m0);
+            if (vt + 1 >= t1) break;
+            load_tile(min(vt + 3, t1 - 1), buf0, m0);
+            compute_store(vt + 1, buf1, m1);
+            if (vt + 2 >= t1) break;
+            load_tile(min(vt + 4, t1 - 1), buf1, m1);
+            compute_store(vt + 2, buf2, m2);
+        }
+    } else {
+        load_tile(t0, buf0, m0);
+        for (int vt = t0; vt < t1; vt += 2) {
+            load_tile(min(vt + 1, t1 - 1), buf1, m1);
+            compute_store(vt, buf0, m0);
+            if (vt + 1 >= t1) break;
+            load_tile(min(vt + 2, t1 - 1), buf0, m0);
+            compute_store(vt + 1, buf1, m1);
+        }
     }
 }
 
