@@ -142,7 +142,8 @@ def matrix_peak(phase: str, b, bf16: bool):
     if phase == "project":
         if bf16 and k % 8 == 0 and 8 <= k <= 256 and d % 8 == 0 and n % 4 == 0 and n >= 128:
             return BF16_PEAK_TFLOPS / 2, "bf16 matrix cores, 2 bf16 products per product"
-        if not bf16 and k % 2 == 0 and 4 <= k <= 64 and d % 4 == 0 and n % 4 == 0 and n >= 128:
+        kok = (k % 2 == 0 and 4 <= k <= 64) or (k % 4 == 0 and 64 < k <= 319)
+        if not bf16 and kok and d % 4 == 0 and n % 4 == 0 and n >= 128:
             return BF16_PEAK_TFLOPS / 6, "bf16 matrix cores, float32 emulated with 6 bf16 products"
         return FP32_PEAK_TFLOPS, "float32 matrix cores"
     if phase == "project_backward":

@@ -42,9 +42,9 @@ bool bf16_bwd_shape_ok(int64_t n, int64_t k, int64_t d);
 hipError_t launch_project_backward_bf16(const uint16_t *phi, const float *mass, const float *dA, int64_t batch,
                                         int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st);
 // float32 forward projection on the bf16 matrix cores, operands split into three bf16 parts
-// (k even, 4 <= k <= 64, d % 4 == 0, n % 4 == 0).
+// (k even <= 64 or k % 4 == 0 up to 319, d % 4 == 0, n % 4 == 0).
 bool f32_split_fwd_shape_ok(int64_t n, int64_t k, int64_t d);
-int f32_split_fwd_nsplit(int64_t batch, int64_t n, int64_t d);
+int f32_split_fwd_nsplit(int64_t batch, int64_t n, int64_t k, int64_t d);
 hipError_t launch_project_f32_split(const float *phi, const float *mass, const float *feat, int64_t batch, int64_t n,
                                     int64_t k, int64_t d, float *A, void *ws, hipStream_t st);
 // float32 backward projection on the bf16 matrix cores, operands split into three bf16 parts (k even, k <= 64).

@@ -674,7 +674,7 @@ size_t project_workspace_bytes(int64_t batch, int64_t n, int64_t k, int64_t d, i
         if (nb > ns) ns = nb;
     }
     if (dtype == 0 && f32_split_fwd_shape_ok(n, k, d)) {
-        const int64_t nx = f32_split_fwd_nsplit(batch, n, d);
+        const int64_t nx = f32_split_fwd_nsplit(batch, n, k, d);
         if (nx > ns) ns = nx;
     }
     if (ns <= 1) return 0;

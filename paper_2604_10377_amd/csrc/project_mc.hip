@@ -541,10 +541,15 @@ constexpr int XFL = 11;     // loads per wave per stage: 8 feature rows, 2 basis
 __host__ __device__ constexpr int x3_np(int k) { return (k + 7) / 8; }  // 1 KB basis windows (32 rows x k floats)
 __host__ __device__ constexpr int x3_stage_bytes(int k) { return (32 + x3_np(k)) * 1024 + 256; }
 
+// SLICED (k > 64, k % 4 == 0): the workgroup owns basis rows [64 kb, 64 kb + 64); a stage holds that
+// 64-float slice of each vertex row (8 windows of 4 vertices).  The row blocks and column blocks of
+// one vertex chunk take consecutive ids on one XCD, so the feature tile they all read comes from
+// HBM once and from that XCD's L2 afterwards.
+template <bool SLICED>
 __global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__restrict__ phi,
                                                            const float *__restrict__ mass,
                                                            const float *__restrict__ feat, int n, int k, int d,
-                                                           int nsplit, int dblocks, int ntiles,
+                                                           int nsplit, int dblocks, int kblocks, int ntiles,
                                                            float *__restrict__ out)
 {
     extern __shared__ __align__(16) float smem[];
@@ -553,11 +558,15 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__rest
     const int m16 = lane & 15, g4 = lane >> 4;
     const int bid = blockIdx.x;
     const int xs = bid & 7, q = bid >> 3;
-    const int db = q % dblocks;
-    const int j = (q / dblocks) * 8 + xs;
+    const int dk = dblocks * kblocks;
+    const int db = (q % dk) % dblocks, kb = (q % dk) / dblocks;
+    const int j = (q / dk) * 8 + xs;
     if (j >= ntiles) return;  // whole workgroup, before any barrier
     const int split = j % nsplit, s = j / nsplit;
     const int dbase = db * 256;
+    const int kbase = SLICED ? 64 * kb : 0;
+    const int kvalid = SLICED ? min(64, k - kbase) : k;  // basis rows of this block (even, >= 4)
+    const int pstride = SLICED ? 64 : k;                 // LDS floats per vertex row of the basis tile
 
     const int nst_all = (n + XS - 1) / XS;
     const int st0 = (int)(((long)split * nst_all) / nsplit), st1 = (int)(((long)(split + 1) * nst_all) / nsplit);
@@ -568,8 +577,8 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__rest
     const float *F = feat + (size_t)s * n * d;
     const float *Mv = mass + (size_t)s * n;
 
-    const int np = x3_np(k);
-    const int stage_bytes = x3_stage_bytes(k);  // [feature rows 32 KB][basis np KB][mass 256 B]
+    const int np = SLICED ? 8 : x3_np(k);
+    const int stage_bytes = (32 + np) * 1024 + 256;  // [feature rows 32 KB][basis np KB][mass 256 B]
     char *ring = reinterpret_cast<char *>(smem);
     for (int e = tid * 16; e < XNST * stage_bytes; e += 256 * 16)
         *reinterpret_cast<f32x4 *>(ring + e) = f32x4{0, 0, 0, 0};
@@ -581,7 +590,11 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__rest
     // may hold fewer rows, clamps row indices.
     const int fcol = min(dbase + 4 * lane, d - 4);  // feature column of this lane (d % 4 == 0)
     const int pw0 = min(wave, np - 1), pw1 = min(wave + 4, np - 1);
-    const int poff0 = min(pw0 * 256 + 4 * lane, XS * k - 4), poff1 = min(pw1 * 256 + 4 * lane, XS * k - 4);
+    // basis offsets (floats from the stage's first vertex row): contiguous windows of the 32 x k tile,
+    // or, sliced, vertex 4w + lane/16 and the 4 floats at column 64 kb + 4 (lane % 16) (clamped to k - 4)
+    const int scol = min(kbase + 4 * (lane & 15), k - 4);
+    const int poff0 = SLICED ? (4 * pw0 + (lane >> 4)) * k + scol : min(pw0 * 256 + 4 * lane, XS * k - 4);
+    const int poff1 = SLICED ? (4 * pw1 + (lane >> 4)) * k + scol : min(pw1 * 256 + 4 * lane, XS * k - 4);
     auto issue = [&](int t) {
         char *S = ring + (t % XNST) * stage_bytes;
         const int v = vbeg + t * XS;
@@ -603,8 +616,14 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__rest
                 dma16(F + (size_t)(v + r) * d + fcol, reinterpret_cast<float *>(S + (8 * wave + i) * 1024));
             }
             const float *Pv = P + (size_t)v * k;
-            dma16(Pv + min(poff0, pvalid - 4), reinterpret_cast<float *>(S + (32 + pw0) * 1024));
-            dma16(Pv + min(poff1, pvalid - 4), reinterpret_cast<float *>(S + (32 + pw1) * 1024));
+            if (SLICED) {  // vertices past the stage's rows read the last row
+                const int r0 = min(4 * pw0 + (lane >> 4), rows - 1), r1 = min(4 * pw1 + (lane >> 4), rows - 1);
+                dma16(Pv + (size_t)r0 * k + scol, reinterpret_cast<float *>(S + (32 + pw0) * 1024));
+                dma16(Pv + (size_t)r1 * k + scol, reinterpret_cast<float *>(S + (32 + pw1) * 1024));
+            } else {
+                dma16(Pv + min(poff0, pvalid - 4), reinterpret_cast<float *>(S + (32 + pw0) * 1024));
+                dma16(Pv + min(poff1, pvalid - 4), reinterpret_cast<float *>(S + (32 + pw1) * 1024));
+            }
             __builtin_amdgcn_global_load_lds((glb_void_t *)(Mv + v + min(lane, rows - 1)),
                                              (lds_void_t *)(S + (32 + np) * 1024), 4, 0, 0);
         }
@@ -617,7 +636,7 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__rest
         for (int t = 0; t < 4; ++t) acc[a][t] = f32x4{0, 0, 0, 0};
     // rows 4*m16 .. +3 as two pairs, each clamped into the row on its own (k even): a pair past k
     // reads the last pair and its results are dropped, while rows below k keep their own data
-    const int r01 = min(4 * m16, k - 2), r23 = min(4 * m16 + 2, k - 2);
+    const int r01 = min(4 * m16, kvalid - 2), r23 = min(4 * m16 + 2, kvalid - 2);
     const int cw = wave * 64 + 4 * m16;  // this lane's 4 feature columns within the block
 
     if (nst > 0) issue(0);
@@ -648,7 +667,7 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__rest
             float x[2][4];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const float *row = Ps + (8 * g4 + 2 * jj + h) * k;
+                const float *row = Ps + (8 * g4 + 2 * jj + h) * pstride;
                 const float2 lo = *reinterpret_cast<const float2 *>(row + r01);
                 const float2 hi = *reinterpret_cast<const float2 *>(row + r23);
                 const float m = mv[2 * jj + h];
@@ -698,7 +717,7 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__rest
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            const int row = 16 * g4 + 4 * r + a;
+            const int row = kbase + 16 * g4 + 4 * r + a;
             if (row >= k || col >= d) continue;
             const f32x4 v = f32x4{acc[a][0][r], acc[a][1][r], acc[a][2][r], acc[a][3][r]};
             *reinterpret_cast<f32x4 *>(O + (size_t)row * d + col) = v;  // d % 4 == 0: all 4 columns exist
@@ -707,37 +726,49 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__rest
 
 bool f32_split_fwd_shape_ok(int64_t n, int64_t k, int64_t d)
 {
-    return k >= 4 && k <= 64 && k % 2 == 0 && d % 4 == 0 && n % 4 == 0 && n >= 4 * XS;
+    const bool kok = (k >= 4 && k <= 64 && k % 2 == 0) || (k > 64 && k <= kMaxK && k % 4 == 0);
+    return kok && d % 4 == 0 && n % 4 == 0 && n >= 4 * XS;
 }
 
-int f32_split_fwd_nsplit(int64_t batch, int64_t n, int64_t d)
+static int x3_kblocks(int64_t k) { return k <= 64 ? 1 : (int)((k + 63) / 64); }
+
+int f32_split_fwd_nsplit(int64_t batch, int64_t n, int64_t k, int64_t d)
 {
-    const int64_t dblocks = (d + 255) / 256;
+    const int64_t blocks = (d + 255) / 256 * x3_kblocks(k);
     const int64_t stages = (n + XS - 1) / XS;
-    int64_t ns = (2 * device_cus()) / (batch * dblocks);  // two workgroups per CU
-    if (ns > stages / 4) ns = stages / 4;                  // keep >= 4 stages per chunk
+    int64_t ns = (2 * device_cus()) / (batch * blocks);  // two workgroups per CU
+    if (ns > stages / 4) ns = stages / 4;               // keep >= 4 stages per chunk
     if (ns < 1) ns = 1;
     return (int)ns;
+}
+
+template <bool SLICED>
+static hipError_t dispatch_x3(const float *phi, const float *mass, const float *feat, int64_t batch, int64_t n,
+                              int64_t k, int64_t d, int ns, float *out, hipStream_t st)
+{
+    const int kblocks = x3_kblocks(k);
+    const size_t lds = (size_t)XNST * ((32 + (SLICED ? 8 : x3_np((int)k))) * 1024 + 256);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)proj_fwd_x3_kernel<SLICED>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)((size_t)XNST * x3_stage_bytes(64)));
+        attr_set = true;
+    }
+    const int dblocks = (int)((d + 255) / 256);
+    const int ntiles = (int)(batch * ns);
+    const unsigned grid = (unsigned)(8 * dblocks * kblocks * ((ntiles + 7) / 8));
+    hipLaunchKernelGGL((proj_fwd_x3_kernel<SLICED>), dim3(grid), dim3(256), lds, st, phi, mass, feat, (int)n, (int)k,
+                       (int)d, ns, dblocks, kblocks, ntiles, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_project_f32_split(const float *phi, const float *mass, const float *feat, int64_t batch, int64_t n,
                                     int64_t k, int64_t d, float *A, void *ws, hipStream_t st)
 {
-    const int ns = f32_split_fwd_nsplit(batch, n, d);
+    const int ns = f32_split_fwd_nsplit(batch, n, k, d);
     float *out = ns > 1 ? (float *)ws : A;
-    const size_t lds = (size_t)XNST * x3_stage_bytes((int)k);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)proj_fwd_x3_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)((size_t)XNST * x3_stage_bytes(64)));
-        attr_set = true;
-    }
-    const int dblocks = (int)((d + 255) / 256);
-    const int ntiles = (int)(batch * ns);
-    const unsigned grid = (unsigned)(8 * dblocks * ((ntiles + 7) / 8));
-    hipLaunchKernelGGL(proj_fwd_x3_kernel, dim3(grid), dim3(256), lds, st, phi, mass, feat, (int)n, (int)k, (int)d,
-                       ns, dblocks, ntiles, out);
-    hipError_t e = hipGetLastError();
+    hipError_t e = k <= 64 ? dispatch_x3<false>(phi, mass, feat, batch, n, k, d, ns, out, st)
+                           : dispatch_x3<true>(phi, mass, feat, batch, n, k, d, ns, out, st);
     if (e != hipSuccess || ns <= 1) return e;
     return launch_reduce(out, ns, batch, k, d, A, st);
 }

@@ -72,7 +72,6 @@ __global__ __launch_bounds__(512) void rowsolve_tiles_kernel(
     const int T = (kx + 31) >> 5;   // column tiles
     const int TR = (kx + 32) >> 5;  // tile rows (row kx is the right-hand side)
     const int AR = kx >> 5, ar = kx & 31;
-    const int ntiles = T * TR - (T * (T - 1)) / 2;
 
     for (int sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
         const int p = sys / ky, i = sys % ky;
@@ -110,24 +109,24 @@ __global__ __launch_bounds__(512) void rowsolve_tiles_kernel(
         const float *Kp = STORED ? nullptr : K + (size_t)p * kx * kx;
         const float *Lp = STORED ? Lin + ((size_t)p * ky + i) * (size_t)(kx * (kx + 1) / 2) : nullptr;
         const float *rp = rhs + ((size_t)p * ky + i) * kx;
-        for (int e = tid; e < ntiles * 1024; e += 512) {
-            const int tau = e >> 10, rc = e & 1023, r = rc >> 5, c = rc & 31;
-            int J = 0, t2 = tau;
-            while (t2 >= TR - J) {
-                t2 -= TR - J;
-                ++J;
+        // tile by tile (column-major order of the lower triangle), two entries per thread per tile:
+        // the loads of a tile are independent, so they are in flight together
+        for (int J = 0, tau = 0; J < T; ++J)
+            for (int I = J; I < TR; ++I, ++tau) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int rc = tid + 512 * h, r = rc >> 5, c = rc & 31;
+                    const int row = 32 * I + r, col = 32 * J + c;
+                    float v = 0.f;
+                    if (row < kx && col <= row) {
+                        if (STORED) v = Lp[packed_col_t(col, kx) + row - col];
+                        else v = Kp[(size_t)row * kx + col] + (row == col ? s_shift[row] : 0.f);
+                    } else if (row == kx && col < kx) {
+                        v = rp[col];
+                    }
+                    tiles[tau * TSZ + r * TLD + c] = v;
+                }
             }
-            const int I = J + t2;
-            const int row = 32 * I + r, col = 32 * J + c;
-            float v = 0.f;
-            if (row < kx && col <= row) {
-                if (STORED) v = Lp[packed_col_t(col, kx) + row - col];
-                else v = Kp[(size_t)row * kx + col] + (row == col ? s_shift[row] : 0.f);
-            } else if (row == kx && col < kx) {
-                v = rp[col];
-            }
-            tiles[tau * TSZ + r * TLD + c] = v;
-        }
         __syncthreads();
 
         for (int pstep = 0; pstep < T; ++pstep) {
@@ -140,6 +139,9 @@ __global__ __launch_bounds__(512) void rowsolve_tiles_kernel(
 #pragma unroll
                 for (int q = 0; q < 32; ++q) sr[q] = (lane < 32) ? Dt[l32 * TLD + q] : 0.f;
                 int fail = 0;
+                // column c of L: the pivot and the entries L_qc come from the lanes that hold rows c and q
+                // (readlane, no LDS round trip); lane j updates its row; entries above the diagonal are
+                // updated too but never read again
 #pragma unroll
                 for (int c = 0; c < 32; ++c) {
                     if (c < kxl && fail == 0) {
@@ -147,51 +149,28 @@ __global__ __launch_bounds__(512) void rowsolve_tiles_kernel(
                         if (!(piv > 0.f) || !isfinite(piv)) {
                             fail = 32 * pstep + c + 1;
                         } else if (!STORED) {
-                            // column c of L: every lane scales its entry; rows above c only touch
-                            // their own upper-triangle entries, which are never read again
                             const float l = sr[c] * __builtin_amdgcn_rsqf(piv);
                             sr[c] = l;
-                            if (lane < 32) s_bc[lane] = l;
-                            __builtin_amdgcn_wave_barrier();
-                            f32x4 lq[8];
 #pragma unroll
-                            for (int q4 = 0; q4 < 8; ++q4)
-                                if (4 * q4 + 3 > c) lq[q4] = *reinterpret_cast<const f32x4 *>(&s_bc[4 * q4]);
-#pragma unroll
-                            for (int q4 = 0; q4 < 8; ++q4)
-#pragma unroll
-                                for (int e = 0; e < 4; ++e)
-                                    if (4 * q4 + e > c) sr[4 * q4 + e] -= l * lq[q4][e];
-                            __builtin_amdgcn_wave_barrier();
+                            for (int q = c + 1; q < 32; ++q) sr[q] -= l * readlane(l, q);
                         }
                     }
                 }
-                if (fail == 0 && lane < 32) {
+                if (fail == 0 && lane < 32 && !STORED) {
 #pragma unroll
-                    for (int q = 0; q < 32; ++q) {
-                        if (!STORED) Dt[l32 * TLD + q] = sr[q];
-                        s_dl[l32 * LDD + q] = (q < kxl && q <= l32 && l32 < kxl) ? sr[q] : 0.f;
-                    }
+                    for (int q = 0; q < 32; ++q) Dt[l32 * TLD + q] = sr[q];
                 }
                 if (lane == 0 && fail != 0) *s_fail = fail;
-                __builtin_amdgcn_wave_barrier();
                 if (fail == 0) {
-                    // column `lane` of L_pp^{-1}: m_q = (delta_{q,lane} - sum_{t<q} L_qt m_t) / L_qq
+                    // column `lane` of L_pp^{-1}: m_q = (delta_{q,lane} - sum_{t<q} L_qt m_t) / L_qq, the
+                    // entries of L read from the lanes holding them
                     float m[32];
 #pragma unroll
                     for (int q = 0; q < 32; ++q) {
-                        float t = 0.f;
-                        if (q < kxl) {
+                        float t = (q == lane) ? 1.f : 0.f;
 #pragma unroll
-                            for (int t4 = 0; t4 < (q + 3) / 4; ++t4) {
-                                const f32x4 Lq = *reinterpret_cast<const f32x4 *>(&s_dl[q * LDD + 4 * t4]);
-#pragma unroll
-                                for (int e = 0; e < 4; ++e)
-                                    if (4 * t4 + e < q) t -= Lq[e] * m[4 * t4 + e];
-                            }
-                            t = (t + (q == lane ? 1.f : 0.f)) * __builtin_amdgcn_rcpf(s_dl[q * LDD + q]);
-                        }
-                        m[q] = t;
+                        for (int tt = 0; tt < q; ++tt) t -= readlane(sr[tt], q) * m[tt];
+                        m[q] = (q < kxl) ? t * __builtin_amdgcn_rcpf(readlane(sr[q], q)) : 0.f;
                     }
                     if (lane < 32) {
 #pragma unroll
@@ -276,16 +255,23 @@ __global__ __launch_bounds__(512) void rowsolve_tiles_kernel(
 
         // ---- factors out (forward mode) ----------------------------------------------------
         if (MODE == RT_FWD && Lout && fail == 0) {
+            // in packed (column-major) order, so consecutive threads store consecutive floats: thread
+            // tid walks entries tid, tid + 512, ... keeping its (column, row) position incrementally
             float *Lo = Lout + ((size_t)p * ky + i) * (size_t)(kx * (kx + 1) / 2);
-            for (int e = tid; e < ntiles * 1024; e += 512) {
-                const int tau = e >> 10, rc = e & 1023, r = rc >> 5, c = rc & 31;
-                int J = 0, t2 = tau;
-                while (t2 >= TR - J) {
-                    t2 -= TR - J;
-                    ++J;
+            const int total = kx * (kx + 1) / 2;
+            int col = 0, row = tid;  // entry tid: column 0 holds rows 0 .. kx-1
+            while (col < kx && row >= kx) {  // past the end of column col: continue at row col + 1
+                row = row - kx + col + 1;
+                ++col;
+            }
+            for (int e = tid; e < total; e += 512) {
+                const int J = col >> 5, I = row >> 5;
+                Lo[e] = tiles[tile_index(I, J, TR) * TSZ + (row & 31) * TLD + (col & 31)];
+                row += 512;  // advance 512 entries down the packed columns
+                while (col < kx && row >= kx) {
+                    row = row - kx + col + 1;
+                    ++col;
                 }
-                const int row = 32 * (J + t2) + r, col = 32 * J + c;
-                if (row < kx && col <= row) Lo[packed_col_t(col, kx) + row - col] = tiles[tau * TSZ + r * TLD + c];
             }
         }
 

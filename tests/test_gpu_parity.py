@@ -57,10 +57,13 @@ LDS_CASES = [(2, 4004, 30, 128), (3, 2048, 17, 200), (2, 640, 52, 256), (1, 1000
 # float32 operands split for the bf16 matrix cores (k even <= 64, n % 4 == 0, d % 4 == 0): most cases
 # above, plus the smallest k with a partial second column block and a narrow block at k = 62
 SPLIT_CASES = [(2, 1028, 4, 260), (1, 2052, 62, 36)]
+# k > 64 (k % 4 == 0): the basis is taken in 64-row slices; partial last slices and column blocks
+SLICED_CASES = [(2, 4004, 80, 256), (1, 2052, 300, 516), (3, 1024, 128, 64), (1, 8192, 68, 260)]
 
 
 @pytest.mark.parametrize("b,n,k,d", [(1, 1, 1, 1), (2, 37, 5, 7), (3, 1234, 30, 128), (2, 5000, 50, 256),
-                                     (1, 4097, 64, 300), (2, 999, 65, 33), (1, 20011, 120, 256)] + LDS_CASES + SPLIT_CASES)
+                                     (1, 4097, 64, 300), (2, 999, 65, 33), (1, 20011, 120, 256)] + LDS_CASES + SPLIT_CASES
+                         + SLICED_CASES)
 def test_project_forward(F, dev, b, n, k, d):
     import torch
     phi, mass, feat = _shapes(1, b, n, k, d)
