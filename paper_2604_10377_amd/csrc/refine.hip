@@ -259,20 +259,20 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
         if (tid == 0) L[pk(c, c)] = lc;
         for (int r = c + 1 + tid; r < kx; r += 512) L[pk(r, c)] /= lc;
         __syncthreads();
-        // trailing triangle rows (c, kx), columns (c, r]: the m x m square walked in steps of 512 entries
+        // trailing triangle rows (c, kx), columns (c, r]: thread -> (row, stride class), so a row's
+        // entries are contiguous in the packed layout and all 512 threads share the work evenly
         const int m = kx - c - 1;
         if (m > 0) {
-            int rr = tid / m, qq = tid - rr * m;
-            const int dr = 512 / m, dq = 512 - dr * m;
-            for (; rr < m; rr += dr, qq += dq) {
-                if (qq >= m) {
-                    qq -= m;
-                    ++rr;
-                    if (rr >= m) break;
-                }
-                if (qq <= rr) {
-                    const int r = c + 1 + rr, q = c + 1 + qq;
-                    L[pk(r, q)] -= L[pk(r, c)] * L[pk(q, c)];
+            const int chunks = max(1, 512 / m);
+            if (tid < chunks * m) {
+                const int rr = tid % m, ch = tid / m;
+                const int r = c + 1 + rr;
+                const float lrc = L[pk(r, c)];
+                float *Lr = L + r * (r + 1) / 2;  // row r
+#pragma unroll 4
+                for (int qq = ch; qq <= rr; qq += chunks) {
+                    const int q = c + 1 + qq;
+                    Lr[q] -= lrc * L[pk(q, c)];
                 }
             }
         }

@@ -264,14 +264,24 @@ __global__ __launch_bounds__(512) void rowsolve_tiles_kernel(
                 row = row - kx + col + 1;
                 ++col;
             }
-            for (int e = tid; e < total; e += 512) {
-                const int J = col >> 5, I = row >> 5;
-                Lo[e] = tiles[tile_index(I, J, TR) * TSZ + (row & 31) * TLD + (col & 31)];
-                row += 512;  // advance 512 entries down the packed columns
-                while (col < kx && row >= kx) {
-                    row = row - kx + col + 1;
-                    ++col;
+            // 8 entries per batch: their LDS reads are issued together, then the stores
+            for (int e0 = tid; e0 < total; e0 += 8 * 512) {
+                int src[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    src[u] = (col < kx) ? tile_index(row >> 5, col >> 5, TR) * TSZ + (row & 31) * TLD + (col & 31) : 0;
+                    row += 512;  // advance 512 entries down the packed columns
+                    while (col < kx && row >= kx) {
+                        row = row - kx + col + 1;
+                        ++col;
+                    }
                 }
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = tiles[src[u]];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (e0 + 512 * u < total) Lo[e0 + 512 * u] = v[u];
             }
         }
 
