@@ -168,7 +168,7 @@ def roofline_entry(flops, nbytes, seconds, mfma_peak_tflops):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "headline_hbm_traffic.txt")
-KERNEL_OF_PHASE = {"project": "proj_fwd_x3_kernel", "project_backward": "proj_bwd_mc_kernel<float, 3, 3, 2>"}
+KERNEL_OF_PHASE = {"project": "proj_fwd_x3_kernel<false>", "project_backward": "proj_bwd_mc_kernel<float, 3, 3, 2>"}
 
 
 def measured_traffic(phase: str, workload: str):
