@@ -478,9 +478,34 @@ __global__ __launch_bounds__(512) void proj_bwd_lds_kernel(const float *__restri
     }
 }
 
-// A[s] = sum over chunks (in chunk order) of part[s][chunk].
+// A[s] = sum over chunks (in chunk order) of part[s][chunk].  Four consecutive
+// elements per thread (k*d % 4 == 0, 16-byte aligned buffers); the chunks are
+// read in groups of RG, all loads of a group in flight before the adds.
+constexpr int RG = 8;
+
 __global__ __launch_bounds__(256) void proj_reduce_kernel(const float *__restrict__ part, int nsplit, int64_t kd,
                                                           int64_t total, float *__restrict__ A)
+{
+    const int64_t q4 = kd / 4, tq = total / 4;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tq; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = e / q4, r = e - s * q4;
+        const f32x4 *p = reinterpret_cast<const f32x4 *>(part + (size_t)s * nsplit * kd) + r;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int c0 = 0; c0 < nsplit; c0 += RG) {
+            f32x4 v[RG];
+#pragma unroll
+            for (int u = 0; u < RG; ++u) v[u] = p[(size_t)min(c0 + u, nsplit - 1) * q4];
+#pragma unroll
+            for (int u = 0; u < RG; ++u)
+                if (c0 + u < nsplit) acc += v[u];
+        }
+        reinterpret_cast<f32x4 *>(A)[e] = acc;
+    }
+}
+
+// The same sum, one element per thread, for any k*d and alignment.
+__global__ __launch_bounds__(256) void proj_reduce1_kernel(const float *__restrict__ part, int nsplit, int64_t kd,
+                                                           int64_t total, float *__restrict__ A)
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = e / kd, r = e - s * kd;
@@ -787,10 +812,11 @@ hipError_t launch_reduce(const float *part, int nsplit, int64_t batch, int64_t k
                                 hipStream_t st)
 {
     const int64_t total = batch * k * d;
-    int64_t blocks = (total + 255) / 256;
+    const bool vec = (k * d) % 4 == 0 && aligned16(part) && aligned16(A);
+    int64_t blocks = ((vec ? total / 4 : total) + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(proj_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, part, nsplit, (int64_t)(k * d),
-                       total, A);
+    hipLaunchKernelGGL(vec ? proj_reduce_kernel : proj_reduce1_kernel, dim3((unsigned)blocks), dim3(256), 0, st, part,
+                       nsplit, (int64_t)(k * d), total, A);
     return hipGetLastError();
 }
 

@@ -93,6 +93,93 @@ __global__ __launch_bounds__(256) void gram_kernel(const float *__restrict__ A, 
     }
 }
 
+// The same products for d % 4 == 0 and 16-byte aligned rows.  The feature range
+// is cut into octets of 8 floats; lane half h of every octet takes the float4 at
+// offset 4h, whose 4 values are 4 matrix-core steps (the two halves supply the
+// two K slots of each step).  A wave owns a contiguous run of octets and reads
+// them in groups of GO octets: a group's loads are all in flight together, and
+// the next group is loaded before the current one is multiplied (two buffers,
+// swapped by unrolling).  Addresses are clamped into the arrays and the values
+// masked where the operands are formed, so no load waits on a branch.
+constexpr int GO = 8;
+
+__global__ __launch_bounds__(256) void gram4_kernel(const float *__restrict__ A, const float *__restrict__ B, int kx,
+                                                    int ky, int d, int tkx, int tky, int with_R,
+                                                    float *__restrict__ K, float *__restrict__ R)
+{
+    __shared__ float red[4][16][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+    const int tiles = tkx * tkx + (with_R ? tky * tkx : 0);
+    const int p = blockIdx.x / tiles;
+    int t = blockIdx.x % tiles;
+    const float *X;
+    float *O;
+    int rowsX;
+    if (t < tkx * tkx) {
+        X = A + (size_t)p * kx * d;
+        O = K + (size_t)p * kx * kx;
+        rowsX = kx;
+    } else {
+        t -= tkx * tkx;
+        X = B + (size_t)p * ky * d;
+        O = R + (size_t)p * ky * kx;
+        rowsX = ky;
+    }
+    const int I = t / tkx, J = t % tkx;
+    const float *Y = A + (size_t)p * kx * d;
+    const int m = I * 32 + l32, nn = J * 32 + l32;
+    const bool mok = m < rowsX, nok = nn < kx;
+    const float *xr = X + (size_t)(mok ? m : 0) * d;
+    const float *yr = Y + (size_t)(nok ? nn : 0) * d;
+
+    const int noct = (d + 7) / 8;
+    const int per = (noct + 3) / 4;
+    const int o0 = wave * per, o1 = min(noct, o0 + per);
+    const int ngrp = o1 > o0 ? (o1 - o0 + GO - 1) / GO : 0;
+    f32x16 acc = zero16();
+    f32x4 xa[GO], ya[GO], xb[GO], yb[GO];
+    auto load = [&](int g, f32x4 (&xs)[GO], f32x4 (&ys)[GO]) {
+#pragma unroll
+        for (int u = 0; u < GO; ++u) {
+            const int off = min(8 * (o0 + g * GO + u) + 4 * half, d - 4);
+            xs[u] = *reinterpret_cast<const f32x4 *>(xr + off);
+            ys[u] = *reinterpret_cast<const f32x4 *>(yr + off);
+        }
+    };
+    auto mul = [&](int g, const f32x4 (&xs)[GO], const f32x4 (&ys)[GO]) {
+#pragma unroll
+        for (int u = 0; u < GO; ++u) {
+            const int o = o0 + g * GO + u;
+            const bool ok = o < o1 && 8 * o + 4 * half < d;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                acc = mfma32x32x2((ok && mok) ? xs[u][e] : 0.f, (ok && nok) ? ys[u][e] : 0.f, acc);
+        }
+    };
+    if (ngrp > 0) {
+        load(0, xa, ya);
+        for (int g = 0; g < ngrp; g += 2) {
+            load(min(g + 1, ngrp - 1), xb, yb);
+            mul(g, xa, ya);
+            if (g + 1 >= ngrp) break;
+            load(min(g + 2, ngrp - 1), xa, ya);
+            mul(g + 1, xb, yb);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[r];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float v = red[0][r][lane] + red[1][r][lane] + red[2][r][lane] + red[3][r][lane];
+            const int row = I * 32 + acc32_row(r, lane);
+            if (row < rowsX && nok) O[(size_t)row * kx + nn] = v;
+        }
+    }
+}
+
 // Offset of column c in LAPACK lower packed column-major storage of order m.
 __device__ __forceinline__ int packed_col(int c, int m) { return c * m - (c * (c - 1)) / 2; }
 
@@ -131,8 +218,28 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     const int T = kx * (kx + 1) / 2;
     const bool jok = j < kx;
 
-    // --- mask row i and validity of lambda / normaliser -------------------------
+    // --- every input load first, unconditional from clamped addresses, so they are all in flight together
+    const int jc = jok ? j : kx - 1;
     const float lamv = lam[p];
+    const float muy = ey[(size_t)p * ky + i];
+    const float exj = ex[(size_t)p * kx + jc];
+    const float eyj = ey[(size_t)p * ky + min(j, ky - 1)];
+    float sr[KMAX];
+    if (MODE == RS_BWD_STORED) {
+        const float *Lp = Lin + ((size_t)p * ky + i) * T;
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {
+            const int qc = min(q, jc);
+            sr[q] = Lp[packed_col(qc, kx) + jc - qc];
+        }
+    } else {
+        const float *Kp = K + (size_t)p * kx * kx + (size_t)jc * kx;
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) sr[q] = Kp[min(q, kx - 1)];
+    }
+    const float rin = rhs[((size_t)p * ky + i) * kx + jc];
+
+    // --- mask row i and validity of lambda / normaliser -------------------------
     int fail = 0;
     if (!(lamv >= 0.f) || !isfinite(lamv)) fail = -1;
     MaskParams mp;
@@ -140,30 +247,20 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     mp.gamma = gamma;
     mp.inv_scale = 1.f;
     if (mask_kind == 1) {
-        float mx = -INFINITY;
-        for (int q = j; q < kx; q += 64) mx = fmaxf(mx, ex[(size_t)p * kx + q]);
-        for (int q = j; q < ky; q += 64) mx = fmaxf(mx, ey[(size_t)p * ky + q]);
+        float mx = fmaxf(jok ? exj : -INFINITY, j < ky ? eyj : -INFINITY);  // k_x <= KMAX <= 64
+        for (int q = j + 64; q < ky; q += 64) mx = fmaxf(mx, ey[(size_t)p * ky + q]);
         mx = uniform(wave_max(mx));
         if ((!(mx > 0.f) || !isfinite(mx)) && fail == 0) fail = -2;
         mp.inv_scale = 1.f / mx;
     }
     fail = __builtin_amdgcn_readfirstlane(fail);
-    const float muy = ey[(size_t)p * ky + i];
-    const float dval = (jok && fail == 0) ? mask_entry(muy, ex[(size_t)p * kx + j], mp) : 0.f;
+    const float dval = (jok && fail == 0) ? mask_entry(muy, exj, mp) : 0.f;
     const float shift = lamv * dval;
 
-    // --- row j of S_i (lower part) or of the stored factor, and the right-hand side
-    float sr[KMAX];
-    if (MODE == RS_BWD_STORED) {
-        const float *Lp = Lin + ((size_t)p * ky + i) * T;
+    // row j of S_i (lower part) or of the stored factor; the strict upper part is zero
 #pragma unroll
-        for (int q = 0; q < KMAX; ++q) sr[q] = (jok && q <= j) ? Lp[packed_col(q, kx) + j - q] : 0.f;
-    } else {
-        const float *Kp = K + (size_t)p * kx * kx + (size_t)(jok ? j : 0) * kx;
-#pragma unroll
-        for (int q = 0; q < KMAX; ++q) sr[q] = (jok && q <= j) ? Kp[q] : 0.f;
-    }
-    float r = jok ? rhs[((size_t)p * ky + i) * kx + j] : 0.f;
+    for (int q = 0; q < KMAX; ++q) sr[q] = (jok && q <= j) ? sr[q] : 0.f;
+    float r = jok ? rin : 0.f;
     float yv = 0.f, myinv = 0.f;
 
     if (MODE != RS_BWD_STORED) {
@@ -284,22 +381,44 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
     const float *Cp = C + (size_t)p * ky * kx;
     const float *Ap = A + (size_t)p * kx * d;
     const float *Bp = B + (size_t)p * ky * d;
-    for (int e = threadIdx.x; e < ky * kx; e += 256) {
-        sV[e] = Vp[e];
-        sC[e] = Cp[e];
+    // staging: every load of the workgroup's operands is issued before the first
+    // LDS write (fixed counts, clamped addresses, masked at the write)
+    constexpr int NVC = (KM * KM + 255) / 256, NAB = KM * 64 / 256;
+    const int nvc = ky * kx;
+    float rv[NVC], rc[NVC], ra[NAB], rb[NAB];
+#pragma unroll
+    for (int u = 0; u < NVC; ++u) {
+        const int e = min((int)threadIdx.x + 256 * u, nvc - 1);
+        rv[u] = Vp[e];
+        rc[u] = Cp[e];
     }
-    for (int e = threadIdx.x; e < kx * 64; e += 256) {
-        const int rr = e >> 6, cc = e & 63;
-        sA[e] = cc < dw ? Ap[(size_t)rr * d + d0 + cc] : 0.f;
+#pragma unroll
+    for (int u = 0; u < NAB; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int rr = e >> 6, cc = min(e & 63, dw - 1);
+        ra[u] = Ap[(size_t)min(rr, kx - 1) * d + d0 + cc];
+        rb[u] = Bp[(size_t)min(rr, ky - 1) * d + d0 + cc];
     }
-    for (int e = threadIdx.x; e < ky * 64; e += 256) {
-        const int rr = e >> 6, cc = e & 63;
-        sB[e] = cc < dw ? Bp[(size_t)rr * d + d0 + cc] : 0.f;
+    const bool sum_dlam = db == 0 && dlam && wave == 0;
+    const float dl = (sum_dlam && lane < ky) ? dlam_part[(size_t)p * ky + lane] : 0.f;  // k_y <= KM <= 64
+#pragma unroll
+    for (int u = 0; u < NVC; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        if (e < nvc) {
+            sV[e] = rv[u];
+            sC[e] = rc[u];
+        }
     }
-    if (db == 0 && dlam && threadIdx.x == 0) {
-        float s = 0.f;
-        for (int i = 0; i < ky; ++i) s += dlam_part[(size_t)p * ky + i];
-        dlam[p] = s;
+#pragma unroll
+    for (int u = 0; u < NAB; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const bool cin = (e & 63) < dw;
+        sA[e] = cin ? ra[u] : 0.f;
+        sB[e] = cin ? rb[u] : 0.f;
+    }
+    if (sum_dlam) {
+        const float s = wave_sum(dl);
+        if (lane == 0) dlam[p] = s;
     }
     __syncthreads();
 
@@ -423,8 +542,9 @@ static void launch_gram(const float *A, const float *B, int64_t P, int64_t kx, i
 {
     const int tkx = (int)((kx + 31) / 32), tky = (int)((ky + 31) / 32);
     const int tiles = tkx * tkx + (with_R ? tky * tkx : 0);
-    hipLaunchKernelGGL(gram_kernel, dim3((unsigned)(P * tiles)), dim3(256), 0, st, A, B, (int)kx, (int)ky, (int)d,
-                       tkx, tky, with_R ? 1 : 0, K, R);
+    const bool vec = d % 4 == 0 && ((uintptr_t)A & 15) == 0 && (!with_R || ((uintptr_t)B & 15) == 0);
+    hipLaunchKernelGGL(vec ? gram4_kernel : gram_kernel, dim3((unsigned)(P * tiles)), dim3(256), 0, st, A, B, (int)kx,
+                       (int)ky, (int)d, tkx, tky, with_R ? 1 : 0, K, R);
 }
 
 // Row systems (waves) per workgroup of the register row solve; the plan's
