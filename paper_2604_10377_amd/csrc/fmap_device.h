@@ -27,6 +27,24 @@ __device__ __forceinline__ f32x16 zero16()
     return z;
 }
 
+// Strided loop e = start, start + stride, ... < end whose body loads one value
+// and consumes it (e.g. staging into LDS).  Written as a plain loop, the
+// compiler waits for each load before the next one is issued, one memory round
+// trip per iteration.  Here U loads are issued from clamped indices before any
+// is consumed, so a loop of N iterations costs N / U round trips.
+template <int U, typename Load, typename Use>
+__device__ __forceinline__ void batched_for(int start, int end, int stride, Load load, Use use)
+{
+    for (int e0 = start; e0 < end; e0 += U * stride) {
+        decltype(load(0)) v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = load(min(e0 + u * stride, end - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + u * stride < end) use(e0 + u * stride, v[u]);
+    }
+}
+
 __device__ __forceinline__ float wave_max(float v)
 {
 #pragma unroll

@@ -403,10 +403,12 @@ __global__ __launch_bounds__(512) void proj_bwd_lds_kernel(const float *__restri
     // ring to zero (finite stale values), dA block to LDS (zero beyond k and d)
     for (int e = tid * 4; e < BNST * BSTAGE; e += 512 * 4) *reinterpret_cast<f32x4 *>(&smem[e]) = f32x4{0, 0, 0, 0};
     const int kp = (k + 1) & ~1;
-    for (int e = tid; e < kp * 256; e += 512) {
-        const int j = e >> 8, c = e & 255, col = dbase + c;
-        sG[j * BLD + c] = (j < k && col < d) ? G[(size_t)j * d + col] : 0.f;
-    }
+    batched_for<8>(
+        tid, kp * 256, 512, [&](int e) { return G[(size_t)min(e >> 8, k - 1) * d + min(dbase + (e & 255), d - 1)]; },
+        [&](int e, float g) {
+            const int j = e >> 8, c = e & 255;
+            sG[j * BLD + c] = (j < k && dbase + c < d) ? g : 0.f;
+        });
     __syncthreads();
 
     const int npw = (BS * k + 255) / 256;  // 1 KB basis windows per stage
@@ -547,11 +549,16 @@ __device__ __forceinline__ void proj_bwd_rows(float *sG, const T *__restrict__ P
     const int nchunks = (k + BWD_KC - 1) / BWD_KC;
     auto stage = [&](int j0, int kc) {
         const int kc2 = (kc + 1) & ~1;
-        for (int e = threadIdx.x; e < kc2 * NT * 32; e += 256) {
-            const int jj = e / (NT * 32), cc = e - jj * (NT * 32);
-            const int col = dbase + cc;
-            sG[jj * LD + cc] = (jj < kc && col < d) ? G[(size_t)(j0 + jj) * d + col] : 0.f;
-        }
+        batched_for<8>(
+            threadIdx.x, kc2 * NT * 32, 256,
+            [&](int e) {
+                const int jj = e / (NT * 32), cc = e - jj * (NT * 32);
+                return G[(size_t)(j0 + min(jj, kc - 1)) * d + min(dbase + cc, d - 1)];
+            },
+            [&](int e, float g) {
+                const int jj = e / (NT * 32), cc = e - jj * (NT * 32);
+                sG[jj * LD + cc] = (jj < kc && dbase + cc < d) ? g : 0.f;
+            });
     };
     __syncthreads();  // sG may still be read by a previous call
     if (nchunks == 1) {

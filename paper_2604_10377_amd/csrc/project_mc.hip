@@ -397,15 +397,22 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict
 
     // dA^T parts for columns [dbase, dbase + 128), rows < 32 KS (zero past k and d)
     char *parts = reinterpret_cast<char *>(smem);
-    for (int e = tid; e < KS * 32 * BB_COLS; e += 512) {
-        const int jj = e / BB_COLS, c = e - jj * BB_COLS;
-        const float v = (jj < k && dbase + c < d) ? G[(size_t)jj * d + dbase + c] : 0.f;
-        uint32_t w[PD];
-        split_pack<PD>(v, 0.f, w);
+    batched_for<8>(
+        tid, KS * 32 * BB_COLS, 512,
+        [&](int e) {
+            const int jj = e / BB_COLS, c = e - jj * BB_COLS;
+            return G[(size_t)min(jj, k - 1) * d + min(dbase + c, d - 1)];
+        },
+        [&](int e, float g) {
+            const int jj = e / BB_COLS, c = e - jj * BB_COLS;
+            const float v = (jj < k && dbase + c < d) ? g : 0.f;
+            uint32_t w[PD];
+            split_pack<PD>(v, 0.f, w);
 #pragma unroll
-        for (int p = 0; p < PD; ++p)
-            *reinterpret_cast<uint16_t *>(parts + (size_t)p * BB_COLS * STRIDE + c * STRIDE + 2 * jj) = (uint16_t)w[p];
-    }
+            for (int p = 0; p < PD; ++p)
+                *reinterpret_cast<uint16_t *>(parts + (size_t)p * BB_COLS * STRIDE + c * STRIDE + 2 * jj) =
+                    (uint16_t)w[p];
+        });
     __syncthreads();
 
     const int ntile = (n + BB_VT - 1) / BB_VT;

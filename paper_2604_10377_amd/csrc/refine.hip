@@ -66,12 +66,17 @@ __global__ __launch_bounds__(256) void gram64_kernel(const float *__restrict__ A
     const float *Y = A + (size_t)p * kx * d;
     double acc = 0.0;
     for (int c0 = 0; c0 < d; c0 += 64) {
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int r = e >> 6, c = e & 63, col = c0 + c;
-            const int xr = I * 16 + r, yr = J * 16 + r;
-            sx[r][c] = (xr < rowsX && col < d) ? (double)X[(size_t)xr * d + col] : 0.0;
-            sy[r][c] = (yr < kx && col < d) ? (double)Y[(size_t)yr * d + col] : 0.0;
-        }
+        batched_for<4>(
+            threadIdx.x, 16 * 64, 256,
+            [&](int e) {
+                const int r = e >> 6, col = min(c0 + (e & 63), d - 1);
+                return float2{X[(size_t)min(I * 16 + r, rowsX - 1) * d + col], Y[(size_t)min(J * 16 + r, kx - 1) * d + col]};
+            },
+            [&](int e, float2 v) {
+                const int r = e >> 6, c = e & 63, col = c0 + c;
+                sx[r][c] = (I * 16 + r < rowsX && col < d) ? (double)v.x : 0.0;
+                sy[r][c] = (J * 16 + r < kx && col < d) ? (double)v.y : 0.0;
+            });
         __syncthreads();
 #pragma unroll 8
         for (int c = 0; c < 64; ++c) acc = fma(sx[ty][c], sy[tx][c], acc);
@@ -97,10 +102,9 @@ __global__ __launch_bounds__(256) void residual64_kernel(const float *__restrict
     const int p = blockIdx.x / rb, i0 = (blockIdx.x % rb) * 16;
     const int tid = threadIdx.x;
     const int nr = min(16, ky - i0);
-    for (int e = tid; e < 16 * kx; e += 256) {
-        const int r = e / kx, q = e - r * kx;
-        sC[e] = r < nr ? (double)C[((size_t)p * ky + i0 + r) * kx + q] : 0.0;
-    }
+    batched_for<8>(
+        tid, 16 * kx, 256, [&](int e) { return C[((size_t)p * ky + i0) * kx + min(e, nr * kx - 1)]; },
+        [&](int e, float v) { sC[e] = e < nr * kx ? (double)v : 0.0; });
     double inv_scale = 1.0;
     if (mask_kind == 1) {
         float mx = -INFINITY;
@@ -231,19 +235,22 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
     __shared__ int s_fail;
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float *Kp = K + (size_t)p * kx * kx;
-    for (int e = tid; e < kx * kx; e += 512) {
-        const int r = e / kx, c = e - r * kx;
-        if (c <= r) L[pk(r, c)] = Kp[e];
-    }
-    // ||K||_1 = max row sum of |K| (symmetric), one wave per row at a time
+    batched_for<8>(
+        tid, kx * kx, 512, [&](int e) { return Kp[e]; },
+        [&](int e, float v) {
+            const int r = e / kx, c = e - r * kx;
+            if (c <= r) L[pk(r, c)] = v;
+        });
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+    // ||K||_1 = max row sum of |K| (symmetric: the strict upper part of row r is column r of L), one wave per row
     float rmax = 0.f;
     for (int r = wave; r < kx; r += 8) {
         float s = 0.f;
-        for (int c = lane; c < kx; c += 64) s += fabsf(Kp[(size_t)r * kx + c]);
+        for (int c = lane; c < kx; c += 64) s += fabsf(c <= r ? L[pk(r, c)] : L[pk(c, r)]);
         rmax = fmaxf(rmax, wave_sum(s));
     }
     if (lane == 0) s_red[wave] = rmax;
-    if (tid == 0) s_fail = 0;
     __syncthreads();
     float knorm = s_red[0];
     for (int w = 1; w < 8; ++w) knorm = fmaxf(knorm, s_red[w]);
@@ -342,8 +349,12 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
     if (tid == 0 && cond_est) cond_est[p] = est;
     // ill-conditioned pair: use the float64-formed products (rounded) for the row factorisations
     if (threshold > 0.f && !(est <= threshold) && K64) {
-        for (int e = tid; e < kx * kx; e += 512) Kout[(size_t)p * kx * kx + e] = (float)K64[(size_t)p * kx * kx + e];
-        for (int e = tid; e < ky * kx; e += 512) Rout[(size_t)p * ky * kx + e] = (float)R64[(size_t)p * ky * kx + e];
+        batched_for<8>(
+            tid, kx * kx, 512, [&](int e) { return K64[(size_t)p * kx * kx + e]; },
+            [&](int e, double v) { Kout[(size_t)p * kx * kx + e] = (float)v; });
+        batched_for<8>(
+            tid, ky * kx, 512, [&](int e) { return R64[(size_t)p * ky * kx + e]; },
+            [&](int e, double v) { Rout[(size_t)p * ky * kx + e] = (float)v; });
     }
 }
 

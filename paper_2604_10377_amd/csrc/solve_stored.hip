@@ -56,8 +56,17 @@ __global__ __launch_bounds__(256) void trisolve_stored_kernel(const float *__res
     const float *Lp = Lin + (size_t)sys * (kx * (kx + 1) / 2);
     const int ng = (kx + SG - 1) / SG;
 
-    // validity of lambda and of the resolvent normaliser (as in the forward solve)
+    // every input load first (unconditional, clamped), then the validity of lambda and of the
+    // resolvent normaliser (as in the forward solve)
     const float lamv = lam[p];
+    float exv[NS], eyv[NS], y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int q = j + 64 * s;
+        exv[s] = ex[(size_t)p * kx + min(q, kx - 1)];
+        eyv[s] = ey[(size_t)p * ky + min(q, ky - 1)];
+        y[s] = rhs[(size_t)sys * kx + min(q, kx - 1)];
+    }
     int fail = 0;
     if (!(lamv >= 0.f) || !isfinite(lamv)) fail = -1;
     MaskParams mp;
@@ -66,20 +75,19 @@ __global__ __launch_bounds__(256) void trisolve_stored_kernel(const float *__res
     mp.inv_scale = 1.f;
     if (mask_kind == 1) {
         float mx = -INFINITY;
-        for (int q = j; q < kx; q += 64) mx = fmaxf(mx, ex[(size_t)p * kx + q]);
-        for (int q = j; q < ky; q += 64) mx = fmaxf(mx, ey[(size_t)p * ky + q]);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int q = j + 64 * s;
+            mx = fmaxf(mx, fmaxf(q < kx ? exv[s] : -INFINITY, q < ky ? eyv[s] : -INFINITY));
+        }
+        for (int q = j + 64 * NS; q < ky; q += 64) mx = fmaxf(mx, ey[(size_t)p * ky + q]);
         mx = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_max(mx))));
         if ((!(mx > 0.f) || !isfinite(mx)) && fail == 0) fail = -2;
         mp.inv_scale = 1.f / mx;
     }
     fail = __builtin_amdgcn_readfirstlane(fail);
-
-    float y[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int q = j + 64 * s;
-        y[s] = q < kx ? rhs[(size_t)sys * kx + q] : 0.f;
-    }
+    for (int s = 0; s < NS; ++s) y[s] = j + 64 * s < kx ? y[s] : 0.f;
 
     float ga[SG][NS], gb[SG][NS];
     // group g of columns into buf: element (q, c) for the lane's rows, address clamped into column c
@@ -166,7 +174,7 @@ __global__ __launch_bounds__(256) void trisolve_stored_kernel(const float *__res
             const size_t o = (size_t)sys * kx + q;
             const float v = fail == 0 ? y[s] : NAN;
             out[o] = addend ? addend[o] + v : v;  // addend: refinement correction c += delta (in place)
-            if (dlam_part) term += v * mask_entry(muy, ex[(size_t)p * kx + q], mp) * Cfwd[o];
+            if (dlam_part) term += v * mask_entry(muy, exv[s], mp) * Cfwd[o];
         }
     }
     if (info && j == 0) info[sys] = fail;
