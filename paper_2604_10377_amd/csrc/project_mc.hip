@@ -309,7 +309,18 @@ constexpr int BB_COLS = 128;   // columns per workgroup
 constexpr int BB_VT = 256;     // vertices per workgroup tile (8 waves x 32)
 
 __host__ __device__ constexpr int bwdmc_stride(int ks) { return ks * 64 + 16; }  // bytes per LDS row (k padded)
-__host__ __device__ constexpr size_t bwdmc_lds(int pd, int ks) { return (size_t)pd * BB_COLS * bwdmc_stride(ks); }
+__host__ __device__ constexpr size_t bwdmc_parts(int pd, int ks) { return (size_t)pd * BB_COLS * bwdmc_stride(ks); }
+// Store staging: a wave's 32 vertices x 32 columns (one M-tile pair) pass through LDS so that every
+// store instruction writes whole 128-byte lines (8 vertices x 32 columns) instead of the matrix-core
+// layout's 64-byte halves (16 vertices x 16 columns), which the memory system drains markedly slower.
+// Rows of 36 floats (144 bytes) keep both the writes and the reads free of bank conflicts.
+constexpr int BT_ROW = 36;
+constexpr size_t BT_BYTES = 8 * 32 * BT_ROW * 4;
+__host__ __device__ constexpr bool bwdmc_transpose(int pd, int ks) { return bwdmc_parts(pd, ks) + BT_BYTES <= 160 * 1024; }
+__host__ __device__ constexpr size_t bwdmc_lds(int pd, int ks)
+{
+    return bwdmc_parts(pd, ks) + (bwdmc_transpose(pd, ks) ? BT_BYTES : 0);
+}
 
 // x (two values per dword) as NP bf16 parts, each the rounding of what the previous parts left
 template <int NP>
@@ -379,7 +390,9 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict
                                                            float *__restrict__ dF)
 {
     constexpr int STRIDE = bwdmc_stride(KS);
+    constexpr bool TR = bwdmc_transpose(PD, KS);
     extern __shared__ __align__(16) float smem[];
+    float *tstage = reinterpret_cast<float *>(reinterpret_cast<char *>(smem) + bwdmc_parts(PD, KS));
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m16 = lane & 15, g4 = lane >> 4;
     const int bid = blockIdx.x;
@@ -439,19 +452,26 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict
             }
         }
     };
+    // Columns are produced 32 at a time (an M-tile pair) over all K steps, and stored right away, so
+    // the stores of one pair drain while the next pair's products run.  The basis operand parts of
+    // the whole tile are formed once.
+    const bool fullcols = vec && dbase + BB_COLS <= d;  // the common case: no column checks
     auto compute_store = [&](int vt, const RowSeg<T> (&cur)[KS][2], const float (&mv)[2]) {
-        f32x4 acc[8][2];
+        u32x4_t B[KS][2][PP];
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt)
+        for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4{0, 0, 0, 0};
+            for (int nt = 0; nt < 2; ++nt) seg_parts<PP>(cur[ks][nt], ks * 32 + 8 * g4, k, B[ks][nt]);
+        const int vrow = vt * BB_VT + wave * 32 + m16;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            u32x4_t B[2][PP];
+        for (int mp = 0; mp < 8; mp += 2) {
+            f32x4 acc[2][2];
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) seg_parts<PP>(cur[ks][nt], ks * 32 + 8 * g4, k, B[nt]);
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int mp = 0; mp < 8; mp += 2) {
+                for (int nt = 0; nt < 2; ++nt) acc[h][nt] = f32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
                 u32x4_t A[2][PD];
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
@@ -470,30 +490,53 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict
                             for (int h = 0; h < 2; ++h)
 #pragma unroll
                                 for (int nt = 0; nt < 2; ++nt)
-                                    acc[mp + h][nt] = mfma16x16x32bf16(A[h][jp], B[nt][i], acc[mp + h][nt]);
+                                    acc[h][nt] = mfma16x16x32bf16(A[h][jp], B[ks][nt][i], acc[h][nt]);
                         }
-                // keep the scheduler from hoisting every tile's LDS operands at once (register pressure)
-                __builtin_amdgcn_sched_barrier(0);
             }
-        }
-        // D layout: register r of lane (m16, g4) is column 4*g4 + r of the column tile, vertex m16
+            // D layout: register r of lane (m16, g4) is column 4*g4 + r of the column tile, vertex m16
+            if constexpr (TR) {
+                if (fullcols) {
+                    float *tw = tstage + wave * 32 * BT_ROW;
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            const int v = vt * BB_VT + wave * 32 + nt * 16 + m16;
-            if (v >= n) continue;
-            float *row = O + (size_t)v * d;
+                    for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-            for (int mt = 0; mt < 8; ++mt) {
-                const int col = dbase + mt * 16 + 4 * g4;
-                const f32x4 val = acc[mt][nt] * mv[nt];
-                if (vec) {
-                    if (col < d) *reinterpret_cast<f32x4 *>(row + col) = val;
-                } else {
+                        for (int h = 0; h < 2; ++h)
+                            *reinterpret_cast<f32x4 *>(tw + (nt * 16 + m16) * BT_ROW + h * 16 + 4 * g4) =
+                                acc[h][nt] * mv[nt];
+                    // LDS operations of one wave complete in order: the reads see these writes, and the
+                    // next pair's writes come after these reads
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (col + r < d) row[col + r] = val[r];
+                    for (int u = 0; u < 4; ++u) {
+                        const int vr = 8 * u + (lane >> 3);
+                        const f32x4 val = *reinterpret_cast<const f32x4 *>(tw + vr * BT_ROW + 4 * (lane & 7));
+                        const int vb = vt * BB_VT + wave * 32 + vr;
+                        if (vb < n) *reinterpret_cast<f32x4 *>(O + (size_t)vb * d + dbase + mp * 16 + 4 * (lane & 7)) = val;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    continue;
                 }
             }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const int v = vrow + nt * 16;
+                float *row = O + (size_t)min(v, n - 1) * d;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int col = dbase + (mp + h) * 16 + 4 * g4;
+                    const f32x4 val = acc[h][nt] * mv[nt];
+                    if (fullcols) {
+                        if (v < n) *reinterpret_cast<f32x4 *>(row + col) = val;
+                    } else if (vec) {
+                        if (v < n && col < d) *reinterpret_cast<f32x4 *>(row + col) = val;
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (v < n && col + r < d) row[col + r] = val[r];
+                    }
+                }
+            }
+            // keep the scheduler from hoisting the next pair's LDS operands above these stores
+            __builtin_amdgcn_sched_barrier(0);
         }
     };
     // The buffers rotate by unrolling (no register copies).  The prefetches are unconditional (the
@@ -824,7 +867,14 @@ static hipError_t dispatch_bwdmc(const T *phi, const float *mass, const float *d
     }
     const int dblocks = (int)((d + BB_COLS - 1) / BB_COLS);
     const int64_t ntile = (n + BB_VT - 1) / BB_VT;
-    const int per_cu = lds <= 80 * 1024 ? 2 : 1;
+    static int per_cu = 0;  // resident workgroups per CU (registers and LDS), queried once
+    if (per_cu == 0) {
+        int r = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, (const void *)proj_bwd_mc_kernel<T, PP, PD, KS>, 512,
+                                                         lds) != hipSuccess || r < 1)
+            r = 1;
+        per_cu = r;
+    }
     const int vsplit = bwdmc_vsplit(batch, dblocks, ntile, per_cu);
     const int ntasks = (int)(batch * vsplit);
     const unsigned grid = (unsigned)(8 * dblocks * ((ntasks + 7) / 8));
