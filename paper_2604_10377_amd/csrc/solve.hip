@@ -188,14 +188,25 @@ __device__ __forceinline__ float uniform(float v) { return __int_as_float(__buil
 // ---------------------------------------------------------------------------
 // One wave per row system; KMAX >= k_x is the register row length.
 //
-// Lane j holds row j of S_i (entries q <= j, the rest zero).  Step c of the
-// right-looking factorisation: the pivot comes from lane c, every lane scales
-// its column-c entry, the column is broadcast through LDS (all reads of a step
-// issued together) and each lane updates its row.  The forward substitution
-// L y = r rides along (y_c is final once column c is).  The back substitution
-// L^T c = y reads a register copy of column j of L (row j of L^T) staged
-// through LDS, so it needs only readlanes.  All control flow is wave-uniform.
+// Lane j holds row j of S_i (entries q <= j; entries above the diagonal are
+// never read).  The right-looking factorisation takes the columns four at a
+// time: within a block the pivots come from the diagonal lanes and the block's
+// own entries are updated with readlanes; then the four new columns are
+// broadcast through LDS in one round trip (one 16-byte row per lane) and each
+// lane applies the block's rank-4 update to the rest of its row, column by
+// column in order (the same roundings as one column at a time).  The forward
+// substitution L y = r rides along.  The factor is then staged in LDS as full
+// rows, from which the packed output is written with consecutive lanes on
+// consecutive elements and each lane takes column j of L (row j of L^T) for
+// the back substitution, which needs only readlanes.  All control flow is
+// wave-uniform; a failed pivot is recorded (LAPACK info) and the system's
+// outputs become NaN.
 // ---------------------------------------------------------------------------
+template <int KMAX> struct RowsolveLds {
+    static constexpr int KP = KMAX + 4;                    // staged factor row stride (floats)
+    static constexpr int PER_WAVE = 4 * KMAX + KMAX * KP + 3 * KMAX;  // block broadcast, staged factor, scalars
+};
+
 template <int KMAX, int MODE>
 __global__ __launch_bounds__(256) void rowsolve_kernel(
     const float *__restrict__ K, const float *__restrict__ Lin, const float *__restrict__ rhs,
@@ -204,13 +215,15 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     const float *__restrict__ Cfwd, float *__restrict__ dlam_part, const float *addend)
 {
     static_assert(KMAX % 4 == 0 && KMAX <= 64, "register row length");
-    // per wave: broadcast vector (KMAX) + rows of L packed (row r at r(r+1)/2); W = systems per workgroup
-    constexpr int PER_WAVE = KMAX + KMAX * (KMAX + 1) / 2;
+    constexpr int KP = RowsolveLds<KMAX>::KP;
     extern __shared__ __align__(16) float s_rs[];
     const int j = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int W = blockDim.x >> 6;
-    float *s_bcw = s_rs + w * PER_WAVE;
-    float *s_Lw = s_bcw + KMAX;
+    float *s_bcw = s_rs + w * RowsolveLds<KMAX>::PER_WAVE;  // [KMAX][4]: the block's columns, row by row
+    float *s_Lw = s_bcw + 4 * KMAX;                          // [KMAX][KP]: rows of L
+    // per-column scalars (1 / L_cc, y_c, c_c): lane 0 records them as the serial steps produce them,
+    // and each lane reads its own entry afterwards (no per-column lane masks)
+    float *s_inv = s_Lw + KMAX * KP, *s_y = s_inv + KMAX, *s_c = s_y + KMAX;
     const int rgroups = (ky + W - 1) / W;
     const int p = blockIdx.x / rgroups;
     const int i = (blockIdx.x % rgroups) * W + w;
@@ -226,6 +239,7 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     const float eyj = ey[(size_t)p * ky + min(j, ky - 1)];
     float sr[KMAX];
     if (MODE == RS_BWD_STORED) {
+        // packed column-major factor: for each q the lanes read consecutive addresses
         const float *Lp = Lin + ((size_t)p * ky + i) * T;
 #pragma unroll
         for (int q = 0; q < KMAX; ++q) {
@@ -233,9 +247,10 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
             sr[q] = Lp[packed_col(qc, kx) + jc - qc];
         }
     } else {
-        const float *Kp = K + (size_t)p * kx * kx + (size_t)jc * kx;
+        // K is symmetric: row j is read as column j, so for each q the lanes read consecutive addresses
+        const float *Kp = K + (size_t)p * kx * kx;
 #pragma unroll
-        for (int q = 0; q < KMAX; ++q) sr[q] = Kp[min(q, kx - 1)];
+        for (int q = 0; q < KMAX; ++q) sr[q] = Kp[min(q, kx - 1) * kx + jc];  // 32-bit offsets from one base
     }
     const float rin = rhs[((size_t)p * ky + i) * kx + jc];
 
@@ -257,91 +272,122 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     const float dval = (jok && fail == 0) ? mask_entry(muy, exj, mp) : 0.f;
     const float shift = lamv * dval;
 
-    // row j of S_i (lower part) or of the stored factor; the strict upper part is zero
+    // row j of S_i = K + lambda diag(D_i) (lower part), or of the stored factor; rows k_x <= j < KMAX
+    // are rows of the identity, so every loop below runs over all KMAX columns with no k_x checks
+    // (their pivots are 1, their solution entries 0, and they add nothing to the real rows)
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) sr[q] = (jok && q <= j) ? sr[q] : 0.f;
+    for (int q = 0; q < KMAX; ++q) {
+        const float v = (jok && q <= j) ? sr[q] : 0.f;
+        sr[q] = (q == j) ? (jok ? (MODE != RS_BWD_STORED ? v + shift : v) : 1.f) : v;
+    }
     float r = jok ? rin : 0.f;
-    float yv = 0.f, myinv = 0.f;
 
+    // Lanes j < c take garbage in column c (and in their entries above the diagonal); none of it is
+    // read: a lane's later use of column c is for rows below c, and y_j was recorded at step j.
     if (MODE != RS_BWD_STORED) {
-        float *bc = s_bcw;
 #pragma unroll
-        for (int c = 0; c < KMAX; ++c) {
-            if (c < kx && fail == 0) {
-                const float piv = uniform(readlane(sr[c], c) + readlane(shift, c));
-                if (!(piv > 0.f) || !isfinite(piv)) {
-                    fail = c + 1;
-                } else {
-                    const float inv = __builtin_amdgcn_rsqf(piv);
-                    const float l = (j > c) ? sr[c] * inv : ((j == c) ? piv * inv : 0.f);
+        for (int c0 = 0; c0 < KMAX; c0 += 4) {
+            if (c0 < kx) {  // blocks past k_x hold only identity rows
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int c = c0 + t;
+                    const float piv = uniform(readlane(sr[c], c));
+                    const bool bad = !(piv > 0.f) || !isfinite(piv);
+                    fail = (bad && fail == 0) ? c + 1 : fail;
+                    const float inv = uniform(__builtin_amdgcn_rsqf(piv));
+                    const float l = sr[c] * inv;  // lane c: sqrt(pivot)
                     sr[c] = l;
-                    if (j == c) myinv = inv;
-                    const float yc = readlane(r, c) * inv;  // forward substitution, step c
-                    if (j == c) yv = yc;
+                    const float yc = uniform(readlane(r, c) * inv);  // forward substitution, step c
+                    if (j == 0) {
+                        s_inv[c] = inv;
+                        s_y[c] = yc;
+                    }
                     r -= l * yc;
-                    if (j < KMAX) bc[j] = l;  // lanes >= KMAX hold zero rows
-                    __builtin_amdgcn_wave_barrier();
-                    constexpr int NQ = KMAX / 4;
-                    f32x4 lq[NQ];
 #pragma unroll
-                    for (int q4 = 0; q4 < NQ; ++q4)
-                        if (4 * q4 + 3 > c) lq[q4] = *reinterpret_cast<const f32x4 *>(&bc[4 * q4]);
-#pragma unroll
-                    for (int q4 = 0; q4 < NQ; ++q4)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (4 * q4 + e > c) sr[4 * q4 + e] -= l * lq[q4][e];
-                    __builtin_amdgcn_wave_barrier();
+                    for (int t2 = t + 1; t2 < 4; ++t2) sr[c0 + t2] -= l * readlane(l, c0 + t2);
                 }
+                if (j < KMAX)
+                    *reinterpret_cast<f32x4 *>(&s_bcw[4 * j]) = f32x4{sr[c0], sr[c0 + 1], sr[c0 + 2], sr[c0 + 3]};
+                __builtin_amdgcn_wave_barrier();
+                // rows of the block columns in groups of 8 (LDS reads of a group in flight together)
+#pragma unroll
+                for (int q0 = c0 + 4; q0 < KMAX; q0 += 8) {
+                    f32x4 lq[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (q0 + u < KMAX) lq[u] = *reinterpret_cast<const f32x4 *>(&s_bcw[4 * (q0 + u)]);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (q0 + u < KMAX) {
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) sr[q0 + u] -= sr[c0 + t] * lq[u][t];
+                        }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_sched_barrier(0);  // blocks are scheduled one at a time (register pressure)
             }
         }
     } else {
 #pragma unroll
         for (int c = 0; c < KMAX; ++c) {
-            if (c < kx && fail == 0) {
-                const float dg = uniform(readlane(sr[c], c));
-                if (!(dg > 0.f) || !isfinite(dg)) {
-                    fail = c + 1;
-                } else {
-                    const float inv = __builtin_amdgcn_rcpf(dg);
-                    if (j == c) myinv = inv;
-                    const float yc = readlane(r, c) * inv;
-                    if (j == c) yv = yc;
-                    r -= sr[c] * yc;
-                }
+            const float dg = uniform(readlane(sr[c], c));
+            const bool bad = !(dg > 0.f) || !isfinite(dg);
+            fail = (bad && fail == 0) ? c + 1 : fail;
+            const float inv = uniform(__builtin_amdgcn_rcpf(dg));
+            const float yc = uniform(readlane(r, c) * inv);
+            if (j == 0) {
+                s_inv[c] = inv;
+                s_y[c] = yc;
             }
+            r -= sr[c] * yc;  // lanes j <= c: final entries already recorded
         }
     }
+    fail = __builtin_amdgcn_readfirstlane(fail);
+
+    // stage the rows of L (entries above the diagonal are not read)
+    if (j < KMAX) {
+#pragma unroll
+        for (int q4 = 0; q4 < KMAX / 4; ++q4)
+            *reinterpret_cast<f32x4 *>(&s_Lw[j * KP + 4 * q4]) =
+                f32x4{sr[4 * q4], sr[4 * q4 + 1], sr[4 * q4 + 2], sr[4 * q4 + 3]};
+    }
+    __builtin_amdgcn_wave_barrier();
 
     if (MODE == RS_FWD && Lout) {
+        // packed column-major output, one store per column (lanes q <= j < k_x); the lane index is
+        // made opaque here so that the per-column lane masks are formed at the stores and not
+        // hoisted above the factorisation, where they would occupy scalar registers throughout
         float *Lp = Lout + ((size_t)p * ky + i) * T;
+        int jl = j;
+        asm volatile("" : "+v"(jl));
+        const bool lok = jl < kx;
 #pragma unroll
-        for (int q = 0; q < KMAX; ++q)
-            if (q < kx && jok && j >= q) Lp[packed_col(q, kx) + j - q] = fail == 0 ? sr[q] : NAN;
+        for (int q = 0; q < KMAX; ++q) {
+            if (q < kx) {
+                const int pc = packed_col(q, kx) - q;
+                if (lok && jl >= q) Lp[pc + jl] = fail == 0 ? sr[q] : NAN;
+            }
+        }
     }
 
     float cv = NAN;
     if (fail == 0) {
-        // stage the rows of L, then take column j of L into registers
-        float *Lr = s_Lw;
-        const int rowoff = j * (j + 1) / 2;
+        // column j of L: L[c][j] for c > j
+        const int jr = min(j, KMAX - 1);
 #pragma unroll
-        for (int q = 0; q < KMAX; ++q)
-            if (j < KMAX && q <= j) Lr[rowoff + q] = sr[q];
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int c = 0; c < KMAX; ++c) sr[c] = (c > j) ? Lr[c * (c + 1) / 2 + j] : 0.f;  // L[c][j]
-        __builtin_amdgcn_wave_barrier();
-        float y = yv;
-        cv = 0.f;
+        for (int c = 0; c < KMAX; ++c) sr[c] = (c > j) ? s_Lw[c * KP + jr] : 0.f;
+        const int jr2 = min(j, KMAX - 1);
+        float y = s_y[jr2];
+        const float myinv = s_inv[jr2];
 #pragma unroll
         for (int c = KMAX - 1; c >= 0; --c) {
-            if (c < kx) {
-                const float cc = readlane(y, c) * readlane(myinv, c);
-                if (j == c) cv = cc;
-                y -= sr[c] * cc;
-            }
+            const float cc = uniform(readlane(y, c) * readlane(myinv, c));
+            if (j == 0) s_c[c] = cc;
+            y -= sr[c] * cc;
         }
+        __builtin_amdgcn_wave_barrier();
+        cv = s_c[jr2];
     }
 
     if (jok) {
@@ -561,11 +607,20 @@ static void launch_rowsolve(const float *K, const float *Lin, const float *rhs, 
 {
     const int W = rowsolve_waves();
     const unsigned grid = (unsigned)(P * ((ky + W - 1) / W));
-    // dynamic LDS: W x (KM + KM(KM+1)/2) floats, at most 4 x 2144 floats (34 KB)
+    // dynamic LDS: W x (4 KM + KM (KM + 4)) floats, at most 4 x 4352 floats (68 KB)
 #define FMAP_RS(KM)                                                                                             \
-    hipLaunchKernelGGL((rowsolve_kernel<KM, MODE>), dim3(grid), dim3(64 * W),                                    \
-                       (size_t)W * (KM + KM * (KM + 1) / 2) * sizeof(float), st, K, Lin, rhs, ex, ey, lam, mask_kind, \
-                       gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part, addend)
+    do {                                                                                                        \
+        const size_t lds_ = (size_t)W * RowsolveLds<KM>::PER_WAVE * sizeof(float);                              \
+        static bool attr_ = false;                                                                              \
+        if (!attr_) {                                                                                           \
+            (void)hipFuncSetAttribute((const void *)rowsolve_kernel<KM, MODE>,                                  \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,                               \
+                                      (int)(4 * RowsolveLds<KM>::PER_WAVE * sizeof(float)));                     \
+            attr_ = true;                                                                                       \
+        }                                                                                                       \
+        hipLaunchKernelGGL((rowsolve_kernel<KM, MODE>), dim3(grid), dim3(64 * W), lds_, st, K, Lin, rhs, ex, ey,  \
+                           lam, mask_kind, gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part, addend);   \
+    } while (0)
     if (kx <= 8) FMAP_RS(8);
     else if (kx <= 16) FMAP_RS(16);
     else if (kx <= 24) FMAP_RS(24);
