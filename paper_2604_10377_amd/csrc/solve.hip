@@ -404,12 +404,12 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint products for one pair and one 64-column block of d:
+// Adjoint products for one pair and one CB-column block of d:
 //   W = V^T C + C^T V,  dA = V^T B - W A,  dB = V A.
 // V, C, W and the A, B column blocks are staged in LDS; matrix-core loops
 // read their operands in batches of GU steps.
 // ---------------------------------------------------------------------------
-template <int KM>
+template <int KM, int CB>
 __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ V, const float *__restrict__ C,
                                                       const float *__restrict__ A, const float *__restrict__ B,
                                                       int kx, int ky, int d, int dblocks,
@@ -417,19 +417,19 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
                                                       float *__restrict__ dA, float *__restrict__ dB)
 {
     __shared__ float sV[KM * KM], sC[KM * KM], sW[KM * KM];
-    __shared__ float sA[KM * 64], sB[KM * 64];
+    __shared__ float sA[KM * CB], sB[KM * CB];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, l32 = lane & 31;
     const int p = blockIdx.x / dblocks, db = blockIdx.x % dblocks;
-    const int d0 = db * 64;
-    const int dw = min(64, d - d0);
+    const int d0 = db * CB;
+    const int dw = min(CB, d - d0);
     const float *Vp = V + (size_t)p * ky * kx;
     const float *Cp = C + (size_t)p * ky * kx;
     const float *Ap = A + (size_t)p * kx * d;
     const float *Bp = B + (size_t)p * ky * d;
     // staging: every load of the workgroup's operands is issued before the first
     // LDS write (fixed counts, clamped addresses, masked at the write)
-    constexpr int NVC = (KM * KM + 255) / 256, NAB = KM * 64 / 256;
+    constexpr int NVC = (KM * KM + 255) / 256, NAB = KM * CB / 256;
     const int nvc = ky * kx;
     float rv[NVC], rc[NVC], ra[NAB], rb[NAB];
 #pragma unroll
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
 #pragma unroll
     for (int u = 0; u < NAB; ++u) {
         const int e = threadIdx.x + 256 * u;
-        const int rr = e >> 6, cc = min(e & 63, dw - 1);
+        const int rr = e / CB, cc = min(e % CB, dw - 1);
         ra[u] = Ap[(size_t)min(rr, kx - 1) * d + d0 + cc];
         rb[u] = Bp[(size_t)min(rr, ky - 1) * d + d0 + cc];
     }
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
 #pragma unroll
     for (int u = 0; u < NAB; ++u) {
         const int e = threadIdx.x + 256 * u;
-        const bool cin = (e & 63) < dw;
+        const bool cin = (e % CB) < dw;
         sA[e] = cin ? ra[u] : 0.f;
         sB[e] = cin ? rb[u] : 0.f;
     }
@@ -495,11 +495,12 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
     }
     __syncthreads();
 
-    const int nA = TI * 2, nB = TY * 2;
+    constexpr int NCB = CB / 32;  // 32-column tiles per block
+    const int nA = TI * NCB, nB = TY * NCB;
     for (int job = wave; job < nA + nB; job += 4) {
         f32x16 acc = zero16();
         if (job < nA) {
-            const int I = job >> 1, cblk = job & 1;
+            const int I = job / NCB, cblk = job % NCB;
             const int m = I * 32 + l32, cl = cblk * 32 + l32, col = d0 + cl;
             const bool mok = m < kx, cok = col < d;
             // half 0: (V^T B)[m][col] over t < ky; half 1: -(W A)[m][col] over t < kx (W symmetric)
@@ -515,7 +516,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
                     const int t = t0 + u;
                     const bool ok = t < tn;
                     a[u] = (mok && ok) ? sg * Xs[t * kx + m] : 0.f;
-                    b[u] = ok ? Ys[t * 64 + cl] : 0.f;
+                    b[u] = ok ? Ys[t * CB + cl] : 0.f;
                 }
 #pragma unroll
                 for (int u = 0; u < GU; ++u) acc = mfma32x32x2(a[u], b[u], acc);
@@ -527,7 +528,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
             }
         } else {
             const int jb = job - nA;
-            const int I = jb >> 1, cblk = jb & 1;
+            const int I = jb / NCB, cblk = jb % NCB;
             const int m = I * 32 + l32, cl = cblk * 32 + l32, col = d0 + cl;
             const bool mok = m < ky, cok = col < d;
             const int KH = (kx + 1) >> 1;
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
                     const int kk = half * KH + t0 + u;
                     const bool ok = (t0 + u < KH) && kk < kx;
                     a[u] = (mok && ok) ? sV[m * kx + kk] : 0.f;
-                    b[u] = ok ? sA[kk * 64 + cl] : 0.f;
+                    b[u] = ok ? sA[kk * CB + cl] : 0.f;
                 }
 #pragma unroll
                 for (int u = 0; u < GU; ++u) acc = mfma32x32x2(a[u], b[u], acc);
@@ -692,8 +693,9 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
                                   nullptr, info, C, dl, (float *)(base + L.tiles), st);
     }
     if (kx <= kSmallK && ky <= kSmallK) {
-        const int dblocks = (int)((d + 63) / 64);
-        hipLaunchKernelGGL((adjoint_kernel<kSmallK>), dim3((unsigned)(P * dblocks)), dim3(256), 0, st, V, C, A, B,
+        // 32-column blocks: twice the workgroups of 64-column ones (W is recomputed per block, k^3 flops)
+        const int dblocks = (int)((d + 31) / 32);
+        hipLaunchKernelGGL((adjoint_kernel<kSmallK, 32>), dim3((unsigned)(P * dblocks)), dim3(256), 0, st, V, C, A, B,
                            (int)kx, (int)ky, (int)d, dblocks, dl, dlam, dA, dB);
     } else {
         launch_adjoint_general(V, C, A, B, P, kx, ky, d, (float *)(base + L.W), dl, dlam, dA, dB, st);
