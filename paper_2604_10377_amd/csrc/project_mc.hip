@@ -774,6 +774,185 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__rest
         }
 }
 
+// ---------------------------------------------------------------------------
+// Forward projection, float32 emulated, k <= 64 (k even): features through
+// registers, basis x mass split once per workgroup.
+//
+// Workgroup = 4 waves over a 256-column block and all (padded) 64 basis rows;
+// wave w owns block columns 64w .. 64w + 63 (column 4m + t of the wave is
+// column m of tile t).  Stages of 32 vertices.  Each lane loads its 4 feature
+// columns of 8 vertices straight into registers (eight 16-byte loads), two
+// stages ahead, so the feature stream -- nearly all of the bytes -- needs no
+// LDS, no barrier and no LDS round trip.  The small basis tile (32 x k floats)
+// and the masses arrive by direct global->LDS loads in a ring of 3.  Per stage
+// wave w splits the basis x mass values of row tile w (rows 4R + w) into their
+// three bf16 parts and stores them in LDS in the matrix-core operand layout;
+// after a barrier every wave reads all four tiles.  The split work per wave is
+// then a quarter of the basis tile plus its own features, below the
+// matrix-core time of its 96 products.
+// ---------------------------------------------------------------------------
+constexpr int RNST = 3;  // basis stages in the LDS ring
+constexpr int RFL = 3;   // direct loads per wave per stage: 2 basis windows, 1 mass window
+constexpr int RFF = 8;   // feature loads per lane per stage
+constexpr int RSTAGE = 8 * 1024 + 256;  // basis windows + mass window
+constexpr int RPARTS = 3 * 4 * 64 * 16;  // split basis tile: [part][row tile][lane] of u32x4
+__host__ __device__ constexpr size_t x3r_lds() { return (size_t)RNST * RSTAGE + RPARTS; }
+
+__global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__restrict__ phi,
+                                                             const float *__restrict__ mass,
+                                                             const float *__restrict__ feat, int n, int k, int d,
+                                                             int nsplit, int dblocks, int ntiles,
+                                                             float *__restrict__ out)
+{
+    extern __shared__ __align__(16) float smem[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int m16 = lane & 15, g4 = lane >> 4;
+    const int bid = blockIdx.x;
+    const int xs = bid & 7, q = bid >> 3;
+    const int db = q % dblocks;
+    const int j = (q / dblocks) * 8 + xs;
+    if (j >= ntiles) return;  // whole workgroup, before any barrier
+    const int split = j % nsplit, s = j / nsplit;
+    const int dbase = db * 256;
+
+    const int nst_all = (n + XS - 1) / XS;
+    const int st0 = (int)(((long)split * nst_all) / nsplit), st1 = (int)(((long)(split + 1) * nst_all) / nsplit);
+    const int vbeg = st0 * XS, vend = min(n, st1 * XS);
+    const int nst = st1 - st0;
+
+    const float *P = phi + (size_t)s * n * k;
+    const float *F = feat + (size_t)s * n * d;
+    const float *Mv = mass + (size_t)s * n;
+
+    const int np = x3_np(k);
+    char *ring = reinterpret_cast<char *>(smem);
+    u32x4_t *parts = reinterpret_cast<u32x4_t *>(ring + RNST * RSTAGE);
+    for (int e = tid * 16; e < RNST * RSTAGE; e += 256 * 16) *reinterpret_cast<f32x4 *>(ring + e) = f32x4{0, 0, 0, 0};
+    __syncthreads();
+
+    // basis roles: windows wave and wave + 4 (clamped to the last), the mass window
+    const int pw0 = min(wave, np - 1), pw1 = min(wave + 4, np - 1);
+    const int poff0 = min(pw0 * 256 + 4 * lane, XS * k - 4), poff1 = min(pw1 * 256 + 4 * lane, XS * k - 4);
+    // feature role: columns fc .. fc + 3 (clamped into d; d % 4 == 0) of vertices 8 g4 .. + 7
+    const int cw = wave * 64 + 4 * m16;
+    const int fc = min(dbase + cw, d - 4);
+    auto issue = [&](int t, f32x4 (&fr)[RFF]) {
+        char *S = ring + (t % RNST) * RSTAGE;
+        const int v = vbeg + t * XS;
+        const int rows = min(XS, vend - v);  // a multiple of 4 (n % 4 == 0)
+        const float *Pv = P + (size_t)v * k;
+        const int pv = rows * k - 4;
+        dma16(Pv + min(poff0, pv), reinterpret_cast<float *>(S + pw0 * 1024));
+        dma16(Pv + min(poff1, pv), reinterpret_cast<float *>(S + pw1 * 1024));
+        __builtin_amdgcn_global_load_lds((glb_void_t *)(Mv + v + min(lane & 31, rows - 1)),
+                                         (lds_void_t *)(S + 8 * 1024), 4, 0, 0);
+#pragma unroll
+        for (int i = 0; i < RFF; ++i)
+            fr[i] = *reinterpret_cast<const f32x4 *>(F + (size_t)(v + min(8 * g4 + i, rows - 1)) * d + fc);
+    };
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[a][t] = f32x4{0, 0, 0, 0};
+    // split role: row tile a = wave, operand lane = lane: basis row 4 m16 + wave, vertices 8 g4 .. + 7
+    const int srow = 4 * m16 + wave;
+    const bool srow_ok = srow < k;
+    const int srow_c = min(srow, k - 1);
+
+    auto stage = [&](int t, const f32x4 (&fr)[RFF]) {
+        const char *S = ring + (t % RNST) * RSTAGE;
+        const float *Ps = reinterpret_cast<const float *>(S);
+        const float *Ms = reinterpret_cast<const float *>(S + 8 * 1024);
+        const int vrem = vend - (vbeg + t * XS);
+        {
+            const f32x4 m0 = *reinterpret_cast<const f32x4 *>(Ms + 8 * g4);
+            const f32x4 m1 = *reinterpret_cast<const f32x4 *>(Ms + 8 * g4 + 4);
+            const float mv[8] = {m0[0], m0[1], m0[2], m0[3], m1[0], m1[1], m1[2], m1[3]};
+            float x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float pv = Ps[(8 * g4 + i) * k + srow_c];
+                x[i] = (srow_ok && 8 * g4 + i < vrem) ? pv * mv[i] : 0.f;
+            }
+            uint32_t w[4][3];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) split_pack<3>(x[2 * jj], x[2 * jj + 1], w[jj]);
+#pragma unroll
+            for (int p = 0; p < 3; ++p) parts[(p * 4 + wave) * 64 + lane] = u32x4_t{w[0][p], w[1][p], w[2][p], w[3][p]};
+        }
+        lds_barrier();
+        u32x4_t A[4][3];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) A[a][p] = parts[(p * 4 + a) * 64 + lane];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            u32x4_t B[3];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                uint32_t w[3];
+                split_pack<3>(fr[2 * jj][tt], fr[2 * jj + 1][tt], w);
+#pragma unroll
+                for (int p = 0; p < 3; ++p) B[p][jj] = w[p];
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int jp = 0; jp < 3; ++jp)
+                    if (i + jp <= 2) {
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) acc[a][tt] = mfma16x16x32bf16(A[a][i], B[jp], acc[a][tt]);
+                    }
+        }
+    };
+
+    // Per iteration t: wait for stage t (stage t + 1 may stay in flight), barrier (stage t visible;
+    // every wave done with stage t - 1, so its ring slot, the split buffer and its feature registers
+    // are free), issue stage t + 2 into them, split, barrier, products.  The three feature buffers
+    // rotate by unrolling; prefetches past the chunk reload its last stage (the same bytes into the
+    // same places), and every load has landed before the workgroup ends (its LDS is then reused).
+    f32x4 f0[RFF], f1[RFF], f2[RFF];
+    constexpr int VPS = RFL + RFF;  // vector-memory operations per stage
+    if (nst <= 0) return;
+    issue(0, f0);
+    issue(min(1, nst - 1), f1);
+    for (int t = 0; t < nst; t += 3) {
+        wait_vmcnt<VPS>();
+        lds_barrier();
+        issue(min(t + 2, nst - 1), f2);
+        stage(t, f0);
+        if (t + 1 >= nst) break;
+        wait_vmcnt<VPS>();
+        lds_barrier();
+        issue(min(t + 3, nst - 1), f0);
+        stage(t + 1, f1);
+        if (t + 2 >= nst) break;
+        wait_vmcnt<VPS>();
+        lds_barrier();
+        issue(min(t + 4, nst - 1), f1);
+        stage(t + 2, f2);
+    }
+    wait_vmcnt<0>();
+
+    // lane (m16, g4), register r: matrix-core row 4*g4 + r -> basis row 4(4*g4 + r) + a; column m16 of
+    // tile tt -> block column 64 wave + 4 m16 + tt
+    float *O = out + (size_t)j * k * d;
+    const int col = dbase + cw;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int row = 16 * g4 + 4 * r + a;
+            if (row >= k || col >= d) continue;
+            const f32x4 v = f32x4{acc[a][0][r], acc[a][1][r], acc[a][2][r], acc[a][3][r]};
+            *reinterpret_cast<f32x4 *>(O + (size_t)row * d + col) = v;  // d % 4 == 0: all 4 columns exist
+        }
+}
+
 bool f32_split_fwd_shape_ok(int64_t n, int64_t k, int64_t d)
 {
     const bool kok = (k >= 4 && k <= 64 && k % 2 == 0) || (k > 64 && k <= kMaxK && k % 4 == 0);
@@ -812,12 +991,23 @@ static hipError_t dispatch_x3(const float *phi, const float *mass, const float *
     return hipGetLastError();
 }
 
+static hipError_t dispatch_x3r(const float *phi, const float *mass, const float *feat, int64_t batch, int64_t n,
+                               int64_t k, int64_t d, int ns, float *out, hipStream_t st)
+{
+    const int dblocks = (int)((d + 255) / 256);
+    const int ntiles = (int)(batch * ns);
+    const unsigned grid = (unsigned)(8 * dblocks * ((ntiles + 7) / 8));
+    hipLaunchKernelGGL(proj_fwd_x3r_kernel, dim3(grid), dim3(256), x3r_lds(), st, phi, mass, feat, (int)n, (int)k,
+                       (int)d, ns, dblocks, ntiles, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_project_f32_split(const float *phi, const float *mass, const float *feat, int64_t batch, int64_t n,
                                     int64_t k, int64_t d, float *A, void *ws, hipStream_t st)
 {
     const int ns = f32_split_fwd_nsplit(batch, n, k, d);
     float *out = ns > 1 ? (float *)ws : A;
-    hipError_t e = k <= 64 ? dispatch_x3<false>(phi, mass, feat, batch, n, k, d, ns, out, st)
+    hipError_t e = k <= 64 ? dispatch_x3r(phi, mass, feat, batch, n, k, d, ns, out, st)
                            : dispatch_x3<true>(phi, mass, feat, batch, n, k, d, ns, out, st);
     if (e != hipSuccess || ns <= 1) return e;
     return launch_reduce(out, ns, batch, k, d, A, st);
