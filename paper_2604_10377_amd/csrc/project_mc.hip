@@ -569,216 +569,22 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict
     }
 }
 
+constexpr int XS = 32;  // vertices per stage (one matrix-core K step)
+
+__host__ __device__ constexpr int x3_np(int k) { return (k + 7) / 8; }  // 1 KB basis windows (32 rows x k floats)
+
 // ---------------------------------------------------------------------------
 // Forward projection with float32 basis and features on the bf16 matrix cores:
 // both operands split into three bf16 parts, six products kept (float32 level,
-// as in the backward above), for k <= 64.
+// as in the backward above).  Features through registers, basis x mass split
+// once per workgroup.
 //
-// Workgroup = 4 waves; a wave owns all 64 (padded) basis rows x 64 feature
-// columns, so a workgroup covers a 256-column block.  Stages of 32 vertices
-// (one K step) arrive by direct global->LDS loads in a ring of 2 (80 KB, two
-// workgroups per CU), the next stage in flight during the current one.  Per
-// stage a lane reads 4 basis rows (two ds_read_b64: rows are only 8-byte
-// aligned for k = 50) and 4 feature columns (one ds_read_b128) of each of its
-// 8 vertices; the three-way split packs two vertices per register, which is
-// the transpose.  Basis row 4R + a of the slab is matrix-core row R of tile a,
-// feature column 4N + t of the wave's 64 is column N of tile t.
-// ---------------------------------------------------------------------------
-constexpr int XS = 32;      // vertices per stage
-constexpr int XNST = 2;     // stages in the ring
-constexpr int XFL = 11;     // loads per wave per stage: 8 feature rows, 2 basis windows, 1 mass window
-
-__host__ __device__ constexpr int x3_np(int k) { return (k + 7) / 8; }  // 1 KB basis windows (32 rows x k floats)
-__host__ __device__ constexpr int x3_stage_bytes(int k) { return (32 + x3_np(k)) * 1024 + 256; }
-
-// SLICED (k > 64, k % 4 == 0): the workgroup owns basis rows [64 kb, 64 kb + 64); a stage holds that
-// 64-float slice of each vertex row (8 windows of 4 vertices).  The row blocks and column blocks of
-// one vertex chunk take consecutive ids on one XCD, so the feature tile they all read comes from
-// HBM once and from that XCD's L2 afterwards.
-template <bool SLICED>
-__global__ __launch_bounds__(256, 2) void proj_fwd_x3_kernel(const float *__restrict__ phi,
-                                                           const float *__restrict__ mass,
-                                                           const float *__restrict__ feat, int n, int k, int d,
-                                                           int nsplit, int dblocks, int kblocks, int ntiles,
-                                                           float *__restrict__ out)
-{
-    extern __shared__ __align__(16) float smem[];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int m16 = lane & 15, g4 = lane >> 4;
-    const int bid = blockIdx.x;
-    const int xs = bid & 7, q = bid >> 3;
-    const int dk = dblocks * kblocks;
-    const int db = (q % dk) % dblocks, kb = (q % dk) / dblocks;
-    const int j = (q / dk) * 8 + xs;
-    if (j >= ntiles) return;  // whole workgroup, before any barrier
-    const int split = j % nsplit, s = j / nsplit;
-    const int dbase = db * 256;
-    const int kbase = SLICED ? 64 * kb : 0;
-    const int kvalid = SLICED ? min(64, k - kbase) : k;  // basis rows of this block (even, >= 4)
-    const int pstride = SLICED ? 64 : k;                 // LDS floats per vertex row of the basis tile
-
-    const int nst_all = (n + XS - 1) / XS;
-    const int st0 = (int)(((long)split * nst_all) / nsplit), st1 = (int)(((long)(split + 1) * nst_all) / nsplit);
-    const int vbeg = st0 * XS, vend = min(n, st1 * XS);
-    const int nst = st1 - st0;
-
-    const float *P = phi + (size_t)s * n * k;
-    const float *F = feat + (size_t)s * n * d;
-    const float *Mv = mass + (size_t)s * n;
-
-    const int np = SLICED ? 8 : x3_np(k);
-    const int stage_bytes = (32 + np) * 1024 + 256;  // [feature rows 32 KB][basis np KB][mass 256 B]
-    char *ring = reinterpret_cast<char *>(smem);
-    for (int e = tid * 16; e < XNST * stage_bytes; e += 256 * 16)
-        *reinterpret_cast<f32x4 *>(ring + e) = f32x4{0, 0, 0, 0};
-    __syncthreads();
-
-    // Load roles, the same count (XFL = 11) for every wave and stage: feature rows 8*wave .. +7, basis
-    // windows wave and wave + 4 (clamped to the last window), one mass window.  Full stages use
-    // per-lane offsets fixed at entry plus a uniform base; only the last stage of a chunk, which
-    // may hold fewer rows, clamps row indices.
-    const int fcol = min(dbase + 4 * lane, d - 4);  // feature column of this lane (d % 4 == 0)
-    const int pw0 = min(wave, np - 1), pw1 = min(wave + 4, np - 1);
-    // basis offsets (floats from the stage's first vertex row): contiguous windows of the 32 x k tile,
-    // or, sliced, vertex 4w + lane/16 and the 4 floats at column 64 kb + 4 (lane % 16) (clamped to k - 4)
-    const int scol = min(kbase + 4 * (lane & 15), k - 4);
-    const int poff0 = SLICED ? (4 * pw0 + (lane >> 4)) * k + scol : min(pw0 * 256 + 4 * lane, XS * k - 4);
-    const int poff1 = SLICED ? (4 * pw1 + (lane >> 4)) * k + scol : min(pw1 * 256 + 4 * lane, XS * k - 4);
-    auto issue = [&](int t) {
-        char *S = ring + (t % XNST) * stage_bytes;
-        const int v = vbeg + t * XS;
-        const int rows = min(XS, vend - v);  // a multiple of 4 (n % 4 == 0)
-        if (rows == XS) {
-            const float *Fv = F + (size_t)(v + 8 * wave) * d + fcol;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) dma16(Fv + (size_t)i * d, reinterpret_cast<float *>(S + (8 * wave + i) * 1024));
-            const float *Pv = P + (size_t)v * k;
-            dma16(Pv + poff0, reinterpret_cast<float *>(S + (32 + pw0) * 1024));
-            dma16(Pv + poff1, reinterpret_cast<float *>(S + (32 + pw1) * 1024));
-            __builtin_amdgcn_global_load_lds((glb_void_t *)(Mv + v + (lane & 31)), (lds_void_t *)(S + (32 + np) * 1024),
-                                             4, 0, 0);
-        } else {
-            const int pvalid = rows * k;  // a multiple of 4
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int r = min(8 * wave + i, rows - 1);
-                dma16(F + (size_t)(v + r) * d + fcol, reinterpret_cast<float *>(S + (8 * wave + i) * 1024));
-            }
-            const float *Pv = P + (size_t)v * k;
-            if (SLICED) {  // vertices past the stage's rows read the last row
-                const int r0 = min(4 * pw0 + (lane >> 4), rows - 1), r1 = min(4 * pw1 + (lane >> 4), rows - 1);
-                dma16(Pv + (size_t)r0 * k + scol, reinterpret_cast<float *>(S + (32 + pw0) * 1024));
-                dma16(Pv + (size_t)r1 * k + scol, reinterpret_cast<float *>(S + (32 + pw1) * 1024));
-            } else {
-                dma16(Pv + min(poff0, pvalid - 4), reinterpret_cast<float *>(S + (32 + pw0) * 1024));
-                dma16(Pv + min(poff1, pvalid - 4), reinterpret_cast<float *>(S + (32 + pw1) * 1024));
-            }
-            __builtin_amdgcn_global_load_lds((glb_void_t *)(Mv + v + min(lane, rows - 1)),
-                                             (lds_void_t *)(S + (32 + np) * 1024), 4, 0, 0);
-        }
-    };
-
-    f32x4 acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[a][t] = f32x4{0, 0, 0, 0};
-    // rows 4*m16 .. +3 as two pairs, each clamped into the row on its own (k even): a pair past k
-    // reads the last pair and its results are dropped, while rows below k keep their own data
-    const int r01 = min(4 * m16, kvalid - 2), r23 = min(4 * m16 + 2, kvalid - 2);
-    const int cw = wave * 64 + 4 * m16;  // this lane's 4 feature columns within the block
-
-    if (nst > 0) issue(0);
-    for (int t = 0; t < nst; ++t) {
-        if (t + 1 < nst) {
-            issue(t + 1);
-            wait_vmcnt<XFL>();
-        } else {
-            wait_vmcnt<0>();
-        }
-        lds_barrier();
-        const char *S = ring + (t % XNST) * stage_bytes;
-        const float *Fs = reinterpret_cast<const float *>(S);
-        const float *Ps = reinterpret_cast<const float *>(S + 32 * 1024);
-        const float *Ms = reinterpret_cast<const float *>(S + (32 + np) * 1024);
-        const int vrem = vend - (vbeg + t * XS);
-
-        const f32x4 m0 = *reinterpret_cast<const f32x4 *>(Ms + 8 * g4);
-        const f32x4 m1 = *reinterpret_cast<const f32x4 *>(Ms + 8 * g4 + 4);
-        float mv[8] = {m0[0], m0[1], m0[2], m0[3], m1[0], m1[1], m1[2], m1[3]};
-#pragma unroll
-        for (int i = 0; i < 8; ++i) mv[i] = (8 * g4 + i < vrem) ? mv[i] : 0.f;
-
-        // basis x mass, rows r4..r4+3 of vertices 8*g4..+7, as three bf16 parts per tile
-        u32x4_t A[4][3];
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            float x[2][4];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const float *row = Ps + (8 * g4 + 2 * jj + h) * pstride;
-                const float2 lo = *reinterpret_cast<const float2 *>(row + r01);
-                const float2 hi = *reinterpret_cast<const float2 *>(row + r23);
-                const float m = mv[2 * jj + h];
-                x[h][0] = lo.x * m;
-                x[h][1] = lo.y * m;
-                x[h][2] = hi.x * m;
-                x[h][3] = hi.y * m;
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                uint32_t w[3];
-                split_pack<3>(x[0][a], x[1][a], w);
-#pragma unroll
-                for (int p = 0; p < 3; ++p) A[a][p][jj] = w[p];
-            }
-        }
-        // feature columns cw..cw+3 of the same vertices
-        f32x4 y[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) y[i] = *reinterpret_cast<const f32x4 *>(Fs + (8 * g4 + i) * 256 + cw);
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-            u32x4_t B[3];
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                uint32_t w[3];
-                split_pack<3>(y[2 * jj][tt], y[2 * jj + 1][tt], w);
-#pragma unroll
-                for (int p = 0; p < 3; ++p) B[p][jj] = w[p];
-            }
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int jp = 0; jp < 3; ++jp)
-                    if (i + jp <= 2) {
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) acc[a][tt] = mfma16x16x32bf16(A[a][i], B[jp], acc[a][tt]);
-                    }
-        }
-        lds_barrier();  // the slot is refilled by the next iteration's issue
-    }
-
-    // lane (m16, g4), register r: matrix-core row 4*g4 + r -> basis row 4(4*g4 + r) + a; column m16 -> 4*m16 + tt
-    float *O = out + (size_t)j * k * d;
-    const int col = dbase + cw;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int row = kbase + 16 * g4 + 4 * r + a;
-            if (row >= k || col >= d) continue;
-            const f32x4 v = f32x4{acc[a][0][r], acc[a][1][r], acc[a][2][r], acc[a][3][r]};
-            *reinterpret_cast<f32x4 *>(O + (size_t)row * d + col) = v;  // d % 4 == 0: all 4 columns exist
-        }
-}
-
-// ---------------------------------------------------------------------------
-// Forward projection, float32 emulated, k <= 64 (k even): features through
-// registers, basis x mass split once per workgroup.
-//
-// Workgroup = 4 waves over a 256-column block and all (padded) 64 basis rows;
+// Workgroup = 4 waves over a 256-column block and 64 (padded) basis rows: all
+// of them for k <= 64 (k even), or, SLICED (k > 64, k % 4 == 0), the slice
+// [64 kb, 64 kb + 64), each stage then holding that 64-float slice of every
+// vertex row (8 windows of 4 vertices).  The row blocks and column blocks of
+// one vertex chunk take consecutive ids on one XCD, so the feature tile they
+// all read comes from HBM once and from that XCD's L2 afterwards.  Within a block:
 // wave w owns block columns 64w .. 64w + 63 (column 4m + t of the wave is
 // column m of tile t).  Stages of 32 vertices.  Each lane loads its 4 feature
 // columns of 8 vertices straight into registers (eight 16-byte loads), two
@@ -798,10 +604,11 @@ constexpr int RSTAGE = 8 * 1024 + 256;  // basis windows + mass window
 constexpr int RPARTS = 3 * 4 * 64 * 16;  // split basis tile: [part][row tile][lane] of u32x4
 __host__ __device__ constexpr size_t x3r_lds() { return (size_t)RNST * RSTAGE + RPARTS; }
 
+template <bool SLICED>
 __global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__restrict__ phi,
                                                              const float *__restrict__ mass,
                                                              const float *__restrict__ feat, int n, int k, int d,
-                                                             int nsplit, int dblocks, int ntiles,
+                                                             int nsplit, int dblocks, int kblocks, int ntiles,
                                                              float *__restrict__ out)
 {
     extern __shared__ __align__(16) float smem[];
@@ -810,11 +617,15 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__res
     const int m16 = lane & 15, g4 = lane >> 4;
     const int bid = blockIdx.x;
     const int xs = bid & 7, q = bid >> 3;
-    const int db = q % dblocks;
-    const int j = (q / dblocks) * 8 + xs;
+    const int dk = dblocks * kblocks;
+    const int db = (q % dk) % dblocks, kb = (q % dk) / dblocks;
+    const int j = (q / dk) * 8 + xs;
     if (j >= ntiles) return;  // whole workgroup, before any barrier
     const int split = j % nsplit, s = j / nsplit;
     const int dbase = db * 256;
+    const int kbase = SLICED ? 64 * kb : 0;
+    const int kvalid = SLICED ? min(64, k - kbase) : k;  // basis rows of this block
+    const int pstride = SLICED ? 64 : k;                 // LDS floats per vertex row of the basis tile
 
     const int nst_all = (n + XS - 1) / XS;
     const int st0 = (int)(((long)split * nst_all) / nsplit), st1 = (int)(((long)(split + 1) * nst_all) / nsplit);
@@ -825,14 +636,17 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__res
     const float *F = feat + (size_t)s * n * d;
     const float *Mv = mass + (size_t)s * n;
 
-    const int np = x3_np(k);
+    const int np = SLICED ? 8 : x3_np(k);
     char *ring = reinterpret_cast<char *>(smem);
     u32x4_t *parts = reinterpret_cast<u32x4_t *>(ring + RNST * RSTAGE);
     for (int e = tid * 16; e < RNST * RSTAGE; e += 256 * 16) *reinterpret_cast<f32x4 *>(ring + e) = f32x4{0, 0, 0, 0};
     __syncthreads();
 
-    // basis roles: windows wave and wave + 4 (clamped to the last), the mass window
+    // basis roles: windows wave and wave + 4 (clamped to the last), the mass window.  A window is
+    // 256 contiguous floats of the 32 x k tile or, sliced, vertices 4w .. 4w + 3 of the slice with
+    // lane l taking the 4 floats at column 64 kb + 4 (l % 16) (clamped to k - 4) of vertex 4w + l/16
     const int pw0 = min(wave, np - 1), pw1 = min(wave + 4, np - 1);
+    const int scol = min(kbase + 4 * (lane & 15), k - 4);
     const int poff0 = min(pw0 * 256 + 4 * lane, XS * k - 4), poff1 = min(pw1 * 256 + 4 * lane, XS * k - 4);
     // feature role: columns fc .. fc + 3 (clamped into d; d % 4 == 0) of vertices 8 g4 .. + 7
     const int cw = wave * 64 + 4 * m16;
@@ -842,9 +656,15 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__res
         const int v = vbeg + t * XS;
         const int rows = min(XS, vend - v);  // a multiple of 4 (n % 4 == 0)
         const float *Pv = P + (size_t)v * k;
-        const int pv = rows * k - 4;
-        dma16(Pv + min(poff0, pv), reinterpret_cast<float *>(S + pw0 * 1024));
-        dma16(Pv + min(poff1, pv), reinterpret_cast<float *>(S + pw1 * 1024));
+        if (SLICED) {  // vertices past the stage's rows read the last row
+            const int r0 = min(4 * pw0 + (lane >> 4), rows - 1), r1 = min(4 * pw1 + (lane >> 4), rows - 1);
+            dma16(Pv + (size_t)r0 * k + scol, reinterpret_cast<float *>(S + pw0 * 1024));
+            dma16(Pv + (size_t)r1 * k + scol, reinterpret_cast<float *>(S + pw1 * 1024));
+        } else {
+            const int pv = rows * k - 4;
+            dma16(Pv + min(poff0, pv), reinterpret_cast<float *>(S + pw0 * 1024));
+            dma16(Pv + min(poff1, pv), reinterpret_cast<float *>(S + pw1 * 1024));
+        }
         __builtin_amdgcn_global_load_lds((glb_void_t *)(Mv + v + min(lane & 31, rows - 1)),
                                          (lds_void_t *)(S + 8 * 1024), 4, 0, 0);
 #pragma unroll
@@ -859,8 +679,8 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__res
         for (int t = 0; t < 4; ++t) acc[a][t] = f32x4{0, 0, 0, 0};
     // split role: row tile a = wave, operand lane = lane: basis row 4 m16 + wave, vertices 8 g4 .. + 7
     const int srow = 4 * m16 + wave;
-    const bool srow_ok = srow < k;
-    const int srow_c = min(srow, k - 1);
+    const bool srow_ok = srow < kvalid;
+    const int srow_c = min(srow, kvalid - 1);
 
     auto stage = [&](int t, const f32x4 (&fr)[RFF]) {
         const char *S = ring + (t % RNST) * RSTAGE;
@@ -874,7 +694,7 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__res
             float x[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const float pv = Ps[(8 * g4 + i) * k + srow_c];
+                const float pv = Ps[(8 * g4 + i) * pstride + srow_c];
                 x[i] = (srow_ok && 8 * g4 + i < vrem) ? pv * mv[i] : 0.f;
             }
             uint32_t w[4][3];
@@ -946,7 +766,7 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__res
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            const int row = 16 * g4 + 4 * r + a;
+            const int row = kbase + 16 * g4 + 4 * r + a;
             if (row >= k || col >= d) continue;
             const f32x4 v = f32x4{acc[a][0][r], acc[a][1][r], acc[a][2][r], acc[a][3][r]};
             *reinterpret_cast<f32x4 *>(O + (size_t)row * d + col) = v;  // d % 4 == 0: all 4 columns exist
@@ -972,33 +792,15 @@ int f32_split_fwd_nsplit(int64_t batch, int64_t n, int64_t k, int64_t d)
 }
 
 template <bool SLICED>
-static hipError_t dispatch_x3(const float *phi, const float *mass, const float *feat, int64_t batch, int64_t n,
-                              int64_t k, int64_t d, int ns, float *out, hipStream_t st)
-{
-    const int kblocks = x3_kblocks(k);
-    const size_t lds = (size_t)XNST * ((32 + (SLICED ? 8 : x3_np((int)k))) * 1024 + 256);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)proj_fwd_x3_kernel<SLICED>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)((size_t)XNST * x3_stage_bytes(64)));
-        attr_set = true;
-    }
-    const int dblocks = (int)((d + 255) / 256);
-    const int ntiles = (int)(batch * ns);
-    const unsigned grid = (unsigned)(8 * dblocks * kblocks * ((ntiles + 7) / 8));
-    hipLaunchKernelGGL((proj_fwd_x3_kernel<SLICED>), dim3(grid), dim3(256), lds, st, phi, mass, feat, (int)n, (int)k,
-                       (int)d, ns, dblocks, kblocks, ntiles, out);
-    return hipGetLastError();
-}
-
 static hipError_t dispatch_x3r(const float *phi, const float *mass, const float *feat, int64_t batch, int64_t n,
                                int64_t k, int64_t d, int ns, float *out, hipStream_t st)
 {
     const int dblocks = (int)((d + 255) / 256);
+    const int kblocks = x3_kblocks(k);
     const int ntiles = (int)(batch * ns);
-    const unsigned grid = (unsigned)(8 * dblocks * ((ntiles + 7) / 8));
-    hipLaunchKernelGGL(proj_fwd_x3r_kernel, dim3(grid), dim3(256), x3r_lds(), st, phi, mass, feat, (int)n, (int)k,
-                       (int)d, ns, dblocks, ntiles, out);
+    const unsigned grid = (unsigned)(8 * dblocks * kblocks * ((ntiles + 7) / 8));
+    hipLaunchKernelGGL((proj_fwd_x3r_kernel<SLICED>), dim3(grid), dim3(256), x3r_lds(), st, phi, mass, feat, (int)n,
+                       (int)k, (int)d, ns, dblocks, kblocks, ntiles, out);
     return hipGetLastError();
 }
 
@@ -1007,8 +809,8 @@ hipError_t launch_project_f32_split(const float *phi, const float *mass, const f
 {
     const int ns = f32_split_fwd_nsplit(batch, n, k, d);
     float *out = ns > 1 ? (float *)ws : A;
-    hipError_t e = k <= 64 ? dispatch_x3r(phi, mass, feat, batch, n, k, d, ns, out, st)
-                           : dispatch_x3<true>(phi, mass, feat, batch, n, k, d, ns, out, st);
+    hipError_t e = k <= 64 ? dispatch_x3r<false>(phi, mass, feat, batch, n, k, d, ns, out, st)
+                           : dispatch_x3r<true>(phi, mass, feat, batch, n, k, d, ns, out, st);
     if (e != hipSuccess || ns <= 1) return e;
     return launch_reduce(out, ns, batch, k, d, A, st);
 }
