@@ -49,6 +49,10 @@ hipError_t launch_project_f32_split(const float *phi, const float *mass, const f
                                     int64_t k, int64_t d, float *A, void *ws, hipStream_t st);
 // float32 backward projection on the bf16 matrix cores, operands split into three bf16 parts (k even, k <= 64).
 bool f32_split_bwd_shape_ok(int64_t n, int64_t k, int64_t d);
+// float32 backward for 64 < k <= kMaxK (k even), 64-column blocks with every k slot's dA^T parts in LDS
+bool f32k_bwd_shape_ok(int64_t n, int64_t k, int64_t d);
+hipError_t launch_project_backward_f32k(const float *phi, const float *mass, const float *dA, int64_t batch,
+                                        int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st);
 hipError_t launch_project_backward_f32_split(const float *phi, const float *mass, const float *dA, int64_t batch,
                                              int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st);
 hipError_t launch_project_bf16(const uint16_t *phi, const float *mass, const uint16_t *feat, int64_t batch, int64_t n,

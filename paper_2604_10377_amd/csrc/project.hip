@@ -895,6 +895,8 @@ hipError_t launch_project_backward(const void *phi, const float *mass, int32_t d
 {
     if (dtype == 0 && f32_split_bwd_shape_ok(n, k, d) && ((uintptr_t)phi & 7) == 0 && ((uintptr_t)dF & 15) == 0)
         return launch_project_backward_f32_split((const float *)phi, mass, dA, batch, n, k, d, dF, st);
+    if (dtype == 0 && f32k_bwd_shape_ok(n, k, d) && ((uintptr_t)phi & 7) == 0 && ((uintptr_t)dF & 15) == 0)
+        return launch_project_backward_f32k((const float *)phi, mass, dA, batch, n, k, d, dF, st);
     if (lds_bwd_shape_ok(n, k, d, dtype) && aligned16(phi) && aligned16(mass)) {
         static bool attr_set = false;
         if (!attr_set) {

@@ -569,6 +569,155 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Backward projection for float32 inputs with 64 < k <= kMaxK (k even), on the
+// bf16 matrix cores with both operands split into three parts (six products).
+//
+// The dA^T parts of every k slot would not fit in LDS for 128 columns, so a
+// workgroup owns a 64-column block: 3 parts x 64 columns x (32 KS + 8) bf16
+// pairs, up to 126 KB, staged once.  8 waves x 32 vertices form a 256-vertex
+// tile.  A wave's work is a flat sequence of steps (tile, K step); the basis
+// row segments of step s + 3 are loaded while step s is multiplied (four
+// register buffers rotated by unrolling, loads unconditional from clamped
+// addresses), so the basis stream never waits for a tile boundary.  The 4 x 2
+// accumulators of a tile are stored, scaled by the masses, after its last K
+// step.  The column blocks of one vertex range share an XCD (their basis rows
+// are read from HBM once and from L2 afterwards).
+// ---------------------------------------------------------------------------
+constexpr int BK_COLS = 64;  // columns per workgroup
+__host__ __device__ constexpr size_t bwdk_lds(int ks) { return (size_t)3 * BK_COLS * bwdmc_stride(ks); }
+
+struct BkStep {
+    RowSeg<float> seg[2];  // vertex tiles nt = 0, 1
+    float m[2];            // their masses
+};
+
+template <int KS>
+__global__ __launch_bounds__(512, 1) void proj_bwd_mck_kernel(const float *__restrict__ phi,
+                                                            const float *__restrict__ mass,
+                                                            const float *__restrict__ dA, int n, int k, int d,
+                                                            int vsplit, int dblocks, int ntasks,
+                                                            float *__restrict__ dF)
+{
+    constexpr int STRIDE = bwdmc_stride(KS);
+    extern __shared__ __align__(16) float smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m16 = lane & 15, g4 = lane >> 4;
+    const int bid = blockIdx.x;
+    const int xs = bid & 7, q = bid >> 3;
+    const int db = q % dblocks;
+    const int j = (q / dblocks) * 8 + xs;
+    if (j >= ntasks) return;  // whole workgroup, before any barrier
+    const int vs = j % vsplit, s = j / vsplit;
+    const int dbase = db * BK_COLS;
+
+    const float *P = phi + (size_t)s * n * k;
+    const float *Mv = mass + (size_t)s * n;
+    const float *G = dA + (size_t)s * k * d;
+    float *O = dF + (size_t)s * n * d;
+
+    // dA^T parts for columns [dbase, dbase + 64), slots < 32 KS (zero past k and d)
+    char *parts = reinterpret_cast<char *>(smem);
+    batched_for<8>(
+        tid, KS * 32 * BK_COLS, 512,
+        [&](int e) {
+            const int jj = e / BK_COLS, c = e - jj * BK_COLS;
+            return G[(size_t)min(jj, k - 1) * d + min(dbase + c, d - 1)];
+        },
+        [&](int e, float g) {
+            const int jj = e / BK_COLS, c = e - jj * BK_COLS;
+            const float v = (jj < k && dbase + c < d) ? g : 0.f;
+            uint32_t w[3];
+            split_pack<3>(v, 0.f, w);
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                *reinterpret_cast<uint16_t *>(parts + (size_t)p * BK_COLS * STRIDE + c * STRIDE + 2 * jj) =
+                    (uint16_t)w[p];
+        });
+    __syncthreads();
+
+    const int ntile = (n + BB_VT - 1) / BB_VT;
+    const int t0 = (int)(((long)vs * ntile) / vsplit), t1 = (int)(((long)(vs + 1) * ntile) / vsplit);
+    if (t0 >= t1) return;
+    const int nsteps = (t1 - t0) * KS;
+    const bool vec = (d & 3) == 0;
+
+    auto load_step = [&](int st, BkStep &b) {
+        const int vt = t0 + st / KS, ks = st % KS;
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int v = min(vt * BB_VT + wave * 32 + nt * 16 + m16, n - 1);
+            b.m[nt] = Mv[v];
+            b.seg[nt] = load_seg_f32(P + (size_t)v * k, ks * 32 + 8 * g4, k);
+        }
+    };
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4{0, 0, 0, 0};
+    auto step = [&](int st, const BkStep &b) {
+        const int vt = t0 + st / KS, ks = st % KS;
+        u32x4_t B[2][3];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) seg_parts<3>(b.seg[nt], ks * 32 + 8 * g4, k, B[nt]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            u32x4_t A[3];
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                A[p] = *reinterpret_cast<const u32x4_t *>(parts + (size_t)p * BK_COLS * STRIDE + (mt * 16 + m16) * STRIDE +
+                                                         2 * (ks * 32 + 8 * g4));
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int jp = 0; jp < 3; ++jp)
+                    if (i + jp <= 2) {
+#pragma unroll
+                        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma16x16x32bf16(A[jp], B[nt][i], acc[mt][nt]);
+                    }
+        }
+        if (ks == KS - 1) {  // the tile is complete: register r of lane (m16, g4) is column 4 g4 + r of tile mt
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const int v = vt * BB_VT + wave * 32 + nt * 16 + m16;
+                float *row = O + (size_t)min(v, n - 1) * d;
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    const int col = dbase + mt * 16 + 4 * g4;
+                    const f32x4 val = acc[mt][nt] * b.m[nt];
+                    if (vec) {
+                        if (v < n && col < d) *reinterpret_cast<f32x4 *>(row + col) = val;
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (v < n && col + r < d) row[col + r] = val[r];
+                    }
+                    acc[mt][nt] = f32x4{0, 0, 0, 0};
+                }
+            }
+        }
+    };
+    BkStep b0, b1, b2, b3;
+    const int last = nsteps - 1;
+    load_step(0, b0);
+    load_step(min(1, last), b1);
+    load_step(min(2, last), b2);
+    for (int st = 0; st < nsteps; st += 4) {
+        load_step(min(st + 3, last), b3);
+        step(st, b0);
+        if (st + 1 >= nsteps) break;
+        load_step(min(st + 4, last), b0);
+        step(st + 1, b1);
+        if (st + 2 >= nsteps) break;
+        load_step(min(st + 5, last), b1);
+        step(st + 2, b2);
+        if (st + 3 >= nsteps) break;
+        load_step(min(st + 6, last), b2);
+        step(st + 3, b3);
+    }
+}
+
 constexpr int XS = 32;  // vertices per stage (one matrix-core K step)
 
 __host__ __device__ constexpr int x3_np(int k) { return (k + 7) / 8; }  // 1 KB basis windows (32 rows x k floats)
@@ -895,6 +1044,52 @@ hipError_t launch_project_backward_f32_split(const float *phi, const float *mass
 {
     if (bwdmc_ks(k) == 1) return dispatch_bwdmc<float, 3, 3, 1>(phi, mass, dA, batch, n, k, d, dF, st);
     return dispatch_bwdmc<float, 3, 3, 2>(phi, mass, dA, batch, n, k, d, dF, st);
+}
+
+bool f32k_bwd_shape_ok(int64_t n, int64_t k, int64_t d)
+{
+    return k > 64 && k <= kMaxK && k % 2 == 0 && n >= 1 && d >= 1;
+}
+
+template <int KS>
+static hipError_t dispatch_bwdk(const float *phi, const float *mass, const float *dA, int64_t batch, int64_t n,
+                                int64_t k, int64_t d, float *dF, hipStream_t st)
+{
+    const size_t lds = bwdk_lds(KS);
+    static int per_cu = 0;  // resident workgroups per CU, queried once (with the LDS limit raised)
+    if (per_cu == 0) {
+        (void)hipFuncSetAttribute((const void *)proj_bwd_mck_kernel<KS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        int r = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, (const void *)proj_bwd_mck_kernel<KS>, 512, lds) !=
+                hipSuccess ||
+            r < 1)
+            r = 1;
+        per_cu = r;
+    }
+    const int dblocks = (int)((d + BK_COLS - 1) / BK_COLS);
+    const int64_t ntile = (n + BB_VT - 1) / BB_VT;
+    const int vsplit = bwdmc_vsplit(batch, dblocks, ntile, per_cu);
+    const int ntasks = (int)(batch * vsplit);
+    const unsigned grid = (unsigned)(8 * dblocks * ((ntasks + 7) / 8));
+    hipLaunchKernelGGL((proj_bwd_mck_kernel<KS>), dim3(grid), dim3(512), lds, st, phi, mass, dA, (int)n, (int)k,
+                       (int)d, vsplit, dblocks, ntasks, dF);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_backward_f32k(const float *phi, const float *mass, const float *dA, int64_t batch,
+                                        int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st)
+{
+    switch (bwdmc_ks(k)) {
+    case 3: return dispatch_bwdk<3>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 4: return dispatch_bwdk<4>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 5: return dispatch_bwdk<5>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 6: return dispatch_bwdk<6>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 7: return dispatch_bwdk<7>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 8: return dispatch_bwdk<8>(phi, mass, dA, batch, n, k, d, dF, st);
+    case 9: return dispatch_bwdk<9>(phi, mass, dA, batch, n, k, d, dF, st);
+    default: return dispatch_bwdk<10>(phi, mass, dA, batch, n, k, d, dF, st);
+    }
 }
 
 }  // namespace fmap

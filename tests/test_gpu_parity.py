@@ -118,8 +118,13 @@ def test_project_backward_bf16_matrix_cores(F, dev, b, n, k, d):
         assert err <= TOL, (s, err)
 
 
+# float32 backward with 64 < k <= 319, k even (64-column blocks, every K step's dA^T parts in LDS): partial
+# column blocks, partial vertex tiles, d % 4 != 0 (element stores), one and ten K steps of 32
+BWDK_CASES = [(2, 1028, 80, 260), (1, 2052, 300, 516), (1, 999, 130, 33), (2, 4004, 318, 64), (1, 600, 66, 8)]
+
+
 @pytest.mark.parametrize("b,n,k,d", [(1, 1, 1, 1), (2, 37, 5, 7), (3, 1234, 30, 128), (2, 5000, 50, 256),
-                                     (1, 4097, 64, 300), (2, 999, 65, 33)] + LDS_CASES + SPLIT_CASES)
+                                     (1, 4097, 64, 300), (2, 999, 65, 33)] + LDS_CASES + SPLIT_CASES + BWDK_CASES)
 def test_project_backward(F, dev, b, n, k, d):
     phi, mass, _ = _shapes(3, b, n, k, d)
     dA = np.random.default_rng(4).standard_normal((b, k, d)).astype(np.float32)
