@@ -23,6 +23,11 @@ struct BwdItem {                  // dF rows [r0, r0 + 128*rb) x columns [dbase,
     float *dF;
     int n, k, d, r0, rb, dbase;
 };
+struct McItem {                   // dF tiles [t0, t1) of 256 vertices x columns [dbase, dbase + block)
+    const float *phi, *mass, *dA;
+    float *dF;
+    int n, k, d, t0, t1, dbase;
+};
 struct RedItem {                  // A = sum of `nchunks` partial k x d slots
     const float *part;
     float *A, *A_user;
@@ -32,6 +37,14 @@ struct RedItem {                  // A = sum of `nchunks` partial k x d slots
 hipError_t launch_fwd_items(const FwdItem *items, int nitems, int kmax, int grid, hipStream_t st);
 hipError_t launch_bwd_items(const BwdItem *items, int nitems, int kmax, int grid, hipStream_t st);
 hipError_t launch_reduce_items(const RedItem *items, int nitems, hipStream_t st);
+// Uneven batches on the emulated float32 kernels, one workgroup per item.  Forward items cover whole
+// 32-vertex stages (v0, v1 multiples of 32) of shapes with x3r_item_shape_ok; `sliced` = k > 64.
+bool x3r_item_shape_ok(int64_t k, int64_t d);
+hipError_t launch_fwd_x3r_items(const FwdItem *items, int nitems, bool sliced, hipStream_t st);
+// Backward items of one k (k even, <= kMaxK): mc_item_cols(k) columns per item.
+bool mc_item_shape_ok(int64_t k);
+int mc_item_cols(int64_t k);
+hipError_t launch_bwd_mc_items(const McItem *items, int nitems, int64_t k, hipStream_t st);
 // Fixed-order sum of split-K partials [batch][nsplit][k][d] into A [batch][k][d].
 hipError_t launch_reduce(const float *part, int nsplit, int64_t batch, int64_t k, int64_t d, float *A, hipStream_t st);
 // bf16 forward projection on the bf16 matrix cores (k % 8 == 0, k <= 256, d % 8 == 0, n % 4 == 0).

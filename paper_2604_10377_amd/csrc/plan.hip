@@ -4,9 +4,15 @@
 // one batch dimension, Eq. (8)), allocates the group buffers, and builds device
 // tables of work items:
 //   - forward projection items: (shape, vertex chunk, 64-row k block, 256-column
-//     d block), run by ONE persistent launch over all shapes of all groups;
+//     d block).  Shapes the emulated float32 kernel takes (k even, d % 4 == 0,
+//     16-byte aligned rows) run their whole 32-vertex stages on it, one
+//     workgroup per item (one launch for k <= 64, one for k > 64); the last
+//     n % 32 vertices, and all other shapes, are items of ONE persistent launch
+//     of the general kernel;
 //   - reduction items: the fixed-order sum of each shape's chunk partials;
-//   - backward projection items: (shape, rows, d block), one persistent launch;
+//   - backward projection items: (shape, 256-vertex tiles, column block) on the
+//     emulated kernels, one launch per k group; (shape, rows, d block) items of
+//     one persistent launch of the general kernel for the rest;
 //   - copy items: gather eigenvalues / lambda / dC into the group buffers and
 //     scatter C / info back to the pairs.
 // It then autotunes (vertices per item, persistent grid size, row systems per
@@ -56,6 +62,7 @@ using namespace fmap;
 struct Bucket {
     int64_t k = 0;
     std::vector<int> pairs;
+    int mc_off = 0, mc_n = 0;  // this group's backward items in the emulated-kernel table
     float *AB = nullptr, *dAB = nullptr, *C = nullptr, *factors = nullptr, *evx = nullptr, *evy = nullptr,
           *lam = nullptr, *dC = nullptr;
     int32_t *info = nullptr;
@@ -72,8 +79,10 @@ struct fmap_plan {
     std::vector<Bucket> buckets;
     std::vector<void *> allocs;
     float *partials = nullptr;
-    FwdItem *d_fwd = nullptr;
-    int nfwd = 0;
+    FwdItem *d_fwd = nullptr, *d_x3 = nullptr, *d_x3s = nullptr;
+    int nfwd = 0, nx3 = 0, nx3s = 0;
+    McItem *d_mc = nullptr;
+    int nmc = 0;
     RedItem *d_red = nullptr;
     int nred = 0;
     BwdItem *d_bwd = nullptr;
@@ -124,6 +133,28 @@ struct Shape {
     int bucket, slot;  // slot within the bucket's [2P] shape array
 };
 
+bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+// the forward of this shape runs its whole stages on the emulated float32 kernel
+bool x3r_shape(const Shape &s, int64_t d)
+{
+    return x3r_item_shape_ok(s.k, d) && aligned(s.phi, 16) && aligned(s.feat, 16) && s.n >= 32;
+}
+
+// the backward of every shape of this group runs on the emulated float32 kernels
+bool mc_bucket(const fmap_plan *pl, int b)
+{
+    const Bucket &B = pl->buckets[b];
+    if (!mc_item_shape_ok(B.k)) return false;
+    for (int q : B.pairs) {
+        const fmap_pair &p = pl->pairs[q];
+        if (!aligned(p.phi_x, 8) || !aligned(p.phi_y, 8) ||
+            (pl->d % 4 == 0 && (!aligned(p.dF_x, 16) || !aligned(p.dF_y, 16))))
+            return false;
+    }
+    return true;
+}
+
 std::vector<Shape> shapes_of(const fmap_plan *pl)
 {
     std::vector<Shape> sh;
@@ -139,20 +170,30 @@ std::vector<Shape> shapes_of(const fmap_plan *pl)
     return sh;
 }
 
-// Forward and reduction items for a given chunk size; partial slots are laid out shape after shape.
-void build_fwd_items(const fmap_plan *pl, int chunk, std::vector<FwdItem> &fi, std::vector<RedItem> &ri,
-                     size_t *partial_floats)
+// Forward and reduction items for a given chunk size (a multiple of 32); partial slots are laid out shape
+// after shape.  fx / fxs: emulated-kernel items (k <= 64 / k > 64), fi: general-kernel items.
+void build_fwd_items(const fmap_plan *pl, int chunk, std::vector<FwdItem> &fi, std::vector<FwdItem> &fx,
+                     std::vector<FwdItem> &fxs, std::vector<RedItem> &ri, size_t *partial_floats)
 {
     fi.clear();
+    fx.clear();
+    fxs.clear();
     ri.clear();
     size_t off = 0;
     const int64_t d = pl->d;
     for (const Shape &s : shapes_of(pl)) {
         const Bucket &B = pl->buckets[s.bucket];
-        const int nch = (int)((s.n + chunk - 1) / chunk);
+        const bool fast = x3r_shape(s, d);
+        const int64_t nfast = fast ? s.n - s.n % 32 : 0;  // vertices in whole stages, on the emulated kernel
+        const int nchf = (int)((nfast + chunk - 1) / chunk);
+        const int nchg = (int)((s.n - nfast + chunk - 1) / chunk);
+        const int nch = nchf + nchg;
         const int kb = (int)((s.k + 63) / 64), db = (int)((d + 255) / 256);
         float *part = pl->partials ? pl->partials + off : nullptr;
-        for (int c = 0; c < nch; ++c)
+        for (int c = 0; c < nch; ++c) {
+            const bool cf = c < nchf;
+            const int64_t v0 = cf ? (int64_t)c * chunk : nfast + (int64_t)(c - nchf) * chunk;
+            const int64_t v1 = std::min<int64_t>(cf ? nfast : s.n, v0 + chunk);
             for (int kk = 0; kk < kb; ++kk)
                 for (int dd = 0; dd < db; ++dd) {
                     FwdItem w;
@@ -163,12 +204,13 @@ void build_fwd_items(const fmap_plan *pl, int chunk, std::vector<FwdItem> &fi, s
                     w.n = (int)s.n;
                     w.k = (int)s.k;
                     w.d = (int)d;
-                    w.v0 = c * chunk;
-                    w.v1 = (int)std::min<int64_t>(s.n, (int64_t)(c + 1) * chunk);
+                    w.v0 = (int)v0;
+                    w.v1 = (int)v1;
                     w.kbase = kk * 64;
                     w.dbase = dd * 256;
-                    fi.push_back(w);
+                    (cf ? (s.k > 64 ? fxs : fx) : fi).push_back(w);
                 }
+        }
         RedItem r;
         r.part = part;
         r.A = B.AB + (size_t)s.slot * s.k * d;
@@ -178,17 +220,53 @@ void build_fwd_items(const fmap_plan *pl, int chunk, std::vector<FwdItem> &fi, s
         ri.push_back(r);
         off += (size_t)nch * s.k * d;
     }
-    // longest items first: the static round-robin of the persistent grid then balances the tails
-    std::stable_sort(fi.begin(), fi.end(), [](const FwdItem &a, const FwdItem &b) { return a.v1 - a.v0 > b.v1 - b.v0; });
+    // longest items first: the workgroup scheduler (or the persistent grid's static round-robin) then
+    // balances the tails
+    auto longer = [](const FwdItem &a, const FwdItem &b) { return a.v1 - a.v0 > b.v1 - b.v0; };
+    std::stable_sort(fi.begin(), fi.end(), longer);
+    std::stable_sort(fx.begin(), fx.end(), longer);
+    std::stable_sort(fxs.begin(), fxs.end(), longer);
     *partial_floats = off;
 }
 
-void build_bwd_items(const fmap_plan *pl, int rb, std::vector<BwdItem> &bi)
+// Backward items: groups on the emulated kernels get McItems of 2 rb 256-vertex tiles (in bucket order,
+// with each bucket's offset and count recorded), the rest general-kernel items of 128 rb rows.
+void build_bwd_items(fmap_plan *pl, int rb, std::vector<BwdItem> &bi, std::vector<McItem> &mi)
 {
     bi.clear();
+    mi.clear();
     const int64_t d = pl->d;
+    for (int b = 0; b < (int)pl->buckets.size(); ++b) {
+        Bucket &B = pl->buckets[b];
+        B.mc_off = (int)mi.size();
+        B.mc_n = 0;
+        if (!mc_bucket(pl, b)) continue;
+        const int cols = mc_item_cols(B.k);
+        const int tpi = 2 * rb;
+        for (const Shape &s : shapes_of(pl)) {
+            if (s.bucket != b) continue;
+            const int ntile = (int)((s.n + 255) / 256);
+            for (int t0 = 0; t0 < ntile; t0 += tpi)
+                for (int64_t c0 = 0; c0 < d; c0 += cols) {
+                    McItem w;
+                    w.phi = s.phi;
+                    w.mass = s.mass;
+                    w.dA = B.dAB + (size_t)s.slot * s.k * d;
+                    w.dF = s.dF;
+                    w.n = (int)s.n;
+                    w.k = (int)s.k;
+                    w.d = (int)d;
+                    w.t0 = t0;
+                    w.t1 = std::min(ntile, t0 + tpi);
+                    w.dbase = (int)c0;
+                    mi.push_back(w);
+                }
+        }
+        B.mc_n = (int)mi.size() - B.mc_off;
+    }
     for (const Shape &s : shapes_of(pl)) {
         const Bucket &B = pl->buckets[s.bucket];
+        if (B.mc_n > 0) continue;
         const int db = (int)((d + 255) / 256);
         for (int64_t r0 = 0; r0 < s.n; r0 += 128 * rb)
             for (int dd = 0; dd < db; ++dd) {
@@ -208,11 +286,29 @@ void build_bwd_items(const fmap_plan *pl, int rb, std::vector<BwdItem> &bi)
     }
 }
 
+// The forward projection items of all shapes, then the fixed-order chunk sums.
+hipError_t launch_projections_fwd(fmap_plan *pl, int grid, hipStream_t st)
+{
+    hipError_t e = launch_fwd_x3r_items(pl->d_x3, pl->nx3, false, st);
+    if (e == hipSuccess) e = launch_fwd_x3r_items(pl->d_x3s, pl->nx3s, true, st);
+    if (e == hipSuccess && pl->nfwd > 0) e = launch_fwd_items(pl->d_fwd, pl->nfwd, (int)pl->kmax, grid, st);
+    if (e == hipSuccess) e = launch_reduce_items(pl->d_red, pl->nred, st);
+    return e;
+}
+
+hipError_t launch_projections_bwd(fmap_plan *pl, int grid, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    for (const Bucket &B : pl->buckets)
+        if (e == hipSuccess && B.mc_n > 0) e = launch_bwd_mc_items(pl->d_mc + B.mc_off, B.mc_n, B.k, st);
+    if (e == hipSuccess && pl->nbwd > 0) e = launch_bwd_items(pl->d_bwd, pl->nbwd, (int)pl->kmax, grid, st);
+    return e;
+}
+
 hipError_t record_forward(fmap_plan *pl, hipStream_t st)
 {
     hipError_t e = launch_copies(pl->d_gf, pl->ngf, st);
-    if (e == hipSuccess) e = launch_fwd_items(pl->d_fwd, pl->nfwd, (int)pl->kmax, pl->grid_fwd, st);
-    if (e == hipSuccess) e = launch_reduce_items(pl->d_red, pl->nred, st);
+    if (e == hipSuccess) e = launch_projections_fwd(pl, pl->grid_fwd, st);
     set_rowsolve_waves(pl->waves);
     for (Bucket &B : pl->buckets) {
         if (e != hipSuccess) break;
@@ -238,7 +334,7 @@ hipError_t record_backward(fmap_plan *pl, hipStream_t st)
                                   nullptr, B.ws, st);
     }
     set_rowsolve_waves(4);
-    if (e == hipSuccess) e = launch_bwd_items(pl->d_bwd, pl->nbwd, (int)pl->kmax, pl->grid_bwd, st);
+    if (e == hipSuccess) e = launch_projections_bwd(pl, pl->grid_bwd, st);
     return e;
 }
 
@@ -422,10 +518,10 @@ fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, 
     // partial slots sized for the smallest candidate chunk
     const int chunks[3] = {512, 1024, 2048};
     {
-        std::vector<FwdItem> fi;
+        std::vector<FwdItem> fi, fx, fxs;
         std::vector<RedItem> ri;
         size_t pf = 0;
-        build_fwd_items(pl, chunks[0], fi, ri, &pf);
+        build_fwd_items(pl, chunks[0], fi, fx, fxs, ri, &pf);
         FMAP_TRY(dev_alloc(pl, &pl->partials, pf));
     }
     const std::string sig = signature(pl);
@@ -433,21 +529,29 @@ fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, 
     pl->from_cache = cache_lookup(tune_cache_path, sig, pl) ? 1 : 0;
 
     auto set_fwd = [&](int chunk) -> hipError_t {
-        std::vector<FwdItem> fi;
+        std::vector<FwdItem> fi, fx, fxs;
         std::vector<RedItem> ri;
         size_t pf = 0;
-        build_fwd_items(pl, chunk, fi, ri, &pf);
+        build_fwd_items(pl, chunk, fi, fx, fxs, ri, &pf);
         pl->nfwd = (int)fi.size();
+        pl->nx3 = (int)fx.size();
+        pl->nx3s = (int)fxs.size();
         pl->nred = (int)ri.size();
         hipError_t e = upload(pl, &pl->d_fwd, fi, st);
+        if (e == hipSuccess) e = upload(pl, &pl->d_x3, fx, st);
+        if (e == hipSuccess) e = upload(pl, &pl->d_x3s, fxs, st);
         if (e == hipSuccess) e = upload(pl, &pl->d_red, ri, st);
         return e;
     };
     auto set_bwd = [&](int rb) -> hipError_t {
         std::vector<BwdItem> bi;
-        build_bwd_items(pl, rb, bi);
+        std::vector<McItem> mi;
+        build_bwd_items(pl, rb, bi, mi);
         pl->nbwd = (int)bi.size();
-        return upload(pl, &pl->d_bwd, bi, st);
+        pl->nmc = (int)mi.size();
+        hipError_t e = upload(pl, &pl->d_bwd, bi, st);
+        if (e == hipSuccess) e = upload(pl, &pl->d_mc, mi, st);
+        return e;
     };
 
     if (!pl->from_cache) {
@@ -458,10 +562,7 @@ fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, 
             FMAP_TRY(set_fwd(c));
             for (int gm : {1, 2, 4}) {
                 const int g = std::max(1, std::min(gm * cus, pl->nfwd));
-                const float t = time_ms(st, [&]() {
-                    (void)launch_fwd_items(pl->d_fwd, pl->nfwd, (int)pl->kmax, g, st);
-                    (void)launch_reduce_items(pl->d_red, pl->nred, st);
-                });
+                const float t = time_ms(st, [&]() { (void)launch_projections_fwd(pl, g, st); });
                 if (t < best) {
                     best = t;
                     bc = c;
@@ -474,8 +575,7 @@ fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, 
         // row systems per workgroup of the register row solve (groups with k <= 64)
         FMAP_TRY(set_fwd(pl->chunk));
         FMAP_TRY(launch_copies(pl->d_gf, pl->ngf, st));
-        FMAP_TRY(launch_fwd_items(pl->d_fwd, pl->nfwd, (int)pl->kmax, pl->grid_fwd, st));
-        FMAP_TRY(launch_reduce_items(pl->d_red, pl->nred, st));
+        FMAP_TRY(launch_projections_fwd(pl, pl->grid_fwd, st));
         best = 1e30f;
         int bw = 4;
         for (int w : {1, 2, 4}) {
@@ -502,10 +602,8 @@ fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, 
             for (int rb : {1, 2, 4}) {
                 FMAP_TRY(set_bwd(rb));
                 for (int gm : {1, 2, 4}) {
-                    const int g = std::max(1, std::min(gm * cus, pl->nbwd));
-                    const float t = time_ms(st, [&]() {
-                        (void)launch_bwd_items(pl->d_bwd, pl->nbwd, (int)pl->kmax, g, st);
-                    });
+                    const int g = std::max(1, std::min(gm * cus, std::max(pl->nbwd, 1)));
+                    const float t = time_ms(st, [&]() { (void)launch_projections_bwd(pl, g, st); });
                     if (t < best) {
                         best = t;
                         brb = rb;

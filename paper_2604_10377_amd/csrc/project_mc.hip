@@ -383,11 +383,12 @@ __device__ __forceinline__ void seg_parts(const RowSeg<float> &r, int kk, int k,
     for (int p = 0; p < PP; ++p) B[p] = u32x4_t{w[0][p], w[1][p], w[2][p], w[3][p]};
 }
 
+// One workgroup's block: 256-vertex tiles [t0, t1) of one shape (basis P, masses Mv, G = dA, O = dF) for the
+// columns [dbase, dbase + 128).
 template <typename T, int PP, int PD, int KS>
-__global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict__ phi, const float *__restrict__ mass,
-                                                           const float *__restrict__ dA, int n, int k, int d,
-                                                           int vsplit, int dblocks, int ntasks,
-                                                           float *__restrict__ dF)
+__device__ __forceinline__ void bwdmc_block(const T *__restrict__ P, const float *__restrict__ Mv,
+                                            const float *__restrict__ G, float *__restrict__ O, int n, int k, int d,
+                                            int t0, int t1, int dbase)
 {
     constexpr int STRIDE = bwdmc_stride(KS);
     constexpr bool TR = bwdmc_transpose(PD, KS);
@@ -395,18 +396,6 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict
     float *tstage = reinterpret_cast<float *>(reinterpret_cast<char *>(smem) + bwdmc_parts(PD, KS));
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m16 = lane & 15, g4 = lane >> 4;
-    const int bid = blockIdx.x;
-    const int xs = bid & 7, q = bid >> 3;
-    const int db = q % dblocks;
-    const int j = (q / dblocks) * 8 + xs;
-    if (j >= ntasks) return;  // whole workgroup, before any barrier
-    const int vs = j % vsplit, s = j / vsplit;
-    const int dbase = db * BB_COLS;
-
-    const T *P = phi + (size_t)s * n * k;
-    const float *Mv = mass + (size_t)s * n;
-    const float *G = dA + (size_t)s * k * d;
-    float *O = dF + (size_t)s * n * d;
 
     // dA^T parts for columns [dbase, dbase + 128), rows < 32 KS (zero past k and d)
     char *parts = reinterpret_cast<char *>(smem);
@@ -428,8 +417,6 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict
         });
     __syncthreads();
 
-    const int ntile = (n + BB_VT - 1) / BB_VT;
-    const int t0 = (int)(((long)vs * ntile) / vsplit), t1 = (int)(((long)(vs + 1) * ntile) / vsplit);
     const bool vec = (d & 3) == 0;
 
     // basis row segments of a tile: [k step][vertex tile of 16]; rows past n are clamped (never stored)
@@ -569,6 +556,32 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict
     }
 }
 
+template <typename T, int PP, int PD, int KS>
+__global__ __launch_bounds__(512, 2) void proj_bwd_mc_kernel(const T *__restrict__ phi, const float *__restrict__ mass,
+                                                           const float *__restrict__ dA, int n, int k, int d,
+                                                           int vsplit, int dblocks, int ntasks,
+                                                           float *__restrict__ dF)
+{
+    const int bid = blockIdx.x;
+    const int xs = bid & 7, q = bid >> 3;
+    const int db = q % dblocks;
+    const int j = (q / dblocks) * 8 + xs;
+    if (j >= ntasks) return;  // whole workgroup, before any barrier
+    const int vs = j % vsplit, s = j / vsplit;
+    const int ntile = (n + BB_VT - 1) / BB_VT;
+    const int t0 = (int)(((long)vs * ntile) / vsplit), t1 = (int)(((long)(vs + 1) * ntile) / vsplit);
+    bwdmc_block<T, PP, PD, KS>(phi + (size_t)s * n * k, mass + (size_t)s * n, dA + (size_t)s * k * d,
+                               dF + (size_t)s * n * d, n, k, d, t0, t1, db * BB_COLS);
+}
+
+// Uneven batches: one workgroup per work item (float32 basis).
+template <int KS>
+__global__ __launch_bounds__(512, 2) void proj_bwd_mc_items_kernel(const McItem *__restrict__ items)
+{
+    const McItem w = items[blockIdx.x];
+    bwdmc_block<float, 3, 3, KS>(w.phi, w.mass, w.dA, w.dF, w.n, w.k, w.d, w.t0, w.t1, w.dbase);
+}
+
 // ---------------------------------------------------------------------------
 // Backward projection for float32 inputs with 64 < k <= kMaxK (k even), on the
 // bf16 matrix cores with both operands split into three parts (six products).
@@ -592,29 +605,16 @@ struct BkStep {
     float m[2];            // their masses
 };
 
+// One workgroup's block: 256-vertex tiles [t0, t1) of one shape for the columns [dbase, dbase + 64).
 template <int KS>
-__global__ __launch_bounds__(512, 1) void proj_bwd_mck_kernel(const float *__restrict__ phi,
-                                                            const float *__restrict__ mass,
-                                                            const float *__restrict__ dA, int n, int k, int d,
-                                                            int vsplit, int dblocks, int ntasks,
-                                                            float *__restrict__ dF)
+__device__ __forceinline__ void bwdk_block(const float *__restrict__ P, const float *__restrict__ Mv,
+                                           const float *__restrict__ G, float *__restrict__ O, int n, int k, int d,
+                                           int t0, int t1, int dbase)
 {
     constexpr int STRIDE = bwdmc_stride(KS);
     extern __shared__ __align__(16) float smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m16 = lane & 15, g4 = lane >> 4;
-    const int bid = blockIdx.x;
-    const int xs = bid & 7, q = bid >> 3;
-    const int db = q % dblocks;
-    const int j = (q / dblocks) * 8 + xs;
-    if (j >= ntasks) return;  // whole workgroup, before any barrier
-    const int vs = j % vsplit, s = j / vsplit;
-    const int dbase = db * BK_COLS;
-
-    const float *P = phi + (size_t)s * n * k;
-    const float *Mv = mass + (size_t)s * n;
-    const float *G = dA + (size_t)s * k * d;
-    float *O = dF + (size_t)s * n * d;
 
     // dA^T parts for columns [dbase, dbase + 64), slots < 32 KS (zero past k and d)
     char *parts = reinterpret_cast<char *>(smem);
@@ -636,8 +636,6 @@ __global__ __launch_bounds__(512, 1) void proj_bwd_mck_kernel(const float *__res
         });
     __syncthreads();
 
-    const int ntile = (n + BB_VT - 1) / BB_VT;
-    const int t0 = (int)(((long)vs * ntile) / vsplit), t1 = (int)(((long)(vs + 1) * ntile) / vsplit);
     if (t0 >= t1) return;
     const int nsteps = (t1 - t0) * KS;
     const bool vec = (d & 3) == 0;
@@ -718,6 +716,33 @@ __global__ __launch_bounds__(512, 1) void proj_bwd_mck_kernel(const float *__res
     }
 }
 
+template <int KS>
+__global__ __launch_bounds__(512, 1) void proj_bwd_mck_kernel(const float *__restrict__ phi,
+                                                            const float *__restrict__ mass,
+                                                            const float *__restrict__ dA, int n, int k, int d,
+                                                            int vsplit, int dblocks, int ntasks,
+                                                            float *__restrict__ dF)
+{
+    const int bid = blockIdx.x;
+    const int xs = bid & 7, q = bid >> 3;
+    const int db = q % dblocks;
+    const int j = (q / dblocks) * 8 + xs;
+    if (j >= ntasks) return;  // whole workgroup, before any barrier
+    const int vs = j % vsplit, s = j / vsplit;
+    const int ntile = (n + BB_VT - 1) / BB_VT;
+    const int t0 = (int)(((long)vs * ntile) / vsplit), t1 = (int)(((long)(vs + 1) * ntile) / vsplit);
+    bwdk_block<KS>(phi + (size_t)s * n * k, mass + (size_t)s * n, dA + (size_t)s * k * d, dF + (size_t)s * n * d, n,
+                   k, d, t0, t1, db * BK_COLS);
+}
+
+// Uneven batches: one workgroup per work item.
+template <int KS>
+__global__ __launch_bounds__(512, 1) void proj_bwd_mck_items_kernel(const McItem *__restrict__ items)
+{
+    const McItem w = items[blockIdx.x];
+    bwdk_block<KS>(w.phi, w.mass, w.dA, w.dF, w.n, w.k, w.d, w.t0, w.t1, w.dbase);
+}
+
 constexpr int XS = 32;  // vertices per stage (one matrix-core K step)
 
 __host__ __device__ constexpr int x3_np(int k) { return (k + 7) / 8; }  // 1 KB basis windows (32 rows x k floats)
@@ -753,37 +778,22 @@ constexpr int RSTAGE = 8 * 1024 + 256;  // basis windows + mass window
 constexpr int RPARTS = 3 * 4 * 64 * 16;  // split basis tile: [part][row tile][lane] of u32x4
 __host__ __device__ constexpr size_t x3r_lds() { return (size_t)RNST * RSTAGE + RPARTS; }
 
+// One workgroup's block: vertices [vbeg, vend) of one shape (P, Mv, F), basis rows [64 kb, 64 kb + 64)
+// (all rows unless SLICED), columns [dbase, dbase + 256); the k x d partial slot O receives its part.
+// vbeg is a multiple of 32, and every stage but the last is full.
 template <bool SLICED>
-__global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__restrict__ phi,
-                                                             const float *__restrict__ mass,
-                                                             const float *__restrict__ feat, int n, int k, int d,
-                                                             int nsplit, int dblocks, int kblocks, int ntiles,
-                                                             float *__restrict__ out)
+__device__ __forceinline__ void x3r_block(const float *__restrict__ P, const float *__restrict__ Mv,
+                                          const float *__restrict__ F, int n, int k, int d, int vbeg, int vend,
+                                          int kb, int dbase, float *__restrict__ O)
 {
     extern __shared__ __align__(16) float smem[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int m16 = lane & 15, g4 = lane >> 4;
-    const int bid = blockIdx.x;
-    const int xs = bid & 7, q = bid >> 3;
-    const int dk = dblocks * kblocks;
-    const int db = (q % dk) % dblocks, kb = (q % dk) / dblocks;
-    const int j = (q / dk) * 8 + xs;
-    if (j >= ntiles) return;  // whole workgroup, before any barrier
-    const int split = j % nsplit, s = j / nsplit;
-    const int dbase = db * 256;
     const int kbase = SLICED ? 64 * kb : 0;
     const int kvalid = SLICED ? min(64, k - kbase) : k;  // basis rows of this block
     const int pstride = SLICED ? 64 : k;                 // LDS floats per vertex row of the basis tile
-
-    const int nst_all = (n + XS - 1) / XS;
-    const int st0 = (int)(((long)split * nst_all) / nsplit), st1 = (int)(((long)(split + 1) * nst_all) / nsplit);
-    const int vbeg = st0 * XS, vend = min(n, st1 * XS);
-    const int nst = st1 - st0;
-
-    const float *P = phi + (size_t)s * n * k;
-    const float *F = feat + (size_t)s * n * d;
-    const float *Mv = mass + (size_t)s * n;
+    const int nst = (vend - vbeg + XS - 1) / XS;
 
     const int np = SLICED ? 8 : x3_np(k);
     char *ring = reinterpret_cast<char *>(smem);
@@ -909,7 +919,6 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__res
 
     // lane (m16, g4), register r: matrix-core row 4*g4 + r -> basis row 4(4*g4 + r) + a; column m16 of
     // tile tt -> block column 64 wave + 4 m16 + tt
-    float *O = out + (size_t)j * k * d;
     const int col = dbase + cw;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -920,6 +929,34 @@ __global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__res
             const f32x4 v = f32x4{acc[a][0][r], acc[a][1][r], acc[a][2][r], acc[a][3][r]};
             *reinterpret_cast<f32x4 *>(O + (size_t)row * d + col) = v;  // d % 4 == 0: all 4 columns exist
         }
+}
+
+template <bool SLICED>
+__global__ __launch_bounds__(256, 2) void proj_fwd_x3r_kernel(const float *__restrict__ phi,
+                                                             const float *__restrict__ mass,
+                                                             const float *__restrict__ feat, int n, int k, int d,
+                                                             int nsplit, int dblocks, int kblocks, int ntiles,
+                                                             float *__restrict__ out)
+{
+    const int bid = blockIdx.x;
+    const int xs = bid & 7, q = bid >> 3;
+    const int dk = dblocks * kblocks;
+    const int db = (q % dk) % dblocks, kb = (q % dk) / dblocks;
+    const int j = (q / dk) * 8 + xs;
+    if (j >= ntiles) return;  // whole workgroup, before any barrier
+    const int split = j % nsplit, s = j / nsplit;
+    const int nst_all = (n + XS - 1) / XS;
+    const int st0 = (int)(((long)split * nst_all) / nsplit), st1 = (int)(((long)(split + 1) * nst_all) / nsplit);
+    x3r_block<SLICED>(phi + (size_t)s * n * k, mass + (size_t)s * n, feat + (size_t)s * n * d, n, k, d, st0 * XS,
+                      min(n, st1 * XS), kb, db * 256, out + (size_t)j * k * d);
+}
+
+// Uneven batches: one workgroup per work item (items of whole 32-vertex stages only).
+template <bool SLICED>
+__global__ __launch_bounds__(256, 2) void proj_fwd_x3r_items_kernel(const FwdItem *__restrict__ items)
+{
+    const FwdItem w = items[blockIdx.x];
+    x3r_block<SLICED>(w.phi, w.mass, w.feat, w.n, w.k, w.d, w.v0, w.v1, w.kbase / 64, w.dbase, w.out);
 }
 
 bool f32_split_fwd_shape_ok(int64_t n, int64_t k, int64_t d)
@@ -1089,6 +1126,69 @@ hipError_t launch_project_backward_f32k(const float *phi, const float *mass, con
     case 8: return dispatch_bwdk<8>(phi, mass, dA, batch, n, k, d, dF, st);
     case 9: return dispatch_bwdk<9>(phi, mass, dA, batch, n, k, d, dF, st);
     default: return dispatch_bwdk<10>(phi, mass, dA, batch, n, k, d, dF, st);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Uneven batches: one workgroup per work item
+// ---------------------------------------------------------------------------
+bool x3r_item_shape_ok(int64_t k, int64_t d)
+{
+    return ((k >= 4 && k <= 64 && k % 2 == 0) || (k > 64 && k <= kMaxK && k % 4 == 0)) && d % 4 == 0;
+}
+
+hipError_t launch_fwd_x3r_items(const FwdItem *items, int nitems, bool sliced, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (sliced)
+        hipLaunchKernelGGL((proj_fwd_x3r_items_kernel<true>), dim3((unsigned)nitems), dim3(256), x3r_lds(), st, items);
+    else
+        hipLaunchKernelGGL((proj_fwd_x3r_items_kernel<false>), dim3((unsigned)nitems), dim3(256), x3r_lds(), st, items);
+    return hipGetLastError();
+}
+
+bool mc_item_shape_ok(int64_t k) { return k >= 2 && k <= kMaxK && k % 2 == 0; }
+int mc_item_cols(int64_t k) { return k <= 64 ? BB_COLS : BK_COLS; }
+
+template <int KS>
+static hipError_t launch_mc_items_ks(const McItem *items, int nitems, hipStream_t st)
+{
+    if constexpr (KS <= 2) {
+        const size_t lds = bwdmc_lds(3, KS);
+        static bool attr_set = false;
+        if (!attr_set) {
+            (void)hipFuncSetAttribute((const void *)proj_bwd_mc_items_kernel<KS>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            attr_set = true;
+        }
+        hipLaunchKernelGGL((proj_bwd_mc_items_kernel<KS>), dim3((unsigned)nitems), dim3(512), lds, st, items);
+    } else {
+        const size_t lds = bwdk_lds(KS);
+        static bool attr_set = false;
+        if (!attr_set) {
+            (void)hipFuncSetAttribute((const void *)proj_bwd_mck_items_kernel<KS>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            attr_set = true;
+        }
+        hipLaunchKernelGGL((proj_bwd_mck_items_kernel<KS>), dim3((unsigned)nitems), dim3(512), lds, st, items);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_mc_items(const McItem *items, int nitems, int64_t k, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    switch (bwdmc_ks(k)) {
+    case 1: return launch_mc_items_ks<1>(items, nitems, st);
+    case 2: return launch_mc_items_ks<2>(items, nitems, st);
+    case 3: return launch_mc_items_ks<3>(items, nitems, st);
+    case 4: return launch_mc_items_ks<4>(items, nitems, st);
+    case 5: return launch_mc_items_ks<5>(items, nitems, st);
+    case 6: return launch_mc_items_ks<6>(items, nitems, st);
+    case 7: return launch_mc_items_ks<7>(items, nitems, st);
+    case 8: return launch_mc_items_ks<8>(items, nitems, st);
+    case 9: return launch_mc_items_ks<9>(items, nitems, st);
+    default: return launch_mc_items_ks<10>(items, nitems, st);
     }
 }
 
