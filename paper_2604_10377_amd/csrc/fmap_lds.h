@@ -12,6 +12,12 @@ __device__ __forceinline__ void dma16(const float *g, float *lds_base)
     __builtin_amdgcn_global_load_lds((glb_void_t *)g, (lds_void_t *)lds_base, 16, 0, 0);
 }
 
+// The same with the streaming (non-temporal) cache policy, for data read once.
+__device__ __forceinline__ void dma16_stream(const float *g, float *lds_base)
+{
+    __builtin_amdgcn_global_load_lds((glb_void_t *)g, (lds_void_t *)lds_base, 16, 0, 2);
+}
+
 // s_waitcnt with only the vector-memory counter constrained (gfx9 encoding).
 template <int N>
 __device__ __forceinline__ void wait_vmcnt()

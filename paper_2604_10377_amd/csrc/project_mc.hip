@@ -122,8 +122,8 @@ __global__ __launch_bounds__(256, KW == 4 ? 2 : 1) void proj_fwd_bf16_kernel(con
             if (item < C::NF) {
                 const int r = min(item * (64 / LPR) + lane / LPR, rows - 1);
                 const int col = min(dbase + (lane % LPR) * 8, d - 8);
-                dma16(reinterpret_cast<const float *>(F + (size_t)(v + r) * d + col),
-                      reinterpret_cast<float *>(S + np * 1024 + item * 1024));
+                dma16_stream(reinterpret_cast<const float *>(F + (size_t)(v + r) * d + col),
+                             reinterpret_cast<float *>(S + np * 1024 + item * 1024));
             } else if (item < C::NF + np) {
                 const int w = item - C::NF;
                 const int off = min(w * 512 + 8 * lane, pvalid - 8);

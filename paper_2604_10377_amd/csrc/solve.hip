@@ -382,7 +382,9 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
         const float myinv = s_inv[jr2];
 #pragma unroll
         for (int c = KMAX - 1; c >= 0; --c) {
-            const float cc = uniform(readlane(y, c) * readlane(myinv, c));
+            // columns of blocks past k_x were never factorised (their scalars were never recorded):
+            // their solution entries are 0, taken by a select so that no stale value enters
+            const float cc = (c < kx) ? uniform(readlane(y, c) * readlane(myinv, c)) : 0.f;
             if (j == 0) s_c[c] = cc;
             y -= sr[c] * cc;
         }

@@ -79,6 +79,27 @@ def test_plan_ragged_forward_backward(F, dev, mask, recompute):
     plan.close()
 
 
+# shapes of a few stages plus a tail (k = 68: sliced forward and the large-k backward), and shapes below
+# one stage (n < 32: the general kernels only)
+SMALL = [dict(pairs=5, d=256, n_lo=70, n_hi=140, ks=(8, 30, 68)), dict(pairs=3, d=64, n_lo=10, n_hi=31, ks=(8,))]
+
+
+@pytest.mark.parametrize("cfg", SMALL, ids=["stages+tails", "below-one-stage"])
+def test_plan_small_shapes(F, dev, cfg):
+    import torch
+    pairs = synth.workload_ragged(**cfg)
+    print("plan small:", [(p.n_x, p.n_y, p.k) for p in pairs], flush=True)
+    dpairs = _device_pairs(pairs, dev)
+    plan = F.FmapPlan(dpairs, synth.MASK_LAPLACIAN, 0.5, backward=True, want_AB=True)
+    for i, p in enumerate(pairs):
+        plan.dC[i].copy_(torch.from_numpy(p.dC))
+    plan.forward()
+    plan.backward()
+    torch.cuda.synchronize()
+    _check(plan, pairs, [_oracle(p, synth.MASK_LAPLACIAN, 0.5) for p in pairs], with_AB=True)
+    plan.close()
+
+
 def test_plan_replays_follow_inputs(F, dev):
     """Three replays; between them the features are rewritten in place and eager work runs."""
     import torch
