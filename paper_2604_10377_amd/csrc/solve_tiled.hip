@@ -109,24 +109,54 @@ __global__ __launch_bounds__(512) void rowsolve_tiles_kernel(
         const float *Kp = STORED ? nullptr : K + (size_t)p * kx * kx;
         const float *Lp = STORED ? Lin + ((size_t)p * ky + i) * (size_t)(kx * (kx + 1) / 2) : nullptr;
         const float *rp = rhs + ((size_t)p * ky + i) * kx;
-        // tile by tile (column-major order of the lower triangle), two entries per thread per tile:
-        // the loads of a tile are independent, so they are in flight together
-        for (int J = 0, tau = 0; J < T; ++J)
-            for (int I = J; I < TR; ++I, ++tau) {
+        // tiles in column-major order of the lower triangle, two entries per thread per tile, TG tiles
+        // at a time: their loads are unconditional (addresses clamped into the arrays, the right-hand
+        // side row selected by address) so all of a group's loads are in flight together, and the
+        // values are masked when written
+        {
+            constexpr int TG = 4;
+            const int ntile = T * TR - (T * (T - 1)) / 2;
+            int I = 0, J = 0;  // tile cursor, uniform
+            for (int tau0 = 0; tau0 < ntile; tau0 += TG) {
+                float v[TG][2];
+                int Iu[TG], Ju[TG];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int rc = tid + 512 * h, r = rc >> 5, c = rc & 31;
-                    const int row = 32 * I + r, col = 32 * J + c;
-                    float v = 0.f;
-                    if (row < kx && col <= row) {
-                        if (STORED) v = Lp[packed_col_t(col, kx) + row - col];
-                        else v = Kp[(size_t)row * kx + col] + (row == col ? s_shift[row] : 0.f);
-                    } else if (row == kx && col < kx) {
-                        v = rp[col];
+                for (int u = 0; u < TG; ++u) {
+                    Iu[u] = I;
+                    Ju[u] = J;
+                    if (++I >= TR) {  // next column of tiles
+                        ++J;
+                        I = J;
                     }
-                    tiles[tau * TSZ + r * TLD + c] = v;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int rc = tid + 512 * h, r = rc >> 5, c = rc & 31;
+                        const int row = min(32 * Iu[u] + r, kx), col = min(32 * Ju[u] + c, kx - 1);
+                        const float *src;
+                        if (STORED) {
+                            const int cc = min(col, min(row, kx - 1));
+                            src = row == kx ? rp + col : Lp + packed_col_t(cc, kx) + min(row, kx - 1) - cc;
+                        } else {
+                            src = row == kx ? rp + col : Kp + (size_t)row * kx + col;
+                        }
+                        v[u][h] = *src;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < TG; ++u) {
+                    if (tau0 + u >= ntile) break;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int rc = tid + 512 * h, r = rc >> 5, c = rc & 31;
+                        const int row = 32 * Iu[u] + r, col = 32 * Ju[u] + c;
+                        float x = 0.f;
+                        if (row < kx && col <= row) x = STORED ? v[u][h] : v[u][h] + (row == col ? s_shift[row] : 0.f);
+                        else if (row == kx && col < kx) x = v[u][h];
+                        tiles[(tau0 + u) * TSZ + r * TLD + c] = x;
+                    }
                 }
             }
+        }
         __syncthreads();
 
         for (int pstep = 0; pstep < T; ++pstep) {
@@ -255,26 +285,28 @@ __global__ __launch_bounds__(512) void rowsolve_tiles_kernel(
 
         // ---- factors out (forward mode) ----------------------------------------------------
         if (MODE == RT_FWD && Lout && fail == 0) {
-            // in packed (column-major) order, so consecutive threads store consecutive floats: thread
-            // tid walks entries tid, tid + 512, ... keeping its (column, row) position incrementally
+            // in packed (column-major) order, so consecutive threads store consecutive floats.  Entry e
+            // lies in the column q with packed_col(q) <= e < packed_col(q + 1), found from the quadratic
+            // for packed_col (hardware square root) and corrected by one step either way; every index
+            // product fits in 24 bits
             float *Lo = Lout + ((size_t)p * ky + i) * (size_t)(kx * (kx + 1) / 2);
             const int total = kx * (kx + 1) / 2;
-            int col = 0, row = tid;  // entry tid: column 0 holds rows 0 .. kx-1
-            while (col < kx && row >= kx) {  // past the end of column col: continue at row col + 1
-                row = row - kx + col + 1;
-                ++col;
-            }
+            const unsigned ku = (unsigned)kx;
+            auto pcol = [&](unsigned q) { return __umul24(q, ku) - (__umul24(q, q - 1u) >> 1); };
+            const float bq = 2.f * kx + 1.f;
             // 8 entries per batch: their LDS reads are issued together, then the stores
             for (int e0 = tid; e0 < total; e0 += 8 * 512) {
                 int src[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    src[u] = (col < kx) ? tile_index(row >> 5, col >> 5, TR) * TSZ + (row & 31) * TLD + (col & 31) : 0;
-                    row += 512;  // advance 512 entries down the packed columns
-                    while (col < kx && row >= kx) {
-                        row = row - kx + col + 1;
-                        ++col;
-                    }
+                    const unsigned e = (unsigned)min(e0 + 512 * u, total - 1);
+                    unsigned q = (unsigned)max(
+                        (int)((bq - __builtin_amdgcn_sqrtf(fmaxf(bq * bq - 8.f * (float)e, 0.f))) * 0.5f), 0);
+                    q = min(q, ku - 1u);
+                    q += (unsigned)((q + 1u < ku) & (pcol(q + 1u) <= e));
+                    q -= (unsigned)((q > 0u) & (pcol(q) > e));
+                    const int col = (int)q, row = (int)min(q + e - pcol(q), ku - 1u);
+                    src[u] = tile_index(row >> 5, col >> 5, TR) * TSZ + (row & 31) * TLD + (col & 31);
                 }
                 float v[8];
 #pragma unroll
