@@ -540,21 +540,41 @@ __device__ __forceinline__ void bwdmc_block(const T *__restrict__ P, const float
     // last tile is loaded again at the end of the range): a conditional load would make the
     // compiler wait for all outstanding loads where the paths join.  With three buffers the loads
     // of tile t+2 are issued before the stores of tile t, so they do not queue behind its writes.
+    // The loop runs whole rounds with no early exit and the last tiles follow it, and the prologue
+    // loads keep their order: otherwise the compiler's wait analysis loses track of which loads a
+    // tile needs and waits at the top of the loop for every outstanding load and store.
     if (t0 >= t1) return;
     if constexpr (NBUF == 3) {
+        const int tfull = t0 + (t1 - t0) / 3 * 3;
         load_tile(t0, buf0, m0);
+        __builtin_amdgcn_sched_barrier(0);
         load_tile(min(t0 + 1, t1 - 1), buf1, m1);
-        for (int vt = t0; vt < t1; vt += 3) {
+        __builtin_amdgcn_sched_barrier(0);
+        for (int vt = t0; vt < tfull; vt += 3) {
             load_tile(min(vt + 2, t1 - 1), buf2, m2);
             compute_store(vt, buf0, m0);
-            if (vt + 1 >= t1) break;
             load_tile(min(vt + 3, t1 - 1), buf0, m0);
             compute_store(vt + 1, buf1, m1);
-            if (vt + 2 >= t1) break;
             load_tile(min(vt + 4, t1 - 1), buf1, m1);
             compute_store(vt + 2, buf2, m2);
         }
+        if (tfull < t1) {  // tiles tfull (in buf0) and tfull + 1 (in buf1) are loaded
+            compute_store(tfull, buf0, m0);
+            if (tfull + 1 < t1) compute_store(tfull + 1, buf1, m1);
+        }
+    } else if constexpr (KS < 8) {
+        // (a tail after the loop makes these instances spill: the last round is predicated instead)
+        load_tile(t0, buf0, m0);
+        __builtin_amdgcn_sched_barrier(0);
+        for (int vt = t0; vt < t1; vt += 2) {
+            load_tile(min(vt + 1, t1 - 1), buf1, m1);
+            compute_store(vt, buf0, m0);
+            load_tile(min(vt + 2, t1 - 1), buf0, m0);
+            if (vt + 1 < t1) compute_store(vt + 1, buf1, m1);
+        }
     } else {
+        // at KS = 8 only the loop with an early exit fits the register file (it keeps the wait for
+        // every outstanding load at the top of each round)
         load_tile(t0, buf0, m0);
         for (int vt = t0; vt < t1; vt += 2) {
             load_tile(min(vt + 1, t1 - 1), buf1, m1);
@@ -708,21 +728,22 @@ __device__ __forceinline__ void bwdk_block(const float *__restrict__ P, const fl
     };
     BkStep b0, b1, b2, b3;
     const int last = nsteps - 1;
+    // rounds of four with no early exit (the last round predicated), as in the backward above
     load_step(0, b0);
+    __builtin_amdgcn_sched_barrier(0);
     load_step(min(1, last), b1);
+    __builtin_amdgcn_sched_barrier(0);
     load_step(min(2, last), b2);
+    __builtin_amdgcn_sched_barrier(0);
     for (int st = 0; st < nsteps; st += 4) {
         load_step(min(st + 3, last), b3);
         step(st, b0);
-        if (st + 1 >= nsteps) break;
         load_step(min(st + 4, last), b0);
-        step(st + 1, b1);
-        if (st + 2 >= nsteps) break;
+        if (st + 1 < nsteps) step(st + 1, b1);
         load_step(min(st + 5, last), b1);
-        step(st + 2, b2);
-        if (st + 3 >= nsteps) break;
+        if (st + 2 < nsteps) step(st + 2, b2);
         load_step(min(st + 6, last), b2);
-        step(st + 3, b3);
+        if (st + 3 < nsteps) step(st + 3, b3);
     }
 }
 
@@ -866,8 +887,9 @@ __device__ __forceinline__ void x3r_block(const float *__restrict__ P, const flo
             float x[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
+                // the mass is masked, not the product, so the LDS reads are unconditional and issued together
                 const float pv = Ps[(8 * g4 + i) * pstride + srow_c];
-                x[i] = (srow_ok && 8 * g4 + i < vrem) ? pv * mv[i] : 0.f;
+                x[i] = pv * ((srow_ok && 8 * g4 + i < vrem) ? mv[i] : 0.f);
             }
             uint32_t w[4][3];
 #pragma unroll
@@ -902,31 +924,46 @@ __device__ __forceinline__ void x3r_block(const float *__restrict__ P, const flo
         }
     };
 
-    // Per iteration t: wait for stage t (stage t + 1 may stay in flight), barrier (stage t visible;
+    // Per stage t: wait for stage t (stage t + 1 may stay in flight), barrier (stage t visible;
     // every wave done with stage t - 1, so its ring slot, the split buffer and its feature registers
     // are free), issue stage t + 2 into them, split, barrier, products.  The three feature buffers
     // rotate by unrolling; prefetches past the chunk reload its last stage (the same bytes into the
     // same places), and every load has landed before the workgroup ends (its LDS is then reused).
+    // The loop runs whole triples and has no early exit, the last one or two stages follow it: an exit
+    // edge back into the loop header, or prologue loads reordered across the two stages, leaves the
+    // compiler's wait analysis unable to tell which loads stage t needs, and it then waits for all of
+    // them, the stage t + 2 prefetch included.
     f32x4 f0[RFF], f1[RFF], f2[RFF];
     constexpr int VPS = RFL + RFF;  // vector-memory operations per stage
     if (nst <= 0) return;
     issue(0, f0);
+    __builtin_amdgcn_sched_barrier(0);
     issue(min(1, nst - 1), f1);
-    for (int t = 0; t < nst; t += 3) {
+    __builtin_amdgcn_sched_barrier(0);
+    const int nfull = nst - nst % 3;
+    for (int t = 0; t < nfull; t += 3) {
         wait_vmcnt<VPS>();
         lds_barrier();
         issue(min(t + 2, nst - 1), f2);
         stage(t, f0);
-        if (t + 1 >= nst) break;
         wait_vmcnt<VPS>();
         lds_barrier();
         issue(min(t + 3, nst - 1), f0);
         stage(t + 1, f1);
-        if (t + 2 >= nst) break;
         wait_vmcnt<VPS>();
         lds_barrier();
         issue(min(t + 4, nst - 1), f1);
         stage(t + 2, f2);
+    }
+    if (nst % 3 != 0) {  // stages nfull (in f0) and nfull + 1 (in f1) are issued
+        wait_vmcnt<VPS>();
+        lds_barrier();
+        stage(nfull, f0);
+        if (nst % 3 == 2) {
+            wait_vmcnt<0>();
+            lds_barrier();
+            stage(nfull + 1, f1);
+        }
     }
     wait_vmcnt<0>();
 

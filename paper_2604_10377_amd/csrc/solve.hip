@@ -406,20 +406,30 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint products for one pair and one CB-column block of d:
+// Adjoint products for one pair and one CB-column block of d (k_x, k_y <= 64):
 //   W = V^T C + C^T V,  dA = V^T B - W A,  dB = V A.
-// V, C, W and the A, B column blocks are staged in LDS; matrix-core loops
-// read their operands in batches of GU steps.
+// V, C and W are staged in LDS as 64 x 64 tiles and the A, B column blocks as
+// 64 x CB tiles, all zero past k_x / k_y, so the matrix-core loops read every
+// operand unconditionally and steps past k add exact zeros.  NS batches of 8
+// steps (8 NS >= max(k_x, k_y)) are unrolled; each product accumulates in two
+// independent chains (even and odd steps) that are added at the end.  Rows of
+// the 64 x 64 tiles are 65 floats apart (the dB operand walks down a column),
+// and each array of a pair read by the two halves of a wave in the same
+// instruction starts 32 floats off the other's banks.
 // ---------------------------------------------------------------------------
-template <int KM, int CB>
+constexpr int ADJ_KM = 64, ADJ_RS = ADJ_KM + 1, ADJ_T = ADJ_KM * ADJ_RS + 32;
+
+template <int CB, int NS>
 __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ V, const float *__restrict__ C,
                                                       const float *__restrict__ A, const float *__restrict__ B,
                                                       int kx, int ky, int d, int dblocks,
                                                       const float *__restrict__ dlam_part, float *__restrict__ dlam,
                                                       float *__restrict__ dA, float *__restrict__ dB)
 {
-    __shared__ float sV[KM * KM], sC[KM * KM], sW[KM * KM];
-    __shared__ float sA[KM * CB], sB[KM * CB];
+    static_assert(NS >= 1 && 8 * NS <= ADJ_KM, "steps");
+    constexpr int KM = ADJ_KM, RS = ADJ_RS;
+    __shared__ float sV[ADJ_T], sC[ADJ_T], sW[ADJ_T];  // sW holds -W
+    __shared__ float sA[KM * CB + 32], sB[KM * CB];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, l32 = lane & 31;
     const int p = blockIdx.x / dblocks, db = blockIdx.x % dblocks;
@@ -429,40 +439,41 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
     const float *Cp = C + (size_t)p * ky * kx;
     const float *Ap = A + (size_t)p * kx * d;
     const float *Bp = B + (size_t)p * ky * d;
-    // staging: every load of the workgroup's operands is issued before the first
-    // LDS write (fixed counts, clamped addresses, masked at the write)
-    constexpr int NVC = (KM * KM + 255) / 256, NAB = KM * CB / 256;
-    const int nvc = ky * kx;
+
+    // staging: every load issued before the first LDS write, from clamped addresses; values outside the
+    // matrices are cleared by a bit mask (a select would let the compiler put the load under a branch)
+    constexpr int NVC = KM * KM / 256, NAB = KM * CB / 256;
     float rv[NVC], rc[NVC], ra[NAB], rb[NAB];
 #pragma unroll
     for (int u = 0; u < NVC; ++u) {
-        const int e = min((int)threadIdx.x + 256 * u, nvc - 1);
-        rv[u] = Vp[e];
-        rc[u] = Cp[e];
+        const int e = threadIdx.x + 256 * u, t = e / KM, m = e % KM;
+        const int src = min(t, ky - 1) * kx + min(m, kx - 1);
+        rv[u] = Vp[src];
+        rc[u] = Cp[src];
     }
 #pragma unroll
     for (int u = 0; u < NAB; ++u) {
-        const int e = threadIdx.x + 256 * u;
-        const int rr = e / CB, cc = min(e % CB, dw - 1);
+        const int e = threadIdx.x + 256 * u, rr = e / CB, cc = min(e % CB, dw - 1);
         ra[u] = Ap[(size_t)min(rr, kx - 1) * d + d0 + cc];
         rb[u] = Bp[(size_t)min(rr, ky - 1) * d + d0 + cc];
     }
     const bool sum_dlam = db == 0 && dlam && wave == 0;
-    const float dl = (sum_dlam && lane < ky) ? dlam_part[(size_t)p * ky + lane] : 0.f;  // k_y <= KM <= 64
+    const float dl = (sum_dlam && lane < ky) ? dlam_part[(size_t)p * ky + lane] : 0.f;  // k_y <= 64
+    auto keep = [](float x, bool ok) { return __uint_as_float(__float_as_uint(x) & (ok ? ~0u : 0u)); };
 #pragma unroll
     for (int u = 0; u < NVC; ++u) {
-        const int e = threadIdx.x + 256 * u;
-        if (e < nvc) {
-            sV[e] = rv[u];
-            sC[e] = rc[u];
-        }
+        const int e = threadIdx.x + 256 * u, t = e / KM, m = e % KM;
+        const bool ok = t < ky && m < kx;
+        sV[t * RS + m] = keep(rv[u], ok);
+        sC[t * RS + m] = keep(rc[u], ok);
+        sW[t * RS + m] = 0.f;  // W tiles beyond k_x are never written
     }
 #pragma unroll
     for (int u = 0; u < NAB; ++u) {
-        const int e = threadIdx.x + 256 * u;
+        const int e = threadIdx.x + 256 * u, rr = e / CB;
         const bool cin = (e % CB) < dw;
-        sA[e] = cin ? ra[u] : 0.f;
-        sB[e] = cin ? rb[u] : 0.f;
+        sA[e] = keep(ra[u], cin && rr < kx);
+        sB[e] = keep(rb[u], cin && rr < ky);
     }
     if (sum_dlam) {
         const float s = wave_sum(dl);
@@ -471,85 +482,57 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *__restrict__ 
     __syncthreads();
 
     const int TI = (kx + 31) / 32, TY = (ky + 31) / 32;
-    if (wave < TI * TI) {  // W tiles (TI*TI <= 4)
+    if (wave < TI * TI) {  // W tiles (TI*TI <= 4); half 0: V^T C, half 1: C^T V (the matrix-core K pair)
         const int I = wave / TI, J = wave % TI;
         const int m = I * 32 + l32, nn = J * 32 + l32;
-        const bool mok = m < kx, nok = nn < kx;
-        const float *Xs = half == 0 ? sV : sC;  // half 0: V^T C, half 1: C^T V
+        const float *Xs = half == 0 ? sV : sC;
         const float *Ys = half == 0 ? sC : sV;
-        f32x16 acc = zero16();
-        for (int t0 = 0; t0 < ky; t0 += GU) {
-            float a[GU], b[GU];
+        f32x16 acc0 = zero16(), acc1 = zero16();
 #pragma unroll
-            for (int u = 0; u < GU; ++u) {
-                const int t = t0 + u;
-                a[u] = (mok && t < ky) ? Xs[t * kx + m] : 0.f;
-                b[u] = (nok && t < ky) ? Ys[t * kx + nn] : 0.f;
-            }
-#pragma unroll
-            for (int u = 0; u < GU; ++u) acc = mfma32x32x2(a[u], b[u], acc);
+        for (int t = 0; t < 8 * NS; t += 2) {
+            acc0 = mfma32x32x2(Xs[t * RS + m], Ys[t * RS + nn], acc0);
+            acc1 = mfma32x32x2(Xs[(t + 1) * RS + m], Ys[(t + 1) * RS + nn], acc1);
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = I * 32 + acc32_row(r, lane);
-            if (row < kx && nok) sW[row * kx + nn] = acc[r];
-        }
+        for (int r = 0; r < 16; ++r) sW[(I * 32 + acc32_row(r, lane)) * RS + nn] = -(acc0[r] + acc1[r]);
     }
     __syncthreads();
 
     constexpr int NCB = CB / 32;  // 32-column tiles per block
     const int nA = TI * NCB, nB = TY * NCB;
     for (int job = wave; job < nA + nB; job += 4) {
-        f32x16 acc = zero16();
+        f32x16 acc0 = zero16(), acc1 = zero16();
         if (job < nA) {
+            // half 0: (V^T B)[m][col] over t < k_y; half 1: (-W A)[m][col] over t < k_x (W symmetric)
             const int I = job / NCB, cblk = job % NCB;
             const int m = I * 32 + l32, cl = cblk * 32 + l32, col = d0 + cl;
-            const bool mok = m < kx, cok = col < d;
-            // half 0: (V^T B)[m][col] over t < ky; half 1: -(W A)[m][col] over t < kx (W symmetric)
             const float *Xs = half == 0 ? sV : sW;
             const float *Ys = half == 0 ? sB : sA;
-            const int tn = half == 0 ? ky : kx;
-            const float sg = half == 0 ? 1.f : -1.f;
-            const int steps = max(kx, ky);
-            for (int t0 = 0; t0 < steps; t0 += GU) {
-                float a[GU], b[GU];
 #pragma unroll
-                for (int u = 0; u < GU; ++u) {
-                    const int t = t0 + u;
-                    const bool ok = t < tn;
-                    a[u] = (mok && ok) ? sg * Xs[t * kx + m] : 0.f;
-                    b[u] = ok ? Ys[t * CB + cl] : 0.f;
-                }
-#pragma unroll
-                for (int u = 0; u < GU; ++u) acc = mfma32x32x2(a[u], b[u], acc);
+            for (int t = 0; t < 8 * NS; t += 2) {
+                acc0 = mfma32x32x2(Xs[t * RS + m], Ys[t * CB + cl], acc0);
+                acc1 = mfma32x32x2(Xs[(t + 1) * RS + m], Ys[(t + 1) * CB + cl], acc1);
             }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = I * 32 + acc32_row(r, lane);
-                if (row < kx && cok) dA[((size_t)p * kx + row) * d + col] = acc[r];
+                if (row < kx && col < d) dA[((size_t)p * kx + row) * d + col] = acc0[r] + acc1[r];
             }
         } else {
+            // (V A)[m][col]: half h takes the terms kk = 2 s + h
             const int jb = job - nA;
             const int I = jb / NCB, cblk = jb % NCB;
             const int m = I * 32 + l32, cl = cblk * 32 + l32, col = d0 + cl;
-            const bool mok = m < ky, cok = col < d;
-            const int KH = (kx + 1) >> 1;
-            for (int t0 = 0; t0 < KH; t0 += GU) {
-                float a[GU], b[GU];
 #pragma unroll
-                for (int u = 0; u < GU; ++u) {
-                    const int kk = half * KH + t0 + u;
-                    const bool ok = (t0 + u < KH) && kk < kx;
-                    a[u] = (mok && ok) ? sV[m * kx + kk] : 0.f;
-                    b[u] = ok ? sA[kk * CB + cl] : 0.f;
-                }
-#pragma unroll
-                for (int u = 0; u < GU; ++u) acc = mfma32x32x2(a[u], b[u], acc);
+            for (int s2 = 0; s2 < 4 * NS; s2 += 2) {
+                const int k0 = 2 * s2 + half, k1 = k0 + 2;
+                acc0 = mfma32x32x2(sV[m * RS + k0], sA[k0 * CB + cl], acc0);
+                acc1 = mfma32x32x2(sV[m * RS + k1], sA[k1 * CB + cl], acc1);
             }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = I * 32 + acc32_row(r, lane);
-                if (row < ky && cok) dB[((size_t)p * ky + row) * d + col] = acc[r];
+                if (row < ky && col < d) dB[((size_t)p * ky + row) * d + col] = acc0[r] + acc1[r];
             }
         }
     }
@@ -697,8 +680,21 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
     if (kx <= kSmallK && ky <= kSmallK) {
         // 32-column blocks: twice the workgroups of 64-column ones (W is recomputed per block, k^3 flops)
         const int dblocks = (int)((d + 31) / 32);
-        hipLaunchKernelGGL((adjoint_kernel<kSmallK, 32>), dim3((unsigned)(P * dblocks)), dim3(256), 0, st, V, C, A, B,
-                           (int)kx, (int)ky, (int)d, dblocks, dl, dlam, dA, dB);
+        const dim3 grid((unsigned)(P * dblocks)), block(256);
+#define FMAP_ADJ(NS)                                                                                           \
+    hipLaunchKernelGGL((adjoint_kernel<32, NS>), grid, block, 0, st, V, C, A, B, (int)kx, (int)ky, (int)d, dblocks, \
+                       dl, dlam, dA, dB)
+        switch ((std::max(kx, ky) + 7) / 8) {
+        case 1: FMAP_ADJ(1); break;
+        case 2: FMAP_ADJ(2); break;
+        case 3: FMAP_ADJ(3); break;
+        case 4: FMAP_ADJ(4); break;
+        case 5: FMAP_ADJ(5); break;
+        case 6: FMAP_ADJ(6); break;
+        case 7: FMAP_ADJ(7); break;
+        default: FMAP_ADJ(8); break;
+        }
+#undef FMAP_ADJ
     } else {
         launch_adjoint_general(V, C, A, B, P, kx, ky, d, (float *)(base + L.W), dl, dlam, dA, dB, st);
     }
