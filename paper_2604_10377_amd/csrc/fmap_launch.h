@@ -104,6 +104,10 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
 void launch_trisolve_stored(const float *Lin, const float *rhs, const float *ex, const float *ey, const float *lam,
                             int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, int *info,
                             const float *Cfwd, float *dlam_part, const float *addend, hipStream_t st);
+// The same for k_x <= 64: one wave per system, both substitutions in registers.
+void launch_trisolve_small(const float *Lin, const float *rhs, const float *ex, const float *ey, const float *lam,
+                           int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, int *info,
+                           const float *Cfwd, float *dlam_part, const float *addend, hipStream_t st);
 void launch_rowsolve_tiled(int mode, const float *K, const float *Lin, const float *rhs, const float *ex,
                            const float *ey, const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx,
                            int64_t ky, float *out, float *Lout, int *info, const float *Cfwd, float *dlam_part,

@@ -10,7 +10,9 @@
 //                    form one batched launch (Eq. (8)); the [k,k,k] left-hand
 //                    side of Eq. (9) is never materialised.
 // Reverse mode (dC given), per pair:
-//   rowsolve_kernel  v_i = S_i^{-1} dC_i with the stored factor (or a refactor)
+//   v_i = S_i^{-1} dC_i: with the stored factor by the triangular solves of
+//   trisolve_small_kernel (solve_stored.hip), or refactorised here
+//   (rowsolve_kernel, reverse mode)
 //   adjoint_kernel   W = V^T C + C^T V, dA = V^T B - W A, dB = V A.
 //
 // Register Cholesky: lane j of the wave holds row j of S_i (entries q <= j;
@@ -24,7 +26,7 @@
 
 namespace fmap {
 
-enum { RS_FWD = 0, RS_BWD_STORED = 1, RS_BWD_RECOMPUTE = 2 };
+enum { RS_FWD = 0, RS_BWD_RECOMPUTE = 2 };  // (value 1, the stored-factor mode, is served in solve_stored.hip)
 
 // ---------------------------------------------------------------------------
 // K = A A^T and (optionally) R = B A^T.  One workgroup per 32x32 output tile;
@@ -197,14 +199,15 @@ __device__ __forceinline__ float uniform(float v) { return __int_as_float(__buil
 // column in order (the same roundings as one column at a time).  The forward
 // substitution L y = r rides along.  The factor is then staged in LDS as full
 // rows, from which the packed output is written with consecutive lanes on
-// consecutive elements and each lane takes column j of L (row j of L^T) for
-// the back substitution, which needs only readlanes.  All control flow is
+// consecutive elements and each lane takes column j of L (row j of L^T),
+// scaled by the inverse pivots, for the back substitution: one readlane and
+// one fused multiply-add per column.  All control flow is
 // wave-uniform; a failed pivot is recorded (LAPACK info) and the system's
 // outputs become NaN.
 // ---------------------------------------------------------------------------
 template <int KMAX> struct RowsolveLds {
     static constexpr int KP = KMAX + 4;                    // staged factor row stride (floats)
-    static constexpr int PER_WAVE = 4 * KMAX + KMAX * KP + 3 * KMAX;  // block broadcast, staged factor, scalars
+    static constexpr int PER_WAVE = 4 * KMAX + KMAX * KP + 2 * KMAX;  // block broadcast, staged factor, scalars
 };
 
 template <int KMAX, int MODE>
@@ -221,9 +224,9 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     const int W = blockDim.x >> 6;
     float *s_bcw = s_rs + w * RowsolveLds<KMAX>::PER_WAVE;  // [KMAX][4]: the block's columns, row by row
     float *s_Lw = s_bcw + 4 * KMAX;                          // [KMAX][KP]: rows of L
-    // per-column scalars (1 / L_cc, y_c, c_c): lane 0 records them as the serial steps produce them,
-    // and each lane reads its own entry afterwards (no per-column lane masks)
-    float *s_inv = s_Lw + KMAX * KP, *s_y = s_inv + KMAX, *s_c = s_y + KMAX;
+    // per-column scalars (1 / L_cc, y_c): lane 0 records them as the serial steps produce them, and
+    // each lane reads its own entry afterwards (no per-column lane masks)
+    float *s_inv = s_Lw + KMAX * KP, *s_y = s_inv + KMAX;
     const int rgroups = (ky + W - 1) / W;
     const int p = blockIdx.x / rgroups;
     const int i = (blockIdx.x % rgroups) * W + w;
@@ -238,15 +241,7 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     const float exj = ex[(size_t)p * kx + jc];
     const float eyj = ey[(size_t)p * ky + min(j, ky - 1)];
     float sr[KMAX];
-    if (MODE == RS_BWD_STORED) {
-        // packed column-major factor: for each q the lanes read consecutive addresses
-        const float *Lp = Lin + ((size_t)p * ky + i) * T;
-#pragma unroll
-        for (int q = 0; q < KMAX; ++q) {
-            const int qc = min(q, jc);
-            sr[q] = Lp[packed_col(qc, kx) + jc - qc];
-        }
-    } else {
+    {
         // K is symmetric: row j is read as column j, so for each q the lanes read consecutive addresses
         const float *Kp = K + (size_t)p * kx * kx;
 #pragma unroll
@@ -278,13 +273,13 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
         const float v = (jok && q <= j) ? sr[q] : 0.f;
-        sr[q] = (q == j) ? (jok ? (MODE != RS_BWD_STORED ? v + shift : v) : 1.f) : v;
+        sr[q] = (q == j) ? (jok ? v + shift : 1.f) : v;
     }
     float r = jok ? rin : 0.f;
 
     // Lanes j < c take garbage in column c (and in their entries above the diagonal); none of it is
     // read: a lane's later use of column c is for rows below c, and y_j was recorded at step j.
-    if (MODE != RS_BWD_STORED) {
+    {
 #pragma unroll
         for (int c0 = 0; c0 < KMAX; c0 += 4) {
             if (c0 < kx) {  // blocks past k_x hold only identity rows
@@ -328,20 +323,6 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
                 __builtin_amdgcn_sched_barrier(0);  // blocks are scheduled one at a time (register pressure)
             }
         }
-    } else {
-#pragma unroll
-        for (int c = 0; c < KMAX; ++c) {
-            const float dg = uniform(readlane(sr[c], c));
-            const bool bad = !(dg > 0.f) || !isfinite(dg);
-            fail = (bad && fail == 0) ? c + 1 : fail;
-            const float inv = uniform(__builtin_amdgcn_rcpf(dg));
-            const float yc = uniform(readlane(r, c) * inv);
-            if (j == 0) {
-                s_inv[c] = inv;
-                s_y[c] = yc;
-            }
-            r -= sr[c] * yc;  // lanes j <= c: final entries already recorded
-        }
     }
     fail = __builtin_amdgcn_readfirstlane(fail);
 
@@ -373,23 +354,21 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
 
     float cv = NAN;
     if (fail == 0) {
-        // column j of L: L[c][j] for c > j
+        // back substitution L^T x = y with column j of L (L[c][j], c > j) scaled by 1 / L_cc up front:
+        // y_j -= (L_cj / L_cc) y_c for c descending, then x_j = y_j / L_jj (a lane's value is final once
+        // its step has passed).  Columns of blocks past k_x were never factorised and their scalars
+        // never recorded: their scales and values are taken as 0 by selects, so no stale value enters.
         const int jr = min(j, KMAX - 1);
+        const float myinv = s_inv[jr];
+        float y = jok ? s_y[jr] : 0.f;
 #pragma unroll
-        for (int c = 0; c < KMAX; ++c) sr[c] = (c > j) ? s_Lw[c * KP + jr] : 0.f;
-        const int jr2 = min(j, KMAX - 1);
-        float y = s_y[jr2];
-        const float myinv = s_inv[jr2];
-#pragma unroll
-        for (int c = KMAX - 1; c >= 0; --c) {
-            // columns of blocks past k_x were never factorised (their scalars were never recorded):
-            // their solution entries are 0, taken by a select so that no stale value enters
-            const float cc = (c < kx) ? uniform(readlane(y, c) * readlane(myinv, c)) : 0.f;
-            if (j == 0) s_c[c] = cc;
-            y -= sr[c] * cc;
+        for (int c = 0; c < KMAX; ++c) {
+            const float ic = (c < kx) ? readlane(myinv, c) : 0.f;
+            sr[c] = (c > j) ? s_Lw[c * KP + jr] * ic : 0.f;
         }
-        __builtin_amdgcn_wave_barrier();
-        cv = s_c[jr2];
+#pragma unroll
+        for (int c = KMAX - 1; c >= 0; --c) y = fmaf(-sr[c], readlane(y, c), y);
+        cv = y * myinv;
     }
 
     if (jok) {
@@ -644,8 +623,8 @@ hipError_t launch_solve(const float *A, const float *B, const float *ex, const f
     for (int it = 0; it < refine_steps; ++it) {
         launch_residual64(C, K64, R64, ex, ey, lam, mask_kind, gamma, P, kx, ky, rho, st);
         if (kx <= kSmallK)
-            launch_rowsolve<RS_BWD_STORED>(nullptr, factors, rho, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, nullptr,
-                                           nullptr, nullptr, nullptr, st, C);
+            launch_trisolve_small(factors, rho, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, nullptr, nullptr, nullptr,
+                                  C, st);
         else
             launch_trisolve_stored(factors, rho, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, nullptr, nullptr, nullptr,
                                    C, st);
@@ -664,8 +643,7 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
     const bool small = kx <= kSmallK;
     if (factors) {
         if (small)
-            launch_rowsolve<RS_BWD_STORED>(nullptr, factors, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, nullptr,
-                                           info, C, dl, st);
+            launch_trisolve_small(factors, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, info, C, dl, nullptr, st);
         else
             launch_trisolve_stored(factors, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, info, C, dl, nullptr, st);
     } else {

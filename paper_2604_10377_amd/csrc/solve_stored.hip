@@ -1,10 +1,11 @@
-// Row solves with stored float32 factors for 64 < k_x <= 319: the reverse
-// mode's S_i v_i = g_i and the refinement correction S_i delta_i = rho_i
-// (Eqs. (6), (7) with the factor of Eq. (5) kept from the forward pass).
+// Row solves with stored float32 factors: the reverse mode's S_i v_i = g_i
+// and the refinement correction S_i delta_i = rho_i (Eqs. (6), (7) with the
+// factor of Eq. (5) kept from the forward pass).  trisolve_stored_kernel
+// serves 64 < k_x <= 319, trisolve_small_kernel (at the end) k_x <= 64.
 //
 // With the factor known, a system is two triangular solves over k_x^2/2
 // stored floats, so the work is streaming the factor, once per substitution.
-// One wave per system; lane j holds rows j, j + 64, ... (NS slots).  The factor
+// Large k_x: one wave per system; lane j holds rows j, j + 64, ... (NS slots).  The factor
 // is packed lower, column-major, so column c is contiguous: the forward
 // substitution L y = r goes column by column (y_c = r_c / L_cc, then the rows
 // below subtract L_qc y_c), the back substitution L^T x = y is a dot product
@@ -201,6 +202,132 @@ void launch_trisolve_stored(const float *Lin, const float *rhs, const float *ex,
     default: FMAP_TS(5); break;
     }
 #undef FMAP_TS
+}
+
+// ---------------------------------------------------------------------------
+// The same two solves for k_x <= 64 (KMAX >= k_x): one wave per system, lane j
+// holding row j and column j of the factor, loaded straight from the packed
+// storage (row entries: for each q the lanes read consecutive addresses;
+// column entries: each lane walks its own contiguous column).  The
+// off-diagonal entries are scaled by the inverse pivots up front, so each
+// substitution step is a broadcast of one lane's running value and one fused
+// multiply-add:
+//   forward  L y = r:    r_j -= (L_jc / L_cc) r_c   (c ascending),  y_j = r_j / L_jj
+//   backward L^T x = y:  y_j -= (L_cj / L_cc) y_c   (c descending), x_j = y_j / L_jj
+// (a lane's own value is final once its step has passed).  Rows k_x <= j <
+// KMAX are identity rows: no k_x checks in the loops.
+// ---------------------------------------------------------------------------
+template <int KMAX>
+__global__ __launch_bounds__(256) void trisolve_small_kernel(const float *__restrict__ Lin,
+                                                            const float *__restrict__ rhs,
+                                                            const float *__restrict__ ex, const float *__restrict__ ey,
+                                                            const float *__restrict__ lam, int mask_kind, float gamma,
+                                                            int kx, int ky, int nsys, float *out,
+                                                            int *__restrict__ info, const float *__restrict__ Cfwd,
+                                                            float *__restrict__ dlam_part, const float *addend)
+{
+    static_assert(KMAX % 8 == 0 && KMAX <= 64, "register row length");
+    const int j = threadIdx.x & 63;
+    // the system index in a scalar register, so the buffer descriptor below is one per wave
+    const int sys = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (sys >= nsys) return;  // wave-uniform; no block-level barrier below
+    const int p = sys / ky, i = sys - p * ky;
+    const float *Lp = Lin + (size_t)sys * (kx * (kx + 1) / 2);
+    const bool jok = j < kx;
+    const int jc = jok ? j : kx - 1;
+
+    // every input load first, from clamped addresses (entries outside the triangle are masked below)
+    const float lamv = lam[p];
+    const float muy = ey[(size_t)p * ky + i];
+    const float exj = ex[(size_t)p * kx + jc];
+    const float eyj = ey[(size_t)p * ky + min(j, ky - 1)];
+    const float rin = rhs[(size_t)sys * kx + jc];
+    const int pj = pcol(jc, kx);  // column jc starts here; its diagonal entry first
+    const float dgl = Lp[pj];
+    // element (row, col) of the packed factor is at pcol(col) + row - col: with a buffer descriptor the
+    // row loads take a lane offset of 4 jc and a scalar offset per column, the column loads a lane base
+    // and a scalar offset per row, so no load needs vector address arithmetic.  Lanes outside the
+    // triangle read neighbouring entries of the same factor (masked below); the descriptor's range
+    // bounds every access to this system's factor.
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)Lp, 0, (int)(kx * (kx + 1) / 2 * sizeof(float)), 0x00020000);
+    float rowv[KMAX], colv[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {  // rowv[q] = L[j][q] for q <= j, colv[q] = L[q][j] for q >= j
+        const int qc = min(q, kx - 1);
+        // (the builtin returns the 32 bits as an integer: reinterpreted, not converted)
+        rowv[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * jc, 4 * (pcol(qc, kx) - qc), 0));
+        colv[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * (pj - jc), 4 * qc, 0));
+    }
+
+    int fail = 0;
+    if (!(lamv >= 0.f) || !isfinite(lamv)) fail = -1;
+    MaskParams mp;
+    mp.kind = mask_kind;
+    mp.gamma = gamma;
+    mp.inv_scale = 1.f;
+    if (mask_kind == 1) {
+        float mx = fmaxf(jok ? exj : -INFINITY, j < ky ? eyj : -INFINITY);  // k_x <= 64
+        for (int q = j + 64; q < ky; q += 64) mx = fmaxf(mx, ey[(size_t)p * ky + q]);
+        mx = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_max(mx))));
+        if ((!(mx > 0.f) || !isfinite(mx)) && fail == 0) fail = -2;
+        mp.inv_scale = 1.f / mx;
+    }
+    // pivots: the first non-positive or non-finite one is reported (LAPACK info)
+    const float dg = jok ? dgl : 1.f;
+    const uint64_t bad = __ballot(!(dg > 0.f) || !isfinite(dg));
+    if (fail == 0 && bad != 0) fail = (int)__builtin_ctzll(bad) + 1;
+    fail = __builtin_amdgcn_readfirstlane(fail);
+    const float inv = __builtin_amdgcn_rcpf(dg);
+
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+        const float iq = readlane(inv, q);
+        rowv[q] = (jok && q < j) ? rowv[q] * iq : 0.f;
+        colv[q] = (jok && q > j) ? colv[q] * iq : 0.f;
+    }
+    float r = jok ? rin : 0.f;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) r = fmaf(-rowv[c], readlane(r, c), r);
+    float y = r * inv;
+#pragma unroll
+    for (int c = KMAX - 1; c >= 0; --c) y = fmaf(-colv[c], readlane(y, c), y);
+    const float x = y * inv;
+
+    const float cv = fail == 0 ? x : NAN;
+    if (jok) {
+        const size_t o = (size_t)sys * kx + j;
+        out[o] = addend ? addend[o] + cv : cv;  // addend: refinement correction c += delta (in place)
+    }
+    if (info && j == 0) info[sys] = fail;
+    if (dlam_part) {
+        const float dval = (jok && fail == 0) ? mask_entry(muy, exj, mp) : 0.f;
+        const float term = jok ? cv * dval * Cfwd[(size_t)sys * kx + j] : 0.f;
+        const float sum = wave_sum(term);
+        if (j == 0) dlam_part[sys] = -sum;
+    }
+}
+
+void launch_trisolve_small(const float *Lin, const float *rhs, const float *ex, const float *ey, const float *lam,
+                           int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, int *info,
+                           const float *Cfwd, float *dlam_part, const float *addend, hipStream_t st)
+{
+    const int nsys = (int)(P * ky);
+    const dim3 grid((unsigned)((nsys + 3) / 4)), block(256);
+#define FMAP_TSS(KM)                                                                                              \
+    hipLaunchKernelGGL((trisolve_small_kernel<KM>), grid, block, 0, st, Lin, rhs, ex, ey, lam, mask_kind, gamma, \
+                       (int)kx, (int)ky, nsys, out, info, Cfwd, dlam_part, addend)
+    switch ((kx + 7) / 8) {
+    case 1: FMAP_TSS(8); break;
+    case 2: FMAP_TSS(16); break;
+    case 3: FMAP_TSS(24); break;
+    case 4: FMAP_TSS(32); break;
+    case 5: FMAP_TSS(40); break;
+    case 6: FMAP_TSS(48); break;
+    case 7: FMAP_TSS(56); break;
+    default: FMAP_TSS(64); break;
+    }
+#undef FMAP_TSS
 }
 
 }  // namespace fmap

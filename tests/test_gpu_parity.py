@@ -291,6 +291,36 @@ def test_solve_info_convention(F, dev):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("kx", [50, 150])
+def test_solve_backward_stored_info_convention(F, dev, kx):
+    """Reverse mode with stored factors: a non-positive pivot (column 5) in one system's factor reports
+    info = 6 for that row system alone, an invalid lambda reports -1 for every row of its pair, and the
+    failed systems' solutions are NaN (the register path k_x <= 64 and the streaming path above)."""
+    import torch
+    P, ky, d = 2, 20, 2 * kx
+    A, B, ex, ey, lam = _spectral(4, P, kx, ky, d)
+    tA, tB, tex, tey, tl = (T(x, dev) for x in (A, B, ex, ey, lam))
+    C, fac, info, _ = F.fmap_solve(tA, tB, tex, tey, tl, 0, 0.5, store_factors=True)
+    assert (N(info) == 0).all()
+    tri = kx * (kx + 1) // 2
+    fac = fac.clone()
+    fac[0, 3 * tri + 5 * kx - (5 * 4) // 2] = -1.0  # diagonal entry of column 5, row system 3 of pair 0
+    lam_bad = tl.clone()
+    lam_bad[1] = -1.0
+    ib = torch.full((P, ky), 12345, dtype=torch.int32, device=dev)
+    dC = np.random.default_rng(6).standard_normal((P, ky, kx)).astype(np.float32)
+    dA, dB, _ = F.fmap_solve_backward(T(dC, dev), tA, tB, C, tex, tey, lam_bad, 0, 0.5, fac, info=ib)
+    expect = np.zeros((P, ky), np.int32)
+    expect[0, 3] = 6
+    expect[1, :] = -1
+    np.testing.assert_array_equal(N(ib), expect)
+    dB = N(dB)
+    others = np.arange(ky) != 3
+    assert np.isnan(dB[0, 3]).all() and np.isfinite(dB[0, others]).all()
+    assert np.isnan(N(dA)[1]).all() and np.isnan(dB[1]).all()
+    torch.cuda.synchronize()
+
+
 # ----------------------------------------------------------------------------- whole pipeline
 
 def _pipeline_gpu(F, b, dev, bwd="stored"):
