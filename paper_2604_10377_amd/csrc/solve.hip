@@ -199,15 +199,14 @@ __device__ __forceinline__ float uniform(float v) { return __int_as_float(__buil
 // column in order (the same roundings as one column at a time).  The forward
 // substitution L y = r rides along.  The factor is then staged in LDS as full
 // rows, from which the packed output is written with consecutive lanes on
-// consecutive elements and each lane takes column j of L (row j of L^T),
-// scaled by the inverse pivots, for the back substitution: one readlane and
-// one fused multiply-add per column.  All control flow is
+// consecutive elements and each lane takes column j of L (row j of L^T) for
+// the back substitution, which needs only readlanes.  All control flow is
 // wave-uniform; a failed pivot is recorded (LAPACK info) and the system's
 // outputs become NaN.
 // ---------------------------------------------------------------------------
 template <int KMAX> struct RowsolveLds {
     static constexpr int KP = KMAX + 4;                    // staged factor row stride (floats)
-    static constexpr int PER_WAVE = 4 * KMAX + KMAX * KP + 2 * KMAX;  // block broadcast, staged factor, scalars
+    static constexpr int PER_WAVE = 4 * KMAX + KMAX * KP + 3 * KMAX;  // block broadcast, staged factor, scalars
 };
 
 template <int KMAX, int MODE>
@@ -224,9 +223,9 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     const int W = blockDim.x >> 6;
     float *s_bcw = s_rs + w * RowsolveLds<KMAX>::PER_WAVE;  // [KMAX][4]: the block's columns, row by row
     float *s_Lw = s_bcw + 4 * KMAX;                          // [KMAX][KP]: rows of L
-    // per-column scalars (1 / L_cc, y_c): lane 0 records them as the serial steps produce them, and
-    // each lane reads its own entry afterwards (no per-column lane masks)
-    float *s_inv = s_Lw + KMAX * KP, *s_y = s_inv + KMAX;
+    // per-column scalars (1 / L_cc, y_c, c_c): lane 0 records them as the serial steps produce them,
+    // and each lane reads its own entry afterwards (no per-column lane masks)
+    float *s_inv = s_Lw + KMAX * KP, *s_y = s_inv + KMAX, *s_c = s_y + KMAX;
     const int rgroups = (ky + W - 1) / W;
     const int p = blockIdx.x / rgroups;
     const int i = (blockIdx.x % rgroups) * W + w;
@@ -354,21 +353,23 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
 
     float cv = NAN;
     if (fail == 0) {
-        // back substitution L^T x = y with column j of L (L[c][j], c > j) scaled by 1 / L_cc up front:
-        // y_j -= (L_cj / L_cc) y_c for c descending, then x_j = y_j / L_jj (a lane's value is final once
-        // its step has passed).  Columns of blocks past k_x were never factorised and their scalars
-        // never recorded: their scales and values are taken as 0 by selects, so no stale value enters.
+        // column j of L: L[c][j] for c > j
         const int jr = min(j, KMAX - 1);
-        const float myinv = s_inv[jr];
-        float y = jok ? s_y[jr] : 0.f;
 #pragma unroll
-        for (int c = 0; c < KMAX; ++c) {
-            const float ic = (c < kx) ? readlane(myinv, c) : 0.f;
-            sr[c] = (c > j) ? s_Lw[c * KP + jr] * ic : 0.f;
+        for (int c = 0; c < KMAX; ++c) sr[c] = (c > j) ? s_Lw[c * KP + jr] : 0.f;
+        const int jr2 = min(j, KMAX - 1);
+        float y = s_y[jr2];
+        const float myinv = s_inv[jr2];
+#pragma unroll
+        for (int c = KMAX - 1; c >= 0; --c) {
+            // columns of blocks past k_x were never factorised (their scalars were never recorded):
+            // their solution entries are 0, taken by a select so that no stale value enters
+            const float cc = (c < kx) ? uniform(readlane(y, c) * readlane(myinv, c)) : 0.f;
+            if (j == 0) s_c[c] = cc;
+            y -= sr[c] * cc;
         }
-#pragma unroll
-        for (int c = KMAX - 1; c >= 0; --c) y = fmaf(-sr[c], readlane(y, c), y);
-        cv = y * myinv;
+        __builtin_amdgcn_wave_barrier();
+        cv = s_c[jr2];
     }
 
     if (jok) {

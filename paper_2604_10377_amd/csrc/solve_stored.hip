@@ -206,9 +206,11 @@ void launch_trisolve_stored(const float *Lin, const float *rhs, const float *ex,
 
 // ---------------------------------------------------------------------------
 // The same two solves for k_x <= 64 (KMAX >= k_x): one wave per system, lane j
-// holding row j and column j of the factor, loaded straight from the packed
-// storage (row entries: for each q the lanes read consecutive addresses;
-// column entries: each lane walks its own contiguous column).  The
+// holding row j and column j of the factor.  The rows are loaded from the
+// packed storage (for each q the lanes read consecutive addresses) and the
+// columns come from them through LDS (row j written by lane j, column j read
+// back by lane j): loading the columns directly would have each lane walk its
+// own column, one cache line per lane and load instruction.  The
 // off-diagonal entries are scaled by the inverse pivots up front, so each
 // substitution step is a broadcast of one lane's running value and one fused
 // multiply-add:
@@ -217,6 +219,11 @@ void launch_trisolve_stored(const float *Lin, const float *rhs, const float *ex,
 // (a lane's own value is final once its step has passed).  Rows k_x <= j <
 // KMAX are identity rows: no k_x checks in the loops.
 // ---------------------------------------------------------------------------
+template <int KMAX> struct TrisolveLds {
+    static constexpr int KP = KMAX + 4;  // row stride (floats): 16-byte row writes, conflict-free column reads
+    static constexpr int PER_WAVE = KMAX * KP;
+};
+
 template <int KMAX>
 __global__ __launch_bounds__(256) void trisolve_small_kernel(const float *__restrict__ Lin,
                                                             const float *__restrict__ rhs,
@@ -245,19 +252,33 @@ __global__ __launch_bounds__(256) void trisolve_small_kernel(const float *__rest
     const int pj = pcol(jc, kx);  // column jc starts here; its diagonal entry first
     const float dgl = Lp[pj];
     // element (row, col) of the packed factor is at pcol(col) + row - col: with a buffer descriptor the
-    // row loads take a lane offset of 4 jc and a scalar offset per column, the column loads a lane base
-    // and a scalar offset per row, so no load needs vector address arithmetic.  Lanes outside the
-    // triangle read neighbouring entries of the same factor (masked below); the descriptor's range
-    // bounds every access to this system's factor.
+    // row loads take a lane offset of 4 jc and a scalar offset per column, so they need no vector
+    // address arithmetic.  Lanes outside the triangle read neighbouring entries of the same factor
+    // (masked below); the descriptor's range bounds every access to this system's factor.
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void *)Lp, 0, (int)(kx * (kx + 1) / 2 * sizeof(float)), 0x00020000);
     float rowv[KMAX], colv[KMAX];
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) {  // rowv[q] = L[j][q] for q <= j, colv[q] = L[q][j] for q >= j
+    for (int q = 0; q < KMAX; ++q) {  // rowv[q] = L[j][q] for q <= j
         const int qc = min(q, kx - 1);
         // (the builtin returns the 32 bits as an integer: reinterpreted, not converted)
         rowv[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * jc, 4 * (pcol(qc, kx) - qc), 0));
-        colv[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * (pj - jc), 4 * qc, 0));
+    }
+    // colv[q] = L[q][j] for q >= j: entry j of row q, through this wave's LDS tile
+    {
+        extern __shared__ __align__(16) float s_ts[];
+        constexpr int KP = TrisolveLds<KMAX>::KP;
+        float *sL = s_ts + (threadIdx.x >> 6) * TrisolveLds<KMAX>::PER_WAVE;
+        if (j < KMAX) {
+#pragma unroll
+            for (int q4 = 0; q4 < KMAX / 4; ++q4)
+                *reinterpret_cast<f32x4 *>(&sL[j * KP + 4 * q4]) =
+                    f32x4{rowv[4 * q4], rowv[4 * q4 + 1], rowv[4 * q4 + 2], rowv[4 * q4 + 3]};
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int jr = min(j, KMAX - 1);
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) colv[q] = sL[q * KP + jr];
     }
 
     int fail = 0;
@@ -314,9 +335,19 @@ void launch_trisolve_small(const float *Lin, const float *rhs, const float *ex, 
 {
     const int nsys = (int)(P * ky);
     const dim3 grid((unsigned)((nsys + 3) / 4)), block(256);
+    // dynamic LDS: 4 waves x KM (KM + 4) floats, at most 69.6 KB
 #define FMAP_TSS(KM)                                                                                              \
-    hipLaunchKernelGGL((trisolve_small_kernel<KM>), grid, block, 0, st, Lin, rhs, ex, ey, lam, mask_kind, gamma, \
-                       (int)kx, (int)ky, nsys, out, info, Cfwd, dlam_part, addend)
+    do {                                                                                                          \
+        const size_t lds_ = (size_t)4 * TrisolveLds<KM>::PER_WAVE * sizeof(float);                                \
+        static bool attr_ = false;                                                                                \
+        if (!attr_) {                                                                                             \
+            (void)hipFuncSetAttribute((const void *)trisolve_small_kernel<KM>,                                    \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_);                     \
+            attr_ = true;                                                                                         \
+        }                                                                                                         \
+        hipLaunchKernelGGL((trisolve_small_kernel<KM>), grid, block, lds_, st, Lin, rhs, ex, ey, lam, mask_kind,  \
+                           gamma, (int)kx, (int)ky, nsys, out, info, Cfwd, dlam_part, addend);                    \
+    } while (0)
     switch ((kx + 7) / 8) {
     case 1: FMAP_TSS(8); break;
     case 2: FMAP_TSS(16); break;
