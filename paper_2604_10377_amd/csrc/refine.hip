@@ -146,9 +146,12 @@ __global__ __launch_bounds__(256) void residual64_kernel(const float *__restrict
 //
 // ||K||_1 is the largest row sum of |K| (K is symmetric), summed along rows so
 // that the loads are coalesced.  The Cholesky factor of K is formed in LDS
-// (packed lower, row-major), right-looking: the column is scaled, then the
-// trailing triangle is updated with its entries spread evenly over the 512
-// threads.  Hager's iteration then runs in one wave with the vectors in
+// (packed lower, row-major), right-looking in panels of 8 columns: one wave
+// factorises a panel in registers, then the trailing triangle is updated one
+// wave per row, the lanes across the row's contiguous entries.  The solves'
+// LDS operand reads are unconditional, from clamped addresses (masked by a
+// bit mask).  Hager's
+// iteration then runs in one wave with the vectors in
 // registers (lane j holds rows j, j + 64, ...): the forward substitution goes
 // column by column (y_c final, rows below updated) and the back substitution
 // row by row (x_c final, rows above updated), so neither needs a reduction.
@@ -156,71 +159,111 @@ __global__ __launch_bounds__(256) void residual64_kernel(const float *__restrict
 __device__ __forceinline__ int pk(int r, int c) { return r * (r + 1) / 2 + c; }  // packed lower, row-major
 
 constexpr int CNS = kMaxCondK / 64;  // register slots per lane (k <= 256)
+constexpr int CPW = 8;                 // Cholesky panel width
+// LDS floats past the last array: the triangular solves' reads for the columns k .. k + 6 of a last
+// partial group (never used) stay inside the allocation; row c < k + 7 ends before
+// k(k+1)/2 + (1 + CPW) k + CPAD for every k
+constexpr int CPAD = 32;
 
-// row c's entry of a slotted vector (c wave-uniform), without runtime indexing of the register array
-__device__ __forceinline__ float slot_value(const float (&v)[CNS], int c)
-{
-    const int l = c & 63, s = c >> 6;
-    float r = readlane(v[0], l);
-#pragma unroll
-    for (int t = 1; t < CNS; ++t) {
-        const float x = readlane(v[t], l);
-        r = (s == t) ? x : r;
-    }
-    return r;
-}
+constexpr int CG = 8;  // columns per group of the triangular solves
 
-// v := K^{-1} v with the packed factor L and the reciprocal pivots Dinv in LDS (one wave).  Columns
-// go in groups of 8: a group's LDS reads are issued together, then its 8 dependent steps run on
-// registers only.
-constexpr int CG = 8;
-__device__ void chol_solve_regs(const float *L, const float *Dinv, float (&v)[CNS], int k)
+// x if ok, else +0, by a bit mask: the read that produced x stays unconditional (a select would let the
+// compiler put the read under a branch of its own)
+__device__ __forceinline__ float keep_if(float x, bool ok) { return __uint_as_float(__float_as_uint(x) & (ok ? ~0u : 0u)); }
+
+// v := K^{-1} v with the packed factor L and the reciprocal pivots Dinv in LDS (one wave; lane l holds rows
+// l + 64 s in slot s).  Columns go in groups of 8 within the 64 rows of one slot S (a runtime loop over the
+// groups, the group unrolled): a group's LDS reads are issued before its 8 dependent steps, each step's
+// broadcast is a readlane from the one slot S, and only the slots that can hold affected rows are
+// touched.  Forward L y = v, columns ascending: at step c the rows below subtract L_rc (v_c / L_cc);
+// column c's entries below the diagonal are row r's entry c (at rb[s] + c, rb the packed offset of the
+// lane's row, clamped into the matrix).  A lane's own value is never touched at its own step, so it ends
+// as L_rr y_r and one scaling at the end gives y (no per-column lane selects).  Back L^T x = y the same
+// way, columns descending, with row c's entries left of the diagonal (consecutive for consecutive lanes).
+// The steps of a last partial group past k - 1 read the allocation's zeroed padding or other finite LDS
+// data and broadcast v_c = 0 (rows past k stay 0), so they change nothing and need no per-column guard.
+template <int S>
+__device__ __forceinline__ void chol_fwd_slot(const float *L, const float *Dinv, float (&v)[CNS], int k,
+                                              const int (&rb)[CNS], int lane)
 {
-    const int lane = threadIdx.x & 63;
-    for (int c0 = 0; c0 < k; c0 += CG) {  // L y = v, columns ascending
+    for (int g = 0; g < 64 && 64 * S + g < k; g += CG) {
+        const int c0 = 64 * S + g;
         float lv[CG][CNS], inv[CG];
-#pragma unroll
-        for (int t = 0; t < CG; ++t) {
-            const int c = min(c0 + t, k - 1);
-            inv[t] = Dinv[c];
-#pragma unroll
-            for (int s = 0; s < CNS; ++s) {
-                const int r = lane + 64 * s;
-                lv[t][s] = (r > c && r < k) ? L[pk(r, c)] : 0.f;
-            }
-        }
 #pragma unroll
         for (int t = 0; t < CG; ++t) {
             const int c = c0 + t;
-            if (c < k) {
-                const float yc = slot_value(v, c) * inv[t];
+            inv[t] = Dinv[c];
 #pragma unroll
-                for (int s = 0; s < CNS; ++s) v[s] = (lane + 64 * s == c) ? yc : v[s] - lv[t][s] * yc;
+            for (int s = S; s < CNS; ++s) {
+                const int r = lane + 64 * s;
+                lv[t][s] = keep_if(L[rb[s] + c], r > c && r < k);
             }
         }
+#pragma unroll
+        for (int t = 0; t < CG; ++t) {
+            const float yc = readlane(v[S], g + t) * inv[t];
+#pragma unroll
+            for (int s = S; s < CNS; ++s) v[s] = fmaf(-lv[t][s], yc, v[s]);
+        }
     }
-    for (int c1 = k - 1; c1 >= 0; c1 -= CG) {  // L^T x = y, columns descending
+}
+
+template <int S>
+__device__ __forceinline__ void chol_bwd_slot(const float *L, const float *Dinv, float (&v)[CNS], int k, int lane)
+{
+    // groups of this slot below k, highest first
+    const int top = min(64, k - 64 * S);  // > 0 when called
+    for (int g = ((top - 1) / CG) * CG; g >= 0; g -= CG) {
+        const int c0 = 64 * S + g;  // the group is columns c0 + CG - 1 down to c0
         float lv[CG][CNS], inv[CG];
 #pragma unroll
         for (int t = 0; t < CG; ++t) {
-            const int c = max(c1 - t, 0);
+            const int c = c0 + CG - 1 - t;
+            const int cb = c * (c + 1) / 2;
             inv[t] = Dinv[c];
 #pragma unroll
-            for (int s = 0; s < CNS; ++s) {
+            for (int s = 0; s <= S; ++s) {
                 const int r = lane + 64 * s;
-                lv[t][s] = (r < c) ? L[pk(c, r)] : 0.f;
+                lv[t][s] = keep_if(L[cb + min(r, c)], r < c);
             }
         }
 #pragma unroll
         for (int t = 0; t < CG; ++t) {
-            const int c = c1 - t;
-            if (c >= 0) {
-                const float xc = slot_value(v, c) * inv[t];
+            const float xc = readlane(v[S], g + CG - 1 - t) * inv[t];
 #pragma unroll
-                for (int s = 0; s < CNS; ++s) v[s] = (lane + 64 * s == c) ? xc : v[s] - lv[t][s] * xc;
-            }
+            for (int s = 0; s <= S; ++s) v[s] = fmaf(-lv[t][s], xc, v[s]);
         }
     }
+}
+
+__device__ __forceinline__ void chol_solve_regs(const float *L, const float *Dinv, float (&v)[CNS], int k_in)
+{
+    static_assert(CNS == 4, "slots unrolled below");
+    // k made opaque per call, so that nothing derived from it is hoisted out of the caller's iteration loop
+    // into scalar registers held across it
+    int k = k_in;
+    asm volatile("" : "+s"(k));
+    const int lane = threadIdx.x & 63;
+    int rb[CNS];
+    float dinv[CNS];
+#pragma unroll
+    for (int s = 0; s < CNS; ++s) {
+        const int r = min(lane + 64 * s, k - 1);
+        rb[s] = r * (r + 1) / 2;
+        dinv[s] = Dinv[r];
+    }
+    chol_fwd_slot<0>(L, Dinv, v, k, rb, lane);
+    if (k > 64) chol_fwd_slot<1>(L, Dinv, v, k, rb, lane);
+    if (k > 128) chol_fwd_slot<2>(L, Dinv, v, k, rb, lane);
+    if (k > 192) chol_fwd_slot<3>(L, Dinv, v, k, rb, lane);
+#pragma unroll
+    for (int s = 0; s < CNS; ++s) v[s] *= dinv[s];  // y
+    if (k > 192) chol_bwd_slot<3>(L, Dinv, v, k, lane);
+    if (k > 128) chol_bwd_slot<2>(L, Dinv, v, k, lane);
+    if (k > 64) chol_bwd_slot<1>(L, Dinv, v, k, lane);
+    chol_bwd_slot<0>(L, Dinv, v, k, lane);
+#pragma unroll
+    for (int s = 0; s < CNS; ++s) v[s] *= dinv[s];  // x
 }
 
 __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, int kx, float threshold,
@@ -228,9 +271,10 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
                                                    float *__restrict__ Kout, float *__restrict__ Rout, int ky,
                                                    float *__restrict__ cond_est)
 {
-    extern __shared__ float sm[];
+    extern __shared__ __align__(16) float sm[];
     float *L = sm;                     // packed lower, kx(kx+1)/2
     float *Dinv = L + kx * (kx + 1) / 2;  // reciprocal pivots, kx
+    float *Pn = sm + ((kx * (kx + 1) / 2 + kx + 3) & ~3);  // the current panel, row by row: [kx][8] (16-byte rows)
     __shared__ float s_red[8];
     __shared__ int s_fail;
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -242,6 +286,11 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
             if (c <= r) L[pk(r, c)] = v;
         });
     if (tid == 0) s_fail = 0;
+    {  // the alignment gap after Dinv and the padding after Pn are read (never used) by the solves' last groups
+        const int gap0 = kx * (kx + 1) / 2 + kx, gap1 = (gap0 + 3) & ~3, pad0 = gap1 + CPW * kx;
+        for (int e = gap0 + tid; e < gap1; e += 512) sm[e] = 0.f;
+        for (int e = pad0 + tid; e < pad0 + CPAD; e += 512) sm[e] = 0.f;
+    }
     __syncthreads();
     // ||K||_1 = max row sum of |K| (symmetric: the strict upper part of row r is column r of L), one wave per row
     float rmax = 0.f;
@@ -254,33 +303,74 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
     __syncthreads();
     float knorm = s_red[0];
     for (int w = 1; w < 8; ++w) knorm = fmaxf(knorm, s_red[w]);
-    // right-looking Cholesky in LDS
-    for (int c = 0; c < kx; ++c) {
-        const float piv = L[pk(c, c)];
-        if (!(piv > 0.f) || !isfinite(piv)) {  // uniform: every thread reads the same pivot
-            if (tid == 0) s_fail = 1;
-            break;
-        }
-        const float lc = sqrtf(piv);
-        __syncthreads();
-        if (tid == 0) L[pk(c, c)] = lc;
-        for (int r = c + 1 + tid; r < kx; r += 512) L[pk(r, c)] /= lc;
-        __syncthreads();
-        // trailing triangle rows (c, kx), columns (c, r]: thread -> (row, stride class), so a row's
-        // entries are contiguous in the packed layout and all 512 threads share the work evenly
-        const int m = kx - c - 1;
-        if (m > 0) {
-            const int chunks = max(1, 512 / m);
-            if (tid < chunks * m) {
-                const int rr = tid % m, ch = tid / m;
-                const int r = c + 1 + rr;
-                const float lrc = L[pk(r, c)];
-                float *Lr = L + r * (r + 1) / 2;  // row r
-#pragma unroll 4
-                for (int qq = ch; qq <= rr; qq += chunks) {
-                    const int q = c + 1 + qq;
-                    Lr[q] -= lrc * L[pk(q, c)];
+    // Blocked right-looking Cholesky in LDS, panels of CPW columns.  Wave 0 factorises the panel in
+    // registers (lane l holds rows c0 + l + 64 s of the panel's columns; the pivots and the panel's own
+    // rows come by readlane) and writes it back, also row by row to Pn.  Then every wave updates the
+    // trailing rows, one row per wave with the lanes across its entries (contiguous in the packed
+    // rows): L[r][q] -= sum_t L[r][c0+t] L[q][c0+t], one fused multiply-add per t in column order, which
+    // are the same operations, in the same order, as a column-at-a-time factorisation.
+    for (int c0 = 0; c0 < kx; c0 += CPW) {
+        if (wave == 0) {
+            float pv[CNS][CPW];
+#pragma unroll
+            for (int s = 0; s < CNS; ++s) {
+                const int rc = min(c0 + lane + 64 * s, kx - 1);
+#pragma unroll
+                for (int t = 0; t < CPW; ++t) pv[s][t] = L[pk(rc, min(c0 + t, rc))];  // clamped into the triangle
+            }
+            bool bad = false;
+#pragma unroll
+            for (int t = 0; t < CPW; ++t) {
+                const int c = c0 + t;
+                if (c < kx && !bad) {  // wave-uniform
+                    const float piv = readlane(pv[0][t], t);  // row c is lane t, slot 0
+                    if (!(piv > 0.f) || !isfinite(piv)) {
+                        bad = true;
+                    } else {
+                        const float lc = sqrtf(piv);
+#pragma unroll
+                        for (int s = 0; s < CNS; ++s) {
+                            const int r = c0 + lane + 64 * s;
+                            pv[s][t] = r > c ? pv[s][t] / lc : (r == c ? lc : pv[s][t]);
+                        }
+#pragma unroll
+                        for (int t2 = t + 1; t2 < CPW; ++t2) {
+                            const float l2 = readlane(pv[0][t], t2);  // L[c0 + t2][c]
+#pragma unroll
+                            for (int s = 0; s < CNS; ++s) pv[s][t2] = fmaf(-pv[s][t], l2, pv[s][t2]);
+                        }
+                    }
                 }
+            }
+            if (bad && lane == 0) s_fail = 1;
+#pragma unroll
+            for (int s = 0; s < CNS; ++s) {
+                const int r = c0 + lane + 64 * s;
+                if (r < kx) {
+#pragma unroll
+                    for (int t = 0; t < CPW; ++t)
+                        if (c0 + t <= r) L[pk(r, c0 + t)] = pv[s][t];
+                    *reinterpret_cast<f32x4 *>(&Pn[r * CPW]) = f32x4{pv[s][0], pv[s][1], pv[s][2], pv[s][3]};
+                    *reinterpret_cast<f32x4 *>(&Pn[r * CPW + 4]) = f32x4{pv[s][4], pv[s][5], pv[s][6], pv[s][7]};
+                }
+            }
+        }
+        __syncthreads();
+        if (s_fail) break;  // uniform
+        const int m0 = c0 + CPW;  // panel columns past k_x are zero (clamped rows, masked below)
+        for (int r = m0 + wave; r < kx; r += 8) {
+            const f32x4 pa = *reinterpret_cast<const f32x4 *>(&Pn[r * CPW]);
+            const f32x4 pb = *reinterpret_cast<const f32x4 *>(&Pn[r * CPW + 4]);
+            float *Lr = L + r * (r + 1) / 2;  // row r
+            for (int q = m0 + lane; q <= r; q += 64) {
+                const f32x4 qa = *reinterpret_cast<const f32x4 *>(&Pn[q * CPW]);
+                const f32x4 qb = *reinterpret_cast<const f32x4 *>(&Pn[q * CPW + 4]);
+                float v = Lr[q];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) v = fmaf(-pa[t], qa[t], v);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) v = fmaf(-pb[t], qb[t], v);
+                Lr[q] = v;
             }
         }
         __syncthreads();
@@ -388,11 +478,12 @@ void launch_residual64(const float *C, const double *K64, const double *R64, con
 void launch_cond(const float *K, int64_t P, int64_t kx, int64_t ky, float threshold, const double *K64,
                  const double *R64, float *Kout, float *Rout, float *cond_est, hipStream_t st)
 {
-    const size_t lds = ((size_t)kx * (kx + 1) / 2 + kx) * sizeof(float);
+    const size_t lds = ((size_t)kx * (kx + 1) / 2 + (1 + CPW) * kx + 4 + CPAD) * sizeof(float);
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void *)cond_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(((size_t)kMaxCondK * (kMaxCondK + 1) / 2 + kMaxCondK) * sizeof(float)));
+                                  (int)(((size_t)kMaxCondK * (kMaxCondK + 1) / 2 + (1 + CPW) * kMaxCondK + 4 + CPAD) *
+                                        sizeof(float)));
         attr = true;
     }
     hipLaunchKernelGGL(cond_kernel, dim3((unsigned)P), dim3(512), lds, st, K, (int)kx, threshold, K64, R64, Kout, Rout,
