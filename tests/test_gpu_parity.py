@@ -434,7 +434,11 @@ def _conditioned(seed, P, k, d, sigma_ratio):
     return A, B, ex, ey
 
 
-@pytest.mark.parametrize("k,d,ratio", [(50, 128, 30.0), (50, 128, 300.0), (120, 256, 100.0), (200, 400, 100.0)])
+# small k: the estimate's last column group reaches past the factor into the allocation's padding;
+# 64 / 65 / 129: register-slot boundaries of the solves; 256: the largest order the estimate supports
+@pytest.mark.parametrize("k,d,ratio", [(50, 128, 30.0), (50, 128, 300.0), (120, 256, 100.0), (200, 400, 100.0),
+                                       (3, 8, 10.0), (7, 16, 30.0), (9, 20, 30.0), (64, 130, 30.0),
+                                       (65, 140, 30.0), (129, 260, 30.0), (256, 520, 30.0)])
 def test_condition_estimate(F, dev, k, d, ratio):
     """1-norm estimate of cond(A A^T) against the exact value (Hager's estimate is a lower bound, within ~x3)."""
     P = 2
