@@ -415,15 +415,26 @@ __global__ __launch_bounds__(256) void batched_gemm_kernel(GemmSeg s0, GemmSeg s
         const GemmSeg &sg = sgi == 0 ? s0 : s1;
         const float *X = sg.X + (long long)p * sg.strideX;
         const float *Y = sg.Y + (long long)p * sg.strideY;
+        // every load unconditional, from addresses clamped into the operands, and masked by a bit mask
+        // afterwards: a load under a condition was compiled as a branch with a wait of its own, and the
+        // batch's loads then went out one at a time
+        const int mc = min(m, M - 1), nc = min(n, N - 1);
+        auto keep = [](float x, bool ok) { return __uint_as_float(__float_as_uint(x) & (ok ? ~0u : 0u)); };
         for (int k0 = 0; k0 < sg.K; k0 += 16) {
             float a[8], b[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int kk = k0 + 2 * u + half;
-                const bool kok = kk < sg.K;
-                a[u] = (mok && kok) ? sg.sign * (sg.transX ? X[(size_t)kk * sg.ldx + m] : X[(size_t)m * sg.ldx + kk])
-                                    : 0.f;
-                b[u] = (nok && kok) ? Y[(size_t)kk * sg.ldy + n] : 0.f;
+                const int kc = min(kk, sg.K - 1);
+                const size_t xo = sg.transX ? (size_t)kc * sg.ldx + mc : (size_t)mc * sg.ldx + kc;
+                a[u] = X[xo];
+                b[u] = Y[(size_t)kc * sg.ldy + nc];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool kok = k0 + 2 * u + half < sg.K;
+                a[u] = keep(sg.sign * a[u], mok && kok);
+                b[u] = keep(b[u], nok && kok);
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc = mfma32x32x2(a[u], b[u], acc);
