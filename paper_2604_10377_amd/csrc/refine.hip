@@ -123,7 +123,19 @@ __global__ __launch_bounds__(256) void residual64_kernel(const float *__restrict
         double acc[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-        for (int q = 0; q < kx; ++q) {
+        // K64 entries in groups of 8, all loaded before the group's products (one at a time, each load
+        // was waited for before its 16 products); the products keep their order
+        int q = 0;
+        for (; q + 8 <= kx; q += 8) {
+            double kq[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) kq[u] = Kp[(size_t)(q + u) * kx + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[r] = fma(sC[r * kx + q + u], kq[u], acc[r]);
+        }
+        for (; q < kx; ++q) {
             const double kq = Kp[(size_t)q * kx + j];
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[r] = fma(sC[r * kx + q], kq, acc[r]);
