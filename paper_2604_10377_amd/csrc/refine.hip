@@ -38,13 +38,15 @@ __device__ __forceinline__ double mask_entry64(double mu_y, double mu_x, int kin
 
 // ---------------------------------------------------------------------------
 // K64 = A A^T (kx x kx) and R64 = B A^T (ky x kx) in float64.  One 256-thread
-// workgroup per 16 x 16 output tile; rows staged in LDS in chunks of 64 columns.
+// workgroup per 32 x 32 output tile; rows staged in LDS in chunks of 64 columns.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void gram64_kernel(const float *__restrict__ A, const float *__restrict__ B, int kx,
                                                      int ky, int d, int tkx, int tky, double *__restrict__ K64,
                                                      double *__restrict__ R64)
 {
-    __shared__ double sx[16][65], sy[16][65];
+    // 32 x 32 output tile, a thread owns rows ty, ty + 16 x columns tx, tx + 16 (one LDS read per product;
+    // with one output per thread it was two, and the kernel was bound by LDS bandwidth)
+    __shared__ double sx[32][65], sy[32][65];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int tiles = tkx * tkx + tky * tkx;
     const int p = blockIdx.x / tiles;
@@ -64,26 +66,37 @@ __global__ __launch_bounds__(256) void gram64_kernel(const float *__restrict__ A
     }
     const int I = t / tkx, J = t % tkx;
     const float *Y = A + (size_t)p * kx * d;
-    double acc = 0.0;
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
     for (int c0 = 0; c0 < d; c0 += 64) {
-        batched_for<4>(
-            threadIdx.x, 16 * 64, 256,
+        batched_for<8>(
+            threadIdx.x, 32 * 64, 256,
             [&](int e) {
                 const int r = e >> 6, col = min(c0 + (e & 63), d - 1);
-                return float2{X[(size_t)min(I * 16 + r, rowsX - 1) * d + col], Y[(size_t)min(J * 16 + r, kx - 1) * d + col]};
+                return float2{X[(size_t)min(I * 32 + r, rowsX - 1) * d + col], Y[(size_t)min(J * 32 + r, kx - 1) * d + col]};
             },
             [&](int e, float2 v) {
                 const int r = e >> 6, c = e & 63, col = c0 + c;
-                sx[r][c] = (I * 16 + r < rowsX && col < d) ? (double)v.x : 0.0;
-                sy[r][c] = (J * 16 + r < kx && col < d) ? (double)v.y : 0.0;
+                sx[r][c] = (I * 32 + r < rowsX && col < d) ? (double)v.x : 0.0;
+                sy[r][c] = (J * 32 + r < kx && col < d) ? (double)v.y : 0.0;
             });
         __syncthreads();
 #pragma unroll 8
-        for (int c = 0; c < 64; ++c) acc = fma(sx[ty][c], sy[tx][c], acc);
+        for (int c = 0; c < 64; ++c) {
+            const double x0 = sx[ty][c], x1 = sx[ty + 16][c], y0 = sy[tx][c], y1 = sy[tx + 16][c];
+            acc[0][0] = fma(x0, y0, acc[0][0]);
+            acc[0][1] = fma(x0, y1, acc[0][1]);
+            acc[1][0] = fma(x1, y0, acc[1][0]);
+            acc[1][1] = fma(x1, y1, acc[1][1]);
+        }
         __syncthreads();
     }
-    const int row = I * 16 + ty, col = J * 16 + tx;
-    if (row < rowsX && col < kx) O[(size_t)row * kx + col] = acc;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int row = I * 32 + ty + 16 * a, col = J * 32 + tx + 16 * b;
+            if (row < rowsX && col < kx) O[(size_t)row * kx + col] = acc[a][b];
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
 void launch_gram64(const float *A, const float *B, int64_t P, int64_t kx, int64_t ky, int64_t d, double *K64,
                    double *R64, hipStream_t st)
 {
-    const int tkx = (int)((kx + 15) / 16), tky = (int)((ky + 15) / 16);
+    const int tkx = (int)((kx + 31) / 32), tky = (int)((ky + 31) / 32);
     hipLaunchKernelGGL(gram64_kernel, dim3((unsigned)(P * (tkx * tkx + tky * tkx))), dim3(256), 0, st, A, B, (int)kx,
                        (int)ky, (int)d, tkx, tky, K64, R64);
 }

@@ -211,7 +211,7 @@ template <int KMAX> struct RowsolveLds {
 
 template <int KMAX, int MODE>
 __global__ __launch_bounds__(256) void rowsolve_kernel(
-    const float *__restrict__ K, const float *__restrict__ Lin, const float *__restrict__ rhs,
+    const float *__restrict__ K, const float *__restrict__ rhs,
     const float *__restrict__ ex, const float *__restrict__ ey, const float *__restrict__ lam, int mask_kind,
     float gamma, int kx, int ky, float *out, float *__restrict__ Lout, int *__restrict__ info,
     const float *__restrict__ Cfwd, float *__restrict__ dlam_part, const float *addend)
@@ -566,7 +566,7 @@ int rowsolve_waves() { return g_rowsolve_waves; }
 void set_rowsolve_waves(int w) { g_rowsolve_waves = (w == 1 || w == 2 || w == 4) ? w : 4; }  // <= launch bound
 
 template <int MODE>
-static void launch_rowsolve(const float *K, const float *Lin, const float *rhs, const float *ex, const float *ey,
+static void launch_rowsolve(const float *K, const float *rhs, const float *ex, const float *ey,
                             const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky,
                             float *out, float *Lout, int *info, const float *Cfwd, float *dlam_part, hipStream_t st,
                             const float *addend = nullptr)
@@ -584,7 +584,7 @@ static void launch_rowsolve(const float *K, const float *Lin, const float *rhs, 
                                       (int)(4 * RowsolveLds<KM>::PER_WAVE * sizeof(float)));                     \
             attr_ = true;                                                                                       \
         }                                                                                                       \
-        hipLaunchKernelGGL((rowsolve_kernel<KM, MODE>), dim3(grid), dim3(64 * W), lds_, st, K, Lin, rhs, ex, ey,  \
+        hipLaunchKernelGGL((rowsolve_kernel<KM, MODE>), dim3(grid), dim3(64 * W), lds_, st, K, rhs, ex, ey,  \
                            lam, mask_kind, gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part, addend);   \
     } while (0)
     if (kx <= 8) FMAP_RS(8);
@@ -614,7 +614,7 @@ hipError_t launch_solve(const float *A, const float *B, const float *ex, const f
         launch_cond(K, P, kx, ky, refine_steps > 0 ? cond_threshold : 0.f, refine_steps > 0 ? K64 : nullptr,
                     refine_steps > 0 ? R64 : nullptr, K, R, cond_est, st);
     if (kx <= kSmallK)
-        launch_rowsolve<RS_FWD>(K, nullptr, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info, nullptr,
+        launch_rowsolve<RS_FWD>(K, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info, nullptr,
                                 nullptr, st);
     else
         launch_rowsolve_tiled(RS_FWD, K, nullptr, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info,
@@ -650,7 +650,7 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
     } else {
         launch_gram(A, B, P, kx, ky, d, false, K, nullptr, st);
         if (small)
-            launch_rowsolve<RS_BWD_RECOMPUTE>(K, nullptr, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, nullptr,
+            launch_rowsolve<RS_BWD_RECOMPUTE>(K, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, nullptr,
                                               info, C, dl, st);
         else
             launch_rowsolve_tiled(RS_BWD_RECOMPUTE, K, nullptr, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V,
