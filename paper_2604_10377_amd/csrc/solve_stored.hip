@@ -51,7 +51,8 @@ __global__ __launch_bounds__(256) void trisolve_stored_kernel(const float *__res
                                                              float *__restrict__ dlam_part, const float *addend)
 {
     const int j = threadIdx.x & 63;
-    const int sys = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the system index in a scalar register, so the buffer descriptor below is one per wave
+    const int sys = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (sys >= nsys) return;  // wave-uniform; no block-level barrier below
     const int p = sys / ky, i = sys - p * ky;
     const float *Lp = Lin + (size_t)sys * (kx * (kx + 1) / 2);
@@ -91,14 +92,20 @@ __global__ __launch_bounds__(256) void trisolve_stored_kernel(const float *__res
     for (int s = 0; s < NS; ++s) y[s] = j + 64 * s < kx ? y[s] : 0.f;
 
     float ga[SG][NS], gb[SG][NS];
-    // group g of columns into buf: element (q, c) for the lane's rows, address clamped into column c
+    // group g of columns into buf: element (q, c) for the lane's rows.  Through a buffer descriptor the
+    // address is a lane offset of 4 q (fixed per slot) plus a scalar offset per column, with no vector
+    // address arithmetic; rows above the diagonal read other entries of the factor and rows past its
+    // end read 0 (the descriptor's range), and both are masked where the values are used
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)Lp, 0, (int)(kx * (kx + 1) / 2 * sizeof(float)), 0x00020000);
     auto load_group = [&](int g, float (&buf)[SG][NS]) {
 #pragma unroll
         for (int t = 0; t < SG; ++t) {
             const int c = min(g * SG + t, kx - 1);
-            const float *col = Lp + pcol(c, kx) - c;
+            const int so = 4 * (pcol(c, kx) - c);
 #pragma unroll
-            for (int s = 0; s < NS; ++s) buf[t][s] = col[min(max(j + 64 * s, c), kx - 1)];
+            for (int s = 0; s < NS; ++s)  // (the builtin returns the bits as an integer: reinterpreted)
+                buf[t][s] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * (j + 64 * s), so, 0));
         }
     };
 
