@@ -9,6 +9,18 @@ namespace fmap {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// A pointer read from a work-item table in device memory carries no address
+// space, so accesses through it compile to flat instructions, which count on
+// both the vector-memory and the LDS counters and make every use of a load wait
+// for all outstanding memory operations.  The tables hold global addresses
+// only: rebuilding them as global pointers (from the integer address, which the
+// compiler cannot fold back into the generic pointer) restores global loads and
+// stores, and with them per-load waits.
+template <typename T> __device__ __forceinline__ T *global_ptr(T *p)
+{
+    return (T *)((__attribute__((address_space(1))) T *)(uintptr_t)p);
+}
+
 // One 32x32x2 float32 matrix-core step.  Operand layout (lane l, wave64):
 //   a = X[m = l % 32][kk = l / 32],  b = Y[kk = l / 32][n = l % 32],
 //   accumulator register r of lane l holds D[acc32_row(r, l)][l % 32].

@@ -151,7 +151,8 @@ __global__ __launch_bounds__(256) void proj_fwd_items_kernel(const FwdItem *__re
 {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const FwdItem w = items[it];
-        proj_fwd_tile<float, MT, NT, U>(w.phi, w.mass, w.feat, w.k, w.d, w.v0, w.v1, w.kbase, w.dbase, w.out);
+        proj_fwd_tile<float, MT, NT, U>(global_ptr(w.phi), global_ptr(w.mass), global_ptr(w.feat), w.k, w.d, w.v0, w.v1,
+                                        w.kbase, w.dbase, global_ptr(w.out));
     }
 }
 
@@ -631,7 +632,7 @@ __global__ __launch_bounds__(256) void proj_bwd_items_kernel(const BwdItem *__re
     extern __shared__ float sG[];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BwdItem w = items[it];
-        proj_bwd_rows<float, NT>(sG, w.phi, w.mass, w.dA, w.dF, w.n, w.k, w.d, w.r0, w.rb, w.dbase);
+        proj_bwd_rows<float, NT>(sG, global_ptr(w.phi), global_ptr(w.mass), global_ptr(w.dA), global_ptr(w.dF), w.n, w.k, w.d, w.r0, w.rb, w.dbase);
     }
 }
 

@@ -609,7 +609,7 @@ template <int KS>
 __global__ __launch_bounds__(512, 2) void proj_bwd_mc_items_kernel(const McItem *__restrict__ items)
 {
     const McItem w = items[blockIdx.x];
-    bwdmc_block<float, 3, 3, KS>(w.phi, w.mass, w.dA, w.dF, w.n, w.k, w.d, w.t0, w.t1, w.dbase);
+    bwdmc_block<float, 3, 3, KS>(global_ptr(w.phi), global_ptr(w.mass), global_ptr(w.dA), global_ptr(w.dF), w.n, w.k, w.d, w.t0, w.t1, w.dbase);
 }
 
 // ---------------------------------------------------------------------------
@@ -771,7 +771,7 @@ template <int KS>
 __global__ __launch_bounds__(512, 1) void proj_bwd_mck_items_kernel(const McItem *__restrict__ items)
 {
     const McItem w = items[blockIdx.x];
-    bwdk_block<KS>(w.phi, w.mass, w.dA, w.dF, w.n, w.k, w.d, w.t0, w.t1, w.dbase);
+    bwdk_block<KS>(global_ptr(w.phi), global_ptr(w.mass), global_ptr(w.dA), global_ptr(w.dF), w.n, w.k, w.d, w.t0, w.t1, w.dbase);
 }
 
 constexpr int XS = 32;  // vertices per stage (one matrix-core K step)
@@ -1006,7 +1006,8 @@ template <bool SLICED>
 __global__ __launch_bounds__(256, 2) void proj_fwd_x3r_items_kernel(const FwdItem *__restrict__ items)
 {
     const FwdItem w = items[blockIdx.x];
-    x3r_block<SLICED>(w.phi, w.mass, w.feat, w.n, w.k, w.d, w.v0, w.v1, w.kbase / 64, w.dbase, w.out);
+    x3r_block<SLICED>(global_ptr(w.phi), global_ptr(w.mass), global_ptr(w.feat), w.n, w.k, w.d, w.v0, w.v1, w.kbase / 64,
+                      w.dbase, global_ptr(w.out));
 }
 
 bool f32_split_fwd_shape_ok(int64_t n, int64_t k, int64_t d)
