@@ -170,6 +170,36 @@ std::vector<Shape> shapes_of(const fmap_plan *pl)
     return sh;
 }
 
+// One workgroup per item, workgroup ids dealt round-robin to the 8 XCDs: reorder an emulated-kernel
+// item list so that the items of one vertex chunk (its k and d blocks, which read the same feature
+// rows) share an XCD and that XCD's L2.  Chunks, longest first, go to the least loaded XCD queue;
+// table slot r * 8 + x is item r of queue x, or an empty item (v0 == v1) that returns at once.
+static void deal_to_xcds(std::vector<FwdItem> &v)
+{
+    if (v.empty()) return;
+    std::vector<std::vector<FwdItem>> q(8);
+    std::vector<int64_t> load(8, 0);
+    for (size_t i = 0; i < v.size();) {
+        size_t j = i + 1;  // the items of one chunk are adjacent (pushed together, stable sort)
+        while (j < v.size() && v[j].phi == v[i].phi && v[j].v0 == v[i].v0 && v[j].v1 == v[i].v1) ++j;
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        for (size_t t = i; t < j; ++t) q[x].push_back(v[t]);
+        load[x] += (int64_t)(j - i) * (v[i].v1 - v[i].v0);
+        i = j;
+    }
+    size_t rounds = 0;
+    for (const auto &qx : q) rounds = std::max(rounds, qx.size());
+    std::vector<FwdItem> out;
+    out.reserve(8 * rounds);
+    for (size_t r = 0; r < rounds; ++r)
+        for (int x = 0; x < 8; ++x) {
+            FwdItem w = r < q[x].size() ? q[x][r] : v[0];
+            if (r >= q[x].size()) w.v1 = w.v0;
+            out.push_back(w);
+        }
+    v.swap(out);
+}
+
 // Forward and reduction items for a given chunk size (a multiple of 32); partial slots are laid out shape
 // after shape.  fx / fxs: emulated-kernel items (k <= 64 / k > 64), fi: general-kernel items.
 void build_fwd_items(const fmap_plan *pl, int chunk, std::vector<FwdItem> &fi, std::vector<FwdItem> &fx,
@@ -226,10 +256,12 @@ void build_fwd_items(const fmap_plan *pl, int chunk, std::vector<FwdItem> &fi, s
     std::stable_sort(fi.begin(), fi.end(), longer);
     std::stable_sort(fx.begin(), fx.end(), longer);
     std::stable_sort(fxs.begin(), fxs.end(), longer);
+    deal_to_xcds(fx);
+    deal_to_xcds(fxs);
     *partial_floats = off;
 }
 
-// Backward items: groups on the emulated kernels get McItems of 2 rb 256-vertex tiles (in bucket order,
+// Backward items: groups on the emulated kernels get McItems of 2 rb 256-vertex tiles (bucket by bucket,
 // with each bucket's offset and count recorded), the rest general-kernel items of 128 rb rows.
 void build_bwd_items(fmap_plan *pl, int rb, std::vector<BwdItem> &bi, std::vector<McItem> &mi)
 {
@@ -243,24 +275,39 @@ void build_bwd_items(fmap_plan *pl, int rb, std::vector<BwdItem> &bi, std::vecto
         if (!mc_bucket(pl, b)) continue;
         const int cols = mc_item_cols(B.k);
         const int tpi = 2 * rb;
+        std::vector<McItem> ranges;  // (shape, tile range) tasks, column block still open
         for (const Shape &s : shapes_of(pl)) {
             if (s.bucket != b) continue;
             const int ntile = (int)((s.n + 255) / 256);
-            for (int t0 = 0; t0 < ntile; t0 += tpi)
-                for (int64_t c0 = 0; c0 < d; c0 += cols) {
-                    McItem w;
-                    w.phi = s.phi;
-                    w.mass = s.mass;
-                    w.dA = B.dAB + (size_t)s.slot * s.k * d;
-                    w.dF = s.dF;
-                    w.n = (int)s.n;
-                    w.k = (int)s.k;
-                    w.d = (int)d;
-                    w.t0 = t0;
-                    w.t1 = std::min(ntile, t0 + tpi);
-                    w.dbase = (int)c0;
-                    mi.push_back(w);
-                }
+            for (int t0 = 0; t0 < ntile; t0 += tpi) {
+                McItem w;
+                w.phi = s.phi;
+                w.mass = s.mass;
+                w.dA = B.dAB + (size_t)s.slot * s.k * d;
+                w.dF = s.dF;
+                w.n = (int)s.n;
+                w.k = (int)s.k;
+                w.d = (int)d;
+                w.t0 = t0;
+                w.t1 = std::min(ntile, t0 + tpi);
+                w.dbase = 0;
+                ranges.push_back(w);
+            }
+        }
+        // Workgroup ids go round-robin to the 8 XCDs: slot q * 8 + x holds column block q % nb of tile
+        // range (q / nb) * 8 + x, so the column blocks of one range run on one XCD and read its basis
+        // rows from HBM once (from that XCD's L2 afterwards).  Slots past the last range are empty
+        // items (t0 == t1, pointers of a real range) that return at once.
+        const int nr = (int)ranges.size();
+        const int nb = (int)((d + cols - 1) / cols);
+        const int slots = nr > 0 ? 8 * nb * ((nr + 7) / 8) : 0;
+        for (int bid = 0; bid < slots; ++bid) {
+            const int x = bid & 7, q = bid >> 3;
+            const int j = (q / nb) * 8 + x;
+            McItem w = ranges[std::min(j, nr - 1)];
+            w.dbase = (q % nb) * cols;
+            if (j >= nr) w.t1 = w.t0;
+            mi.push_back(w);
         }
         B.mc_n = (int)mi.size() - B.mc_off;
     }
@@ -399,7 +446,7 @@ bool cache_lookup(const char *path, const std::string &sig, fmap_plan *pl)
         // only values the tuner itself can produce: the partial slots are sized for the smallest chunk
         if (std::sscanf(s.c_str() + bar + 1, "%d %d %d %d %d", &c, &gfm, &w, &rb, &gbm) == 5 &&
             (c == 512 || c == 1024 || c == 2048) && gfm >= 1 && gfm <= 65535 && (w == 1 || w == 2 || w == 4) &&
-            (rb == 1 || rb == 2 || rb == 4) && gbm >= 1 && gbm <= 65535) {
+            (rb == 1 || rb == 2 || rb == 4 || rb == 8) && gbm >= 1 && gbm <= 65535) {
             pl->chunk = c;
             pl->grid_fwd = gfm;
             pl->waves = w;
@@ -599,7 +646,7 @@ fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, 
         if (bwd) {
             best = 1e30f;
             int brb = 2, bgb = 2 * cus;
-            for (int rb : {1, 2, 4}) {
+            for (int rb : {1, 2, 4, 8}) {
                 FMAP_TRY(set_bwd(rb));
                 for (int gm : {1, 2, 4}) {
                     const int g = std::max(1, std::min(gm * cus, std::max(pl->nbwd, 1)));

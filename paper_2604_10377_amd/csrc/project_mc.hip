@@ -609,6 +609,7 @@ template <int KS>
 __global__ __launch_bounds__(512, 2) void proj_bwd_mc_items_kernel(const McItem *__restrict__ items)
 {
     const McItem w = items[blockIdx.x];
+    if (w.t0 >= w.t1) return;  // empty slot of the table (whole workgroup, before any barrier)
     bwdmc_block<float, 3, 3, KS>(global_ptr(w.phi), global_ptr(w.mass), global_ptr(w.dA), global_ptr(w.dF), w.n, w.k, w.d, w.t0, w.t1, w.dbase);
 }
 
@@ -771,6 +772,7 @@ template <int KS>
 __global__ __launch_bounds__(512, 1) void proj_bwd_mck_items_kernel(const McItem *__restrict__ items)
 {
     const McItem w = items[blockIdx.x];
+    if (w.t0 >= w.t1) return;  // empty slot of the table (whole workgroup, before any barrier)
     bwdk_block<KS>(global_ptr(w.phi), global_ptr(w.mass), global_ptr(w.dA), global_ptr(w.dF), w.n, w.k, w.d, w.t0, w.t1, w.dbase);
 }
 
@@ -1006,6 +1008,7 @@ template <bool SLICED>
 __global__ __launch_bounds__(256, 2) void proj_fwd_x3r_items_kernel(const FwdItem *__restrict__ items)
 {
     const FwdItem w = items[blockIdx.x];
+    if (w.v0 >= w.v1) return;  // empty slot of the table (whole workgroup, before any barrier)
     x3r_block<SLICED>(global_ptr(w.phi), global_ptr(w.mass), global_ptr(w.feat), w.n, w.k, w.d, w.v0, w.v1, w.kbase / 64,
                       w.dbase, global_ptr(w.out));
 }
