@@ -44,8 +44,10 @@ constexpr int aux_floats(int TRM) { return TSZ /*minv*/ + 32 * LDD /*dl*/ + 32 /
 
 enum { RT_FWD = 0, RT_BWD_STORED = 1, RT_BWD_RECOMPUTE = 2 };
 
+// At TMAX = 4 the ten tiles take 40 KB of LDS: capped at 128 VGPRs (4 waves per SIMD, no spills),
+// two workgroups, i.e. two systems, share a CU instead of one.
 template <int TMAX, bool GT, int MODE>
-__global__ __launch_bounds__(512) void rowsolve_tiles_kernel(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ? 4 : 1))) void rowsolve_tiles_kernel(
     const float *__restrict__ K, const float *__restrict__ Lin, const float *__restrict__ rhs,
     const float *__restrict__ ex, const float *__restrict__ ey, const float *__restrict__ lam, int mask_kind,
     float gamma, int kx, int ky, int nsys, float *out, float *__restrict__ Lout, int *__restrict__ info,
