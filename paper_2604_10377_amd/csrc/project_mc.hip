@@ -637,7 +637,9 @@ struct BkStep {
 };
 
 // One workgroup's block: 256-vertex tiles [t0, t1) of one shape for the columns [dbase, dbase + 64).
-template <int KS>
+// SHALLOW: loads one step ahead instead of three (two step buffers), for instances that run two
+// workgroups per CU, where the other workgroup covers the load latency.
+template <int KS, bool SHALLOW = false>
 __device__ __forceinline__ void bwdk_block(const float *__restrict__ P, const float *__restrict__ Mv,
                                            const float *__restrict__ G, float *__restrict__ O, int n, int k, int d,
                                            int t0, int t1, int dbase)
@@ -727,8 +729,20 @@ __device__ __forceinline__ void bwdk_block(const float *__restrict__ P, const fl
             }
         }
     };
-    BkStep b0, b1, b2, b3;
     const int last = nsteps - 1;
+    if constexpr (SHALLOW) {
+        BkStep b0, b1;
+        load_step(0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        for (int st = 0; st < nsteps; st += 2) {
+            load_step(min(st + 1, last), b1);
+            step(st, b0);
+            load_step(min(st + 2, last), b0);
+            if (st + 1 < nsteps) step(st + 1, b1);
+        }
+        return;
+    }
+    BkStep b0, b1, b2, b3;
     // rounds of four with no early exit (the last round predicated), as in the backward above
     load_step(0, b0);
     __builtin_amdgcn_sched_barrier(0);
@@ -768,12 +782,15 @@ __global__ __launch_bounds__(512, 1) void proj_bwd_mck_kernel(const float *__res
 }
 
 // Uneven batches: one workgroup per work item.
+// KS <= 5: the dA^T parts take at most 66 KB of LDS, so with the shallow pipeline (<= 128 VGPRs) two
+// workgroups share a CU.
 template <int KS>
-__global__ __launch_bounds__(512, 1) void proj_bwd_mck_items_kernel(const McItem *__restrict__ items)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(KS <= 5 ? 4 : 1))) void
+proj_bwd_mck_items_kernel(const McItem *__restrict__ items)
 {
     const McItem w = items[blockIdx.x];
     if (w.t0 >= w.t1) return;  // empty slot of the table (whole workgroup, before any barrier)
-    bwdk_block<KS>(global_ptr(w.phi), global_ptr(w.mass), global_ptr(w.dA), global_ptr(w.dF), w.n, w.k, w.d, w.t0, w.t1, w.dbase);
+    bwdk_block<KS, (KS <= 5)>(global_ptr(w.phi), global_ptr(w.mass), global_ptr(w.dA), global_ptr(w.dF), w.n, w.k, w.d, w.t0, w.t1, w.dbase);
 }
 
 constexpr int XS = 32;  // vertices per stage (one matrix-core K step)
