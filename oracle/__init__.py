@@ -19,6 +19,13 @@ Functions and the passages they follow (Sec. 3.1 of the paper):
 Pins: every function is checked in ``tests/test_oracle_pins.py`` against closed
 forms, invariants, a Kronecker brute force, library least squares, hand-worked
 fixtures in ``tests/golden`` and central finite differences.
+
+Two further oracles, in plain numpy float64, live in submodules:
+  oracle.overlap     confusion counts and overlap metrics, balanced accuracy
+                     (Sec. 3.3); pins in tests/test_oracle_pins_overlap.py
+  oracle.gradfeat    DiffusionNet spatial-gradient features, variants A and B,
+                     and their reverse mode (Sec. 3.2); pins in
+                     tests/test_oracle_pins_gradfeat.py
 """
 from __future__ import annotations
 
