@@ -37,12 +37,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup-seconds", type=float, default=1.5,
+                    help="untimed replays for this much wall time before the counted warm-up")
     ap.add_argument("--workload", default="headline", choices=["headline", "plain", "mixed", "large", "ragged"])
     ap.add_argument("--bwd", default=None, choices=["stored", "recompute"],
                     help="backward mode (default: recompute for the large workload, stored otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
+    ap.add_argument("--split", type=int, default=1,
+                    help="sub-batches per step, staggered on their own streams (1: one sequence of calls)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-pair float32 leg")
+    ap.add_argument("--oracle-one-pair", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many eager steps (for rocprofv3), no JSON")
     ap.add_argument("--copy-probe", action="store_true",
@@ -50,15 +56,16 @@ def parse():
     return ap.parse_args()
 
 
-def make_workload(name: str):
+def make_workload(name: str, pairs=None):
     from paper_2604_10377_amd import synth
+    kw = {} if pairs is None else {"pairs": pairs}
     if name == "headline":
-        return synth.workload_headline()
+        return synth.workload_headline(**kw)
     if name == "plain":
         return synth.workload_plain()
     if name == "mixed":
-        return synth.workload_mixed()
-    return synth.workload_large()
+        return synth.workload_mixed(**kw)
+    return synth.workload_large(**kw)
 
 
 # solve options per workload: the mixed-precision workload runs one float64-residual
@@ -171,15 +178,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "headline_hbm_traffic.txt")
 KERNEL_OF_PHASE = {"project": "proj_fwd_x3r_kernel<false>", "project_backward": "proj_bwd_mc_kernel<float, 3, 3, 2>"}
 
 
-def measured_traffic(phase: str, workload: str):
+def measured_traffic(phase: str, workload: str, pairs_per_launch: int):
     """HBM bytes per launch of the phase's main kernel from the committed byte-counter summary.
 
-    None unless the summary covers this workload and the kernel source still has the hash the
-    counters were taken with (a changed kernel voids them)."""
+    None unless the summary covers this workload at this launch size (its "shapes per launch" line) and
+    the kernel source still has the hash the counters were taken with (a changed kernel voids them)."""
     import hashlib
     if workload != "headline" or phase not in KERNEL_OF_PHASE or not os.path.exists(TRAFFIC_FILE):
         return None
     lines = open(TRAFFIC_FILE).read().splitlines()
+    per = [ln for ln in lines if ln.startswith("shapes per launch: ")]
+    if not per or int(per[0].split(":")[1]) != 2 * pairs_per_launch:
+        return None
     src = [ln for ln in lines if ln.startswith("source: ")]
     if not src:
         return None
@@ -196,8 +206,74 @@ def measured_traffic(phase: str, workload: str):
     return None
 
 
-def cpu_baseline(b, seconds: float):
-    """The oracle, as it stands, on a bounded sample of the same workload (whole pairs, full n)."""
+def warm_up(replay, args):
+    """Untimed replays for --warmup-seconds of wall time (the GPU's clocks settle under sustained load;
+    a short burst right after set-up runs slower), then the W counted warm-up steps."""
+    import torch
+    t0, i = time.perf_counter(), 0
+    while time.perf_counter() - t0 < args.warmup_seconds:
+        for _ in range(10):
+            replay(i)
+            i += 1
+        torch.cuda.synchronize()
+    for j in range(args.warmup):
+        replay(i + j)
+    torch.cuda.synchronize()
+
+
+def timed_steps(replay, K, stream):
+    """K steps between events on the replay stream, one event after each step.
+
+    Returns (mean ms per step over the whole timed region, per-step statistics)."""
+    import torch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(stream)
+    for i in range(K):
+        replay(i)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(K)])
+    ms = evs[0].elapsed_time(evs[K]) / K
+    stats = {"median": round(float(np.median(per)), 5), "p10": round(float(np.percentile(per, 10)), 5),
+             "p90": round(float(np.percentile(per, 90)), 5), "mean": round(ms, 5)}
+    return ms, stats
+
+
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def single_core_pair(workload: str):
+    """Seconds the oracle takes for pair 0 of the workload (forward + backward, full n) on one thread, in a
+    child process started with OMP_NUM_THREADS=1 (it never touches the GPU)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-one-pair", "--workload", workload],
+                       capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def oracle_one_pair(workload: str):
+    import oracle
+    b = make_workload(workload, pairs=1)
+    args = (b.phi_consumed(), b.mass, b.feat_consumed(), b.evals, b.lam, b.mask, b.gamma, b.dC)
+    t0 = time.perf_counter()
+    oracle.pipeline_batch(*args)
+    print(json.dumps({"seconds": round(time.perf_counter() - t0, 3), "threads": oracle.num_threads()}), flush=True)
+
+
+def cpu_baseline(b, seconds: float, workload: str):
+    """The oracle, as it stands, on a bounded sample of the same workload (whole pairs, full n), on every
+    host core this process may use; plus one pair on one core."""
     import oracle
     P = b.pairs
     npairs = max(1, min(P, 4))
@@ -212,32 +288,53 @@ def cpu_baseline(b, seconds: float):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
+    one = single_core_pair(workload)
     return {"value": round(done / el, 3), "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{done} solves ({npairs}-pair batches of the {b.name} workload, full n) in {el:.1f} s, fp64"}
+            "sample": f"{done} solves ({npairs}-pair batches of the {b.name} workload, full n) in {el:.1f} s, fp64",
+            "cpu_model": cpu_model(), "affinity_cores": len(os.sched_getaffinity(0)),
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"),
+            "one_pair_one_core_s": None if one is None else one["seconds"]}
 
 
-def accuracy(b, step, pairs=(0, 1)):
-    """Relative Frobenius error of C and dF of sampled pairs against the oracle."""
+def accuracy(b, split, pairs=(0, 1)):
+    """Relative Frobenius error of C and dF of sampled pairs against the oracle (pairs located in their
+    sub-batch of the split step)."""
+    P = b.pairs
+    out = {}
+    for p in pairs:
+        st, q = split.locate(p)
+        out[p] = (st.C[q].cpu().numpy(), None if b.dC is None else
+                  (st.dF[q].cpu().numpy(), st.dF[st.b.pairs + q].cpu().numpy()))
+    return _errors(b, out)
+
+
+def accuracy_plain(b, psteps, pairs):
+    out = {}
+    for p in pairs:
+        st = psteps[p][0]
+        out[p] = (st.C[0].cpu().numpy(), None if b.dC is None else (st.dF[0].cpu().numpy(),
+                                                                   st.dF[1].cpu().numpy()))
+    return _errors(b, out)
+
+
+def _errors(b, got):
     import oracle
     P = b.pairs
-    C = step.C.cpu().numpy()
-    dF = None if b.dC is None else step.dF.cpu().numpy()
     phi, feat = b.phi_consumed(), b.feat_consumed()
     worst = {"C": 0.0, "dF": 0.0}
     rel = lambda x, r: float(np.linalg.norm(x - r) / np.linalg.norm(r))
-    pairs = tuple(p for p in pairs if p < P)
-    for p in pairs:
+    for p, (C, dF) in got.items():
         A, B, D, Cr, _ = oracle.forward_pair(phi[p], b.mass[p], feat[p], phi[P + p], b.mass[P + p], feat[P + p],
                                              b.evals[p], b.evals[P + p], float(b.lam[p]), b.mask, b.gamma)
-        worst["C"] = max(worst["C"], rel(C[p], Cr))
-        if b.dC is None:
+        worst["C"] = max(worst["C"], rel(C, Cr))
+        if dF is None:
             continue  # forward-only workload
         dA, dB, _ = oracle.solve_backward(A, B, Cr, D, float(b.lam[p]), b.dC[p])
-        worst["dF"] = max(worst["dF"], rel(dF[p], oracle.project_backward(phi[p], b.mass[p], dA)),
-                          rel(dF[P + p], oracle.project_backward(phi[P + p], b.mass[P + p], dB)))
+        worst["dF"] = max(worst["dF"], rel(dF[0], oracle.project_backward(phi[p], b.mass[p], dA)),
+                          rel(dF[1], oracle.project_backward(phi[P + p], b.mass[P + p], dB)))
     if b.dC is None:
         worst.pop("dF")
-    return {k: float(f"{v:.3e}") for k, v in worst.items()} | {"pairs": list(pairs)}
+    return {k: float(f"{v:.3e}") for k, v in worst.items()} | {"pairs": sorted(got)}
 
 
 def ragged_costs(pairs, d):
@@ -299,16 +396,8 @@ def bench_ragged(args, F, dev):
         torch.cuda.synchronize()
         print(f"profiled {args.profile_steps} plan steps of the ragged workload", flush=True)
         return
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    warm_up(lambda i: step(), args)
+    ms, step_stats = timed_steps(lambda i: step(), args.steps, stream)
     # forward and backward graphs timed separately
     pass_ms = {}
     for name, fn in (("fwd", plan.forward), ("bwd", plan.backward)):
@@ -350,6 +439,7 @@ def bench_ragged(args, F, dev):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 5),
+        "step_ms": step_stats,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -368,8 +458,103 @@ def bench_ragged(args, F, dev):
     plan.close()
 
 
+class SplitStep:
+    """One step as S sub-batches of consecutive pairs on S streams (default priority), staggered: sub-batch
+    j starts its projection when sub-batch j - 1's projection is done, so the latency-bound solve and
+    adjoint of one sub-batch run beside the HBM-bound projections of its neighbours.  S = 1 is the plain
+    sequence of the four library calls.  Captured once as a graph, the streams become graph branches."""
+
+    def __init__(self, steps, side_streams):
+        self.steps, self.side = steps, side_streams
+
+    def run(self):
+        # the sub-batches fork from the stream current at the call (under graph capture: the capture
+        # stream) and join it again at the end
+        import torch
+        main = torch.cuda.current_stream()
+        streams = [main] + list(self.side)
+        prev = None
+        for j, (st, s) in enumerate(zip(self.steps, streams)):
+            if j > 0:
+                s.wait_event(prev)
+            with torch.cuda.stream(s):
+                st.project()
+                prev = torch.cuda.Event()
+                prev.record(s)
+                st.solve()
+                if st.dC is not None:
+                    st.solve_backward()
+                    st.project_backward()
+        for s in streams[1:]:
+            main.wait_stream(s)
+
+    def locate(self, p):
+        """(sub-batch step, index within it) of pair p."""
+        for st in self.steps:
+            if p < st.b.pairs:
+                return st, p
+            p -= st.b.pairs
+        raise IndexError(p)
+
+
+def split_pairs(P: int, S: int):
+    """S consecutive ranges of pairs, sizes differing by at most one."""
+    S = max(1, min(S, P))
+    edges = [round(j * P / S) for j in range(S + 1)]
+    return [list(range(edges[j], edges[j + 1])) for j in range(S)]
+
+
+def sub_batch(b, npairs):
+    from types import SimpleNamespace
+    return SimpleNamespace(pairs=npairs, n=b.n, k=b.k, d=b.d, mask=b.mask, gamma=b.gamma, name=b.name)
+
+
+def plain_leg(args, F, b, dev, inputs, opts):
+    """The plain float32 GPU path: per-pair library calls (two projections, solve, adjoint, two projection
+    backwards), launched eagerly, no graph, factors stored.  Timed over whole steps like the batched form;
+    returns (solves/s, ms per step, errors of sampled pairs against the oracle)."""
+    import torch
+    phi, mass, feat, ex, ey, lam, dC = inputs
+    P, k, d = b.pairs, b.k, b.d
+    one = sub_batch(b, 1)
+    steps = []
+    for p in range(P):
+        sl = lambda t, i: t[i:i + 1]
+        stx = Step(F, dev, one, (sl(phi, p), sl(mass, p), sl(feat, p), sl(ex, p), sl(ey, p), sl(lam, p),
+                                 None if dC is None else sl(dC, p)), "stored", **opts)
+        sty = (sl(phi, P + p), sl(mass, P + p), sl(feat, P + p))
+        steps.append((stx, sty))
+    dev_AB = [torch.empty((2, k, d), dtype=torch.float32, device=dev) for _ in range(P)]
+
+    def run():
+        for p, (st, (py, my, fy)) in enumerate(steps):
+            AB = dev_AB[p]
+            F.fmap_project(st.phi, st.mass, st.feat, A=AB[:1], workspace=st.wsp)
+            F.fmap_project(py, my, fy, A=AB[1:], workspace=st.wsp)
+            F.fmap_solve(AB[:1], AB[1:], st.ex, st.ey, st.lam, b.mask, b.gamma, C=st.C, factors=st.fac,
+                         info=st.info, workspace=st.wss, store_factors=True, refine_steps=st.refine,
+                         cond_fp64_threshold=st.cond_thr)
+            if st.dC is not None:
+                F.fmap_solve_backward(st.dC, AB[:1], AB[1:], st.C, st.ex, st.ey, st.lam, b.mask, b.gamma, st.fac,
+                                      dA=st.dAB[:1], dB=st.dAB[1:], workspace=st.wss)
+                F.fmap_project_backward(st.phi, st.mass, st.dAB[:1], dF=st.dF[:1])
+                F.fmap_project_backward(py, my, st.dAB[1:], dF=st.dF[1:])
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.5:
+        run()
+        torch.cuda.synchronize()
+    K = max(3, min(args.steps, 20))
+    ms, stats = timed_steps(lambda i: run(), K, torch.cuda.current_stream(dev))
+    return P / (ms * 1e-3), ms, stats, steps
+
+
 def main():
     args = parse()
+    if args.oracle_one_pair:
+        return oracle_one_pair(args.workload)
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build runs the solve on a single device (asked for --gpus "
               f"{args.gpus}); pairs are independent, so several GPUs would each take a share of the batch.",
@@ -394,28 +579,35 @@ def main():
     b = make_workload(args.workload)
     bf16 = b.phi_bf16 is not None
     P = b.pairs
+    opts = SOLVE_OPTS.get(args.workload, {})
+    subs = split_pairs(P, args.split)
+    S = len(subs)
 
-    def upload():
+    def upload(sel):
+        idx = list(sel) + [P + p for p in sel]
         if bf16:
-            phi = torch.from_numpy(b.phi_bf16.view(np.int16)).to(dev).view(torch.bfloat16)
-            feat = torch.from_numpy(b.feat_bf16.view(np.int16)).to(dev).view(torch.bfloat16)
+            phi = torch.from_numpy(b.phi_bf16[idx].view(np.int16)).to(dev).view(torch.bfloat16)
+            feat = torch.from_numpy(b.feat_bf16[idx].view(np.int16)).to(dev).view(torch.bfloat16)
         else:
-            phi = torch.from_numpy(b.phi).to(dev)
-            feat = torch.from_numpy(b.feat).to(dev)
+            phi = torch.from_numpy(b.phi[idx]).to(dev)
+            feat = torch.from_numpy(b.feat[idx]).to(dev)
         t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
-        return (phi, t(b.mass), feat, t(b.evals_x), t(b.evals_y), t(b.lam), None if b.dC is None else t(b.dC))
+        return (phi, t(b.mass[idx]), feat, t(b.evals_x[list(sel)]), t(b.evals_y[list(sel)]), t(b.lam[list(sel)]),
+                None if b.dC is None else t(b.dC[list(sel)]))
 
-    base = upload()
-    sets = [base] + [tuple(None if x is None else x.clone() for x in base) for _ in range(2)]
+    base = [upload(sel) for sel in subs]
+    sets = [base] + [[tuple(None if x is None else x.clone() for x in inp) for inp in base] for _ in range(2)]
     fwd_only = b.dC is None  # the plain workload is a forward solve
-    steps = [Step(F, dev, b, s, args.bwd, **SOLVE_OPTS.get(args.workload, {})) for s in sets]
     stream = torch.cuda.current_stream(dev)
+    side = [torch.cuda.Stream(dev) for _ in range(S - 1)]
+    steps = [SplitStep([Step(F, dev, sub_batch(b, len(sel)), inp, args.bwd, **opts) for sel, inp in zip(subs, st)],
+                       side) for st in sets]
 
     if args.profile_steps:
         for i in range(args.profile_steps):
             steps[i % 3].run()
         torch.cuda.synchronize()
-        print(f"profiled {args.profile_steps} eager steps of {b.name}", flush=True)
+        print(f"profiled {args.profile_steps} eager steps of {b.name} ({S} sub-batches)", flush=True)
         return
 
     # warm-up (also JIT-free: the library is AOT compiled) and graph capture
@@ -432,59 +624,80 @@ def main():
             graphs.append(g)
         torch.cuda.synchronize()
     replay = (lambda i: graphs[i % 3].replay()) if graphs else (lambda i: steps[i % 3].run())
-    for i in range(args.warmup):
-        replay(i)
+    warm_up(replay, args)
+    ms, step_stats = timed_steps(replay, args.steps, stream)
+    # accuracy from one more replay of input set 0 into outputs first filled with NaN, so that every
+    # checked value comes from the replayed step itself
+    for st in steps[0].steps:
+        st.C.fill_(float("nan"))
+        st.dF.fill_(float("nan"))
+    replay(0)
     torch.cuda.synchronize()
+    acc = accuracy(b, steps[0], pairs=(0, P - 1))
 
-    # timed region: K steps between two events on the replay stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for i in range(args.steps):
-        replay(i)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-
-    # per-phase average duration in the step's own context: K more steps launched eagerly (the host
-    # stays ahead of the device, so the kernels run back to back as in the graph), with HIP events on the
-    # launch stream between the phases.  A phase's time then includes the cache state the previous
-    # phases leave, e.g. the write-back of the backward projection's output during the next forward
-    # projection.  (Events inside a captured graph are not available on this platform.)
+    # per-phase average duration of the sub-batch kernels, each phase alone: K more steps launched eagerly,
+    # the sub-batches one after the other on the launch stream (the host stays ahead of the device, so the
+    # kernels run back to back), HIP events on that stream between the phases.  A phase's time includes the
+    # cache state the previous phases leave, e.g. the write-back of the backward projection's output during
+    # the next forward projection.  In the timed graph the sub-batches overlap, so these are the kernels'
+    # own rates, not their shares of the step.  (Events inside a captured graph are not available here.)
     phases = ("project", "solve") if fwd_only else ("project", "solve", "solve_backward", "project_backward")
     rs = torch.cuda.current_stream(dev)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(phases) + 1)] for _ in range(args.steps)]
+    nev = len(phases) * S
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nev + 1)] for _ in range(args.steps)]
     for i in range(max(args.warmup, 1)):
-        steps[i % 3].run()
+        for st in steps[i % 3].steps:
+            st.run()
     torch.cuda.synchronize()
     for i in range(args.steps):
-        stp = steps[i % 3]
         evs[i][0].record(rs)
-        for ph, name in enumerate(phases):
-            getattr(stp, name)()
-            evs[i][ph + 1].record(rs)
+        e = 1
+        for st in steps[i % 3].steps:
+            for name in phases:
+                getattr(st, name)()
+                evs[i][e].record(rs)
+                e += 1
     torch.cuda.synchronize()
-    phase_ms = {name: sum(evs[i][ph].elapsed_time(evs[i][ph + 1]) for i in range(args.steps)) / args.steps
-                for ph, name in enumerate(phases)}
-    costs = {nme: c for nme, c in phase_costs(b, bf16).items() if nme in phase_ms}
+    phase_ms = {name: 0.0 for name in phases}
+    for i in range(args.steps):
+        e = 0
+        for _ in range(S):
+            for name in phases:
+                phase_ms[name] += evs[i][e].elapsed_time(evs[i][e + 1]) / args.steps
+                e += 1
+    # costs and roofline of one sub-batch launch of each phase (the launches the step is made of)
+    sub0 = sub_batch(b, len(subs[0]))
+    costs = {nme: c for nme, c in phase_costs(sub0, bf16).items() if nme in phase_ms}
     peaks = {nme: matrix_peak(nme, b, bf16) for nme in costs}
+    launch_ms = {nme: v / S for nme, v in phase_ms.items()}
     dom = max([nme for nme in ("project", "project_backward") if nme in phase_ms], key=lambda nme: phase_ms[nme])
-    roof = roofline_entry(costs[dom][0], costs[dom][1], phase_ms[dom] * 1e-3, peaks[dom][0])
+    roof = roofline_entry(costs[dom][0], costs[dom][1], launch_ms[dom] * 1e-3, peaks[dom][0])
     roof["matrix_path"] = peaks[dom][1]
-    roof["kernel"] = "fmap_project (split-K partials + fixed-order reduce)" if dom == "project" else \
-        "fmap_project_backward"
-    tr = measured_traffic(dom, args.workload)
+    roof["kernel"] = ("fmap_project (split-K partials + fixed-order reduce)" if dom == "project" else
+                      "fmap_project_backward") + f", one launch = {len(subs[0])} pairs"
+    tr = measured_traffic(dom, args.workload, len(subs[0]))
     roof["traffic"] = None if tr is None else tr["bytes"]
     if tr is not None:
         roof["traffic_detail"] = tr | {"algorithmic_bytes": round(costs[dom][1])}
     roof["phase_us"] = {k: round(v * 1e3, 2) for k, v in phase_ms.items()}
-    roof["phase_timing"] = "K eager steps after the timed ones, HIP events between phases, mean over the K steps"
-    t_roof = sum(max(f / (peaks[nme][0] * 1e12), by / (HBM_PEAK_GBS * 1e9)) for nme, (f, by) in costs.items())
+    roof["phase_timing"] = (f"K eager steps after the timed ones, the {S} sub-batches in sequence, HIP events "
+                            "between phases; summed over sub-batches, mean over the K steps")
+    full_costs = {nme: c for nme, c in phase_costs(b, bf16).items() if nme in phase_ms}
+    t_roof = sum(max(f / (peaks[nme][0] * 1e12), by / (HBM_PEAK_GBS * 1e9)) for nme, (f, by) in full_costs.items())
     roof["step_roofline_us"] = round(t_roof * 1e6, 2)
     roof["step_frac"] = round(t_roof * 1e3 / ms, 4)
+    step_bytes = sum(by for _, by in full_costs.values())
+    roof["step_hbm_GBs"] = round(step_bytes / (ms * 1e-3) / 1e9, 1)
 
-    acc = accuracy(b, steps[0])
-    cpu = None if (args.no_cpu_baseline or fwd_only) else cpu_baseline(b, args.cpu_seconds)
+    vs_plain = None
+    if not args.no_plain and not fwd_only:
+        pv, pms, pstats, psteps = plain_leg(args, F, b, dev, base_full(b, dev, upload, P), opts)
+        pacc = accuracy_plain(b, psteps, pairs=(0, P - 1))
+        vs_plain = {"value": round(pv, 1), "unit": "solves/s", "ms_per_step": round(pms, 5), "step_ms": pstats,
+                    "ratio": round((P / (ms * 1e-3)) / pv, 3), "accuracy_vs_oracle": pacc,
+                    "path": "plain float32 GPU path: per-pair library calls, eager launches, no graph, no "
+                            "sub-batches, factors stored"}
+    cpu = None if (args.no_cpu_baseline or fwd_only) else cpu_baseline(b, args.cpu_seconds, args.workload)
     out = {
         "metric": "functional map solves/sec (fwd+bwd) at k=50,d=256,batch 32" if args.workload == "headline"
         else f"functional map solves/sec ({'fwd' if fwd_only else 'fwd+bwd'}), {b.name}",
@@ -494,19 +707,28 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 5),
+        "step_ms": step_stats,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
+        "vs_plain": vs_plain,
         "dtype": "bf16-proj/f32" if bf16 else "f32",
         "data": "synthetic",
         "config": {"workload": b.name, "pairs": P, "n": b.n, "k": b.k, "d": b.d,
                    "mask": "resolvent" if b.mask == 1 else "laplacian", "lambda": float(b.lam[0]),
-                   "backward": args.bwd, "graph": not args.no_graph, **SOLVE_OPTS.get(args.workload, {})},
+                   "backward": args.bwd, "graph": not args.no_graph, "sub_batches": S, **opts},
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy_vs_oracle": acc,
     }
+    if args.workload == "large":
+        out["peak_hbm_bytes"] = int(torch.cuda.max_memory_allocated(dev))
     print(json.dumps(out), flush=True)
+
+
+def base_full(b, dev, upload, P):
+    """The whole batch as one [2P] upload (the plain leg's per-pair slices index it)."""
+    return upload(list(range(P)))
 
 
 if __name__ == "__main__":

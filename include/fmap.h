@@ -176,9 +176,17 @@ fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, 
 fmap_status fmap_plan_forward(fmap_plan *plan, void *stream);   /* replays the captured forward  */
 fmap_status fmap_plan_backward(fmap_plan *plan, void *stream);  /* replays the captured backward */
 /* Tuned parameters: vertices per projection work item, persistent grid size,   */
-/* row systems per workgroup, and whether they came from the cache (1) or a run. */
+/* row systems per workgroup of the first group with k <= 64 (4 if there is     */
+/* none), and whether they came from the cache (1) or a run.  Any pointer may   */
+/* be NULL.                                                                     */
 fmap_status fmap_plan_tuning(const fmap_plan *plan, int32_t *chunk, int32_t *grid, int32_t *systems_per_wg,
                              int32_t *from_cache);
+/* The plan's k groups, in increasing k: *groups = their number (any pointer   */
+/* may be NULL).  For group g (0 <= g < groups; FMAP_ERR_VALUE otherwise):      */
+/* its k, its number of pairs, and the row systems per workgroup the tuner     */
+/* picked for it (1, 2 or 4 for k <= 64; 1 for the tiled solve of larger k).    */
+fmap_status fmap_plan_groups(const fmap_plan *plan, int32_t *groups);
+fmap_status fmap_plan_group(const fmap_plan *plan, int32_t g, int32_t *k, int32_t *npairs, int32_t *systems_per_wg);
 fmap_status fmap_plan_destroy(fmap_plan *plan);
 
 #ifdef __cplusplus

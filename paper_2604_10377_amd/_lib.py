@@ -36,6 +36,8 @@ SIGNATURES = {
     "fmap_plan_forward": (_i32, [_vp, _vp]),
     "fmap_plan_backward": (_i32, [_vp, _vp]),
     "fmap_plan_tuning": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "fmap_plan_groups": (_i32, [_vp, _vp]),
+    "fmap_plan_group": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "fmap_plan_destroy": (_i32, [_vp]),
 }
 

@@ -36,6 +36,18 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+def build_id() -> str:
+    """Hash of every kernel source and header (keys the plan's tuning cache to this build)."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sources() + sorted(glob.glob(os.path.join(CSRC, "*.h"))) + [os.path.join(os.path.dirname(HERE), "include",
+                                                                                    "fmap.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str, extra) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
     cmd = [HIPCC] + CFLAGS + list(extra) + ["-c", src, "-o", obj]
@@ -66,6 +78,7 @@ def build(extra=(), jobs: int = 8) -> str:
     """Compile every HIP source for gfx950 and link libfmap.so; returns its path."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = sources()
+    extra = list(extra) + [f'-DFMAP_BUILD_ID="{build_id()}"']
     with cf.ThreadPoolExecutor(max_workers=min(jobs, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, extra), srcs))
     tmp = OUT + ".tmp"

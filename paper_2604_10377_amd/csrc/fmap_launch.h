@@ -71,8 +71,6 @@ hipError_t launch_project_backward_f32_split(const float *phi, const float *mass
 hipError_t launch_project_bf16(const uint16_t *phi, const float *mass, const uint16_t *feat, int64_t batch, int64_t n,
                                int64_t k, int64_t d, float *A, void *ws, hipStream_t st);
 int device_cus();
-int rowsolve_waves();
-void set_rowsolve_waves(int w);
 
 struct ProjPlan {
     int MT, NT, kblocks, dblocks, nsplit, chunk;
@@ -85,6 +83,7 @@ hipError_t launch_project(const void *phi, const float *mass, const void *feat, 
 hipError_t launch_project_backward(const void *phi, const float *mass, int32_t dtype, const float *dA, int64_t batch,
                                    int64_t n, int64_t k, int64_t d, float *dF, hipStream_t st);
 
+// rs_waves: row systems per workgroup of the register row solve (k_x <= kSmallK): 1, 2 or 4.
 // Workspace carve-up of the solver (byte offsets, 256-aligned).
 struct SolveWs {
     size_t K, R, V, W, tiles, K64, R64, dlam, total;
@@ -94,11 +93,11 @@ SolveWs solve_workspace_layout(int64_t pairs, int64_t kx, int64_t ky, int64_t d)
 hipError_t launch_solve(const float *A, const float *B, const float *ex, const float *ey, const float *lam,
                         int32_t mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, int64_t d,
                         int32_t refine_steps, float cond_threshold, float *C, float *factors, int32_t *info,
-                        float *cond_est, void *ws, hipStream_t st);
+                        float *cond_est, void *ws, hipStream_t st, int rs_waves = 4);
 hipError_t launch_solve_backward(const float *dC, const float *A, const float *B, const float *C, const float *ex,
                                  const float *ey, const float *lam, int32_t mask_kind, float gamma, int64_t P,
                                  int64_t kx, int64_t ky, int64_t d, const float *factors, float *dA, float *dB,
-                                 float *dlam, int32_t *info, void *ws, hipStream_t st);
+                                 float *dlam, int32_t *info, void *ws, hipStream_t st, int rs_waves = 4);
 
 // Row solves with stored factors (reverse mode, refinement correction) by streaming triangular solves.
 void launch_trisolve_stored(const float *Lin, const float *rhs, const float *ex, const float *ey, const float *lam,

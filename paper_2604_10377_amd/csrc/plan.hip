@@ -62,6 +62,7 @@ using namespace fmap;
 struct Bucket {
     int64_t k = 0;
     std::vector<int> pairs;
+    int waves = 4;             // row systems per workgroup of the register row solve (k <= kSmallK)
     int mc_off = 0, mc_n = 0;  // this group's backward items in the emulated-kernel table
     float *AB = nullptr, *dAB = nullptr, *C = nullptr, *factors = nullptr, *evx = nullptr, *evy = nullptr,
           *lam = nullptr, *dC = nullptr;
@@ -89,7 +90,7 @@ struct fmap_plan {
     int nbwd = 0;
     CopyItem *d_gf = nullptr, *d_sf = nullptr, *d_gb = nullptr;
     int ngf = 0, nsf = 0, ngb = 0;
-    int chunk = 1024, grid_fwd = 512, grid_bwd = 512, rb = 2, waves = 4, from_cache = 0;
+    int chunk = 1024, grid_fwd = 512, grid_bwd = 512, rb = 2, from_cache = 0;
     hipStream_t cap = nullptr;
     hipGraph_t gf = nullptr, gb = nullptr;
     hipGraphExec_t ef = nullptr, eb = nullptr;
@@ -356,14 +357,13 @@ hipError_t record_forward(fmap_plan *pl, hipStream_t st)
 {
     hipError_t e = launch_copies(pl->d_gf, pl->ngf, st);
     if (e == hipSuccess) e = launch_projections_fwd(pl, pl->grid_fwd, st);
-    set_rowsolve_waves(pl->waves);
     for (Bucket &B : pl->buckets) {
         if (e != hipSuccess) break;
         const int64_t P = (int64_t)B.pairs.size();
         e = launch_solve(B.AB, B.AB + (size_t)P * B.k * pl->d, B.evx, B.evy, B.lam, pl->mask_kind, pl->gamma, P, B.k,
-                         B.k, pl->d, 0, 0.f, B.C, pl->recompute ? nullptr : B.factors, B.info, nullptr, B.ws, st);
+                         B.k, pl->d, 0, 0.f, B.C, pl->recompute ? nullptr : B.factors, B.info, nullptr, B.ws, st,
+                         B.waves);
     }
-    set_rowsolve_waves(4);
     if (e == hipSuccess) e = launch_copies(pl->d_sf, pl->nsf, st);
     return e;
 }
@@ -371,16 +371,14 @@ hipError_t record_forward(fmap_plan *pl, hipStream_t st)
 hipError_t record_backward(fmap_plan *pl, hipStream_t st)
 {
     hipError_t e = launch_copies(pl->d_gb, pl->ngb, st);
-    set_rowsolve_waves(pl->waves);
     for (Bucket &B : pl->buckets) {
         if (e != hipSuccess) break;
         const int64_t P = (int64_t)B.pairs.size();
         const size_t half = (size_t)P * B.k * pl->d;
         e = launch_solve_backward(B.dC, B.AB, B.AB + half, B.C, B.evx, B.evy, B.lam, pl->mask_kind, pl->gamma, P, B.k,
                                   B.k, pl->d, pl->recompute ? nullptr : B.factors, B.dAB, B.dAB + half, nullptr,
-                                  nullptr, B.ws, st);
+                                  nullptr, B.ws, st, B.waves);
     }
-    set_rowsolve_waves(4);
     if (e == hipSuccess) e = launch_projections_bwd(pl, pl->grid_bwd, st);
     return e;
 }
@@ -419,41 +417,58 @@ float time_ms(hipStream_t st, Fn fn, int reps = 3)
     return t[t.size() / 2];
 }
 
+#ifndef FMAP_BUILD_ID
+#define FMAP_BUILD_ID "unversioned"
+#endif
+
+// Cache key: the library build (a hash of its kernel sources), the pass set (forward only, or with a
+// backward pass storing or recomputing the factors) and the workload (d, mask, vertex total, k histogram).
 std::string signature(const fmap_plan *pl)
 {
     int64_t verts = 0;
     for (const fmap_pair &p : pl->pairs) verts += p.n_x + p.n_y;
-    char buf[256];
+    char buf[320];
     std::string ks;
     for (const Bucket &B : pl->buckets) ks += std::to_string(B.k) + "x" + std::to_string(B.pairs.size()) + ",";
-    std::snprintf(buf, sizeof buf, "gfx950 f32 d=%lld mask=%d bwd=%d verts=%lldk pairs=%zu k=", (long long)pl->d,
-                  pl->mask_kind, pl->recompute ? 1 : 0, (long long)(verts / 1000), pl->pairs.size());
+    const int pass = !pl->has_bwd ? 0 : (pl->recompute ? 2 : 1);
+    std::snprintf(buf, sizeof buf, "gfx950 build=%s f32 d=%lld mask=%d pass=%d verts=%lldk pairs=%zu k=",
+                  FMAP_BUILD_ID, (long long)pl->d, pl->mask_kind, pass, (long long)(verts / 1000), pl->pairs.size());
     return std::string(buf) + ks;
 }
 
+// Line format: "<signature>|chunk grid_fwd rb grid_bwd w_0 w_1 ..." with one row-solve width per k group.
 bool cache_lookup(const char *path, const std::string &sig, fmap_plan *pl)
 {
     if (!path) return false;
     FILE *f = std::fopen(path, "r");
     if (!f) return false;
-    char line[1024];
+    char line[2048];
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
         std::string s(line);
         const size_t bar = s.find('|');
         if (bar == std::string::npos || s.substr(0, bar) != sig) continue;
-        int c, gfm, w, rb, gbm;
+        int c, gfm, rb, gbm, used = 0;
+        const char *q = s.c_str() + bar + 1;
         // only values the tuner itself can produce: the partial slots are sized for the smallest chunk
-        if (std::sscanf(s.c_str() + bar + 1, "%d %d %d %d %d", &c, &gfm, &w, &rb, &gbm) == 5 &&
-            (c == 512 || c == 1024 || c == 2048) && gfm >= 1 && gfm <= 65535 && (w == 1 || w == 2 || w == 4) &&
-            (rb == 1 || rb == 2 || rb == 4 || rb == 8) && gbm >= 1 && gbm <= 65535) {
-            pl->chunk = c;
-            pl->grid_fwd = gfm;
-            pl->waves = w;
-            pl->rb = rb;
-            pl->grid_bwd = gbm;
-            found = true;  // the last matching line wins
+        if (std::sscanf(q, "%d %d %d %d%n", &c, &gfm, &rb, &gbm, &used) != 4 ||
+            !(c == 512 || c == 1024 || c == 2048) || gfm < 1 || gfm > 65535 ||
+            !(rb == 1 || rb == 2 || rb == 4 || rb == 8) || gbm < 1 || gbm > 65535)
+            continue;
+        q += used;
+        std::vector<int> w(pl->buckets.size());
+        bool ok = true;
+        for (size_t b = 0; b < w.size() && ok; ++b) {
+            ok = std::sscanf(q, "%d%n", &w[b], &used) == 1 && (w[b] == 1 || w[b] == 2 || w[b] == 4);
+            q += ok ? used : 0;
         }
+        if (!ok) continue;
+        pl->chunk = c;
+        pl->grid_fwd = gfm;
+        pl->rb = rb;
+        pl->grid_bwd = gbm;
+        for (size_t b = 0; b < w.size(); ++b) pl->buckets[b].waves = w[b];
+        found = true;  // the last matching line wins
     }
     std::fclose(f);
     return found;
@@ -464,7 +479,9 @@ void cache_store(const char *path, const std::string &sig, const fmap_plan *pl)
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s|%d %d %d %d %d\n", sig.c_str(), pl->chunk, pl->grid_fwd, pl->waves, pl->rb, pl->grid_bwd);
+    std::fprintf(f, "%s|%d %d %d %d", sig.c_str(), pl->chunk, pl->grid_fwd, pl->rb, pl->grid_bwd);
+    for (const Bucket &B : pl->buckets) std::fprintf(f, " %d", B.waves);
+    std::fprintf(f, "\n");
     std::fclose(f);
 }
 
@@ -619,29 +636,28 @@ fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, 
         }
         pl->chunk = bc;
         pl->grid_fwd = bg;
-        // row systems per workgroup of the register row solve (groups with k <= 64)
+        // row systems per workgroup of the register row solve, per k group (k <= 64; the tiled solve of
+        // larger k runs one system per workgroup)
         FMAP_TRY(set_fwd(pl->chunk));
         FMAP_TRY(launch_copies(pl->d_gf, pl->ngf, st));
         FMAP_TRY(launch_projections_fwd(pl, pl->grid_fwd, st));
-        best = 1e30f;
-        int bw = 4;
-        for (int w : {1, 2, 4}) {
-            const float t = time_ms(st, [&]() {
-                set_rowsolve_waves(w);
-                for (Bucket &B : pl->buckets) {
-                    if (B.k > kSmallK) continue;
-                    const int64_t P = (int64_t)B.pairs.size();
+        for (Bucket &B : pl->buckets) {
+            if (B.k > kSmallK) continue;
+            const int64_t P = (int64_t)B.pairs.size();
+            best = 1e30f;
+            int bw = 4;
+            for (int w : {1, 2, 4}) {
+                const float t = time_ms(st, [&]() {
                     (void)launch_solve(B.AB, B.AB + (size_t)P * B.k * d, B.evx, B.evy, B.lam, mask_kind, gamma, P, B.k,
-                                       B.k, d, 0, 0.f, B.C, B.factors, B.info, nullptr, B.ws, st);
+                                       B.k, d, 0, 0.f, B.C, B.factors, B.info, nullptr, B.ws, st, w);
+                });
+                if (t < best) {
+                    best = t;
+                    bw = w;
                 }
-                set_rowsolve_waves(4);
-            });
-            if (t < best) {
-                best = t;
-                bw = w;
             }
+            B.waves = bw;
         }
-        pl->waves = bw;
         // backward projection: rows per item x persistent grid
         if (bwd) {
             best = 1e30f;
@@ -709,8 +725,33 @@ fmap_status fmap_plan_tuning(const fmap_plan *plan, int32_t *chunk, int32_t *gri
     if (!plan) return FMAP_ERR_NULL;
     if (chunk) *chunk = plan->chunk;
     if (grid) *grid = plan->grid_fwd;
-    if (systems_per_wg) *systems_per_wg = plan->waves;
+    if (systems_per_wg) {
+        *systems_per_wg = 4;
+        for (const Bucket &B : plan->buckets)
+            if (B.k <= kSmallK) {
+                *systems_per_wg = B.waves;
+                break;
+            }
+    }
     if (from_cache) *from_cache = plan->from_cache;
+    return FMAP_OK;
+}
+
+fmap_status fmap_plan_groups(const fmap_plan *plan, int32_t *groups)
+{
+    if (!plan) return FMAP_ERR_NULL;
+    if (groups) *groups = (int32_t)plan->buckets.size();
+    return FMAP_OK;
+}
+
+fmap_status fmap_plan_group(const fmap_plan *plan, int32_t g, int32_t *k, int32_t *npairs, int32_t *systems_per_wg)
+{
+    if (!plan) return FMAP_ERR_NULL;
+    if (g < 0 || g >= (int32_t)plan->buckets.size()) return FMAP_ERR_VALUE;
+    const Bucket &B = plan->buckets[(size_t)g];
+    if (k) *k = (int32_t)B.k;
+    if (npairs) *npairs = (int32_t)B.pairs.size();
+    if (systems_per_wg) *systems_per_wg = B.k <= kSmallK ? B.waves : 1;
     return FMAP_OK;
 }
 

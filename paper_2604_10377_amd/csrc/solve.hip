@@ -559,19 +559,15 @@ static void launch_gram(const float *A, const float *B, int64_t P, int64_t kx, i
                        (int)ky, (int)d, tkx, tky, with_R ? 1 : 0, K, R);
 }
 
-// Row systems (waves) per workgroup of the register row solve; the plan's
-// autotuner overrides it for the launches it records.
-static thread_local int g_rowsolve_waves = 4;
-int rowsolve_waves() { return g_rowsolve_waves; }
-void set_rowsolve_waves(int w) { g_rowsolve_waves = (w == 1 || w == 2 || w == 4) ? w : 4; }  // <= launch bound
-
+// W = row systems (waves) per workgroup of the register row solve: 1, 2 or 4 (the launch bound); the
+// plan's autotuner picks it per k group.
 template <int MODE>
 static void launch_rowsolve(const float *K, const float *rhs, const float *ex, const float *ey,
                             const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky,
                             float *out, float *Lout, int *info, const float *Cfwd, float *dlam_part, hipStream_t st,
-                            const float *addend = nullptr)
+                            int W)
 {
-    const int W = rowsolve_waves();
+    if (W != 1 && W != 2) W = 4;
     const unsigned grid = (unsigned)(P * ((ky + W - 1) / W));
     // dynamic LDS: W x (4 KM + KM (KM + 4)) floats, at most 4 x 4352 floats (68 KB)
 #define FMAP_RS(KM)                                                                                             \
@@ -585,7 +581,7 @@ static void launch_rowsolve(const float *K, const float *rhs, const float *ex, c
             attr_ = true;                                                                                       \
         }                                                                                                       \
         hipLaunchKernelGGL((rowsolve_kernel<KM, MODE>), dim3(grid), dim3(64 * W), lds_, st, K, rhs, ex, ey,  \
-                           lam, mask_kind, gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part, addend);   \
+                           lam, mask_kind, gamma, (int)kx, (int)ky, out, Lout, info, Cfwd, dlam_part, nullptr);  \
     } while (0)
     if (kx <= 8) FMAP_RS(8);
     else if (kx <= 16) FMAP_RS(16);
@@ -601,7 +597,7 @@ static void launch_rowsolve(const float *K, const float *rhs, const float *ex, c
 hipError_t launch_solve(const float *A, const float *B, const float *ex, const float *ey, const float *lam,
                         int32_t mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, int64_t d,
                         int32_t refine_steps, float cond_threshold, float *C, float *factors, int32_t *info,
-                        float *cond_est, void *ws, hipStream_t st)
+                        float *cond_est, void *ws, hipStream_t st, int rs_waves)
 {
     SolveWs L = solve_workspace_layout(P, kx, ky, d);
     char *base = (char *)ws;
@@ -615,7 +611,7 @@ hipError_t launch_solve(const float *A, const float *B, const float *ex, const f
                     refine_steps > 0 ? R64 : nullptr, K, R, cond_est, st);
     if (kx <= kSmallK)
         launch_rowsolve<RS_FWD>(K, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info, nullptr,
-                                nullptr, st);
+                                nullptr, st, rs_waves);
     else
         launch_rowsolve_tiled(RS_FWD, K, nullptr, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info,
                               nullptr, nullptr, tiles, st);
@@ -636,7 +632,7 @@ hipError_t launch_solve(const float *A, const float *B, const float *ex, const f
 hipError_t launch_solve_backward(const float *dC, const float *A, const float *B, const float *C, const float *ex,
                                  const float *ey, const float *lam, int32_t mask_kind, float gamma, int64_t P,
                                  int64_t kx, int64_t ky, int64_t d, const float *factors, float *dA, float *dB,
-                                 float *dlam, int32_t *info, void *ws, hipStream_t st)
+                                 float *dlam, int32_t *info, void *ws, hipStream_t st, int rs_waves)
 {
     SolveWs L = solve_workspace_layout(P, kx, ky, d);
     char *base = (char *)ws;
@@ -651,7 +647,7 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
         launch_gram(A, B, P, kx, ky, d, false, K, nullptr, st);
         if (small)
             launch_rowsolve<RS_BWD_RECOMPUTE>(K, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, nullptr,
-                                              info, C, dl, st);
+                                              info, C, dl, st, rs_waves);
         else
             launch_rowsolve_tiled(RS_BWD_RECOMPUTE, K, nullptr, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V,
                                   nullptr, info, C, dl, (float *)(base + L.tiles), st);

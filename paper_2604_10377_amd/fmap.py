@@ -301,6 +301,17 @@ class FmapPlan:
         _lib.check("fmap_plan_tuning", _lib.lib().fmap_plan_tuning(self._h, *[ctypes.byref(x) for x in v]))
         return dict(chunk=v[0].value, grid=v[1].value, systems_per_wg=v[2].value, from_cache=bool(v[3].value))
 
+    def groups(self) -> list:
+        """Per k group (increasing k): dict(k, pairs, systems_per_wg) as tuned for this plan."""
+        n = ctypes.c_int32()
+        _lib.check("fmap_plan_groups", _lib.lib().fmap_plan_groups(self._h, ctypes.byref(n)))
+        out = []
+        for g in range(n.value):
+            v = [ctypes.c_int32() for _ in range(3)]
+            _lib.check("fmap_plan_group", _lib.lib().fmap_plan_group(self._h, g, *[ctypes.byref(x) for x in v]))
+            out.append(dict(k=v[0].value, pairs=v[1].value, systems_per_wg=v[2].value))
+        return out
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.check("fmap_plan_destroy", _lib.lib().fmap_plan_destroy(self._h))

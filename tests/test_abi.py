@@ -160,4 +160,6 @@ def test_plan_validation(L):
     assert L.fmap_plan_forward(NULL, None) == 1
     assert L.fmap_plan_backward(NULL, None) == 1
     assert L.fmap_plan_tuning(NULL, NULL, NULL, NULL, NULL) == 1
+    assert L.fmap_plan_groups(NULL, NULL) == 1
+    assert L.fmap_plan_group(NULL, 0, NULL, NULL, NULL) == 1
     assert L.fmap_plan_destroy(NULL) == 1

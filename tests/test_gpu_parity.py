@@ -119,8 +119,10 @@ def test_project_backward_bf16_matrix_cores(F, dev, b, n, k, d):
 
 
 # float32 backward with 64 < k <= 319, k even (64-column blocks, every K step's dA^T parts in LDS): partial
-# column blocks, partial vertex tiles, d % 4 != 0 (element stores), one and ten K steps of 32
-BWDK_CASES = [(2, 1028, 80, 260), (1, 2052, 300, 516), (1, 999, 130, 33), (2, 4004, 318, 64), (1, 600, 66, 8)]
+# column blocks, partial vertex tiles, d % 4 != 0 (element stores), three to ten K steps of 32 (k = 120 and
+# k = 150 are the uneven workload's large groups: four and five K steps)
+BWDK_CASES = [(2, 1028, 80, 260), (1, 2052, 300, 516), (1, 999, 130, 33), (2, 4004, 318, 64), (1, 600, 66, 8),
+              (2, 3001, 120, 256), (1, 20000, 120, 256), (1, 2500, 150, 200), (2, 1500, 96, 128)]
 
 
 @pytest.mark.parametrize("b,n,k,d", [(1, 1, 1, 1), (2, 37, 5, 7), (3, 1234, 30, 128), (2, 5000, 50, 256),
@@ -214,12 +216,12 @@ def test_solve_backward(F, dev, mask, stored, P, kx, ky, d):
 
 
 # Tiled row solve (k_x > 64): tile-boundary sizes, the workspace-tile variant (k_x >= 224), rectangular maps.
-# The float32 error of a k x k Cholesky grows with k; inputs keep cond(A A^T) near 30 (d = 2k) and the bar
-# for these sizes is stated per case (derived: ~sqrt(k) * 6e-8 * cond(S)).
-LARGE_CASES = [(2, 65, 65, 160, 1e-5), (2, 96, 96, 200, 1e-5), (2, 127, 127, 256, 1e-5), (1, 128, 128, 256, 1e-5),
-               (1, 150, 150, 300, 2e-5), (1, 200, 200, 400, 2e-5), (1, 223, 223, 450, 2e-5),
-               (1, 224, 224, 450, 2e-5), (1, 300, 300, 600, 3e-5), (1, 319, 319, 640, 3e-5),
-               (2, 100, 40, 200, 1e-5), (2, 30, 100, 128, 1e-5)]
+# Inputs keep cond(A A^T) near 30 (d = 2k); the float32 bar of 1e-5 holds at every k (measured C <= 1.4e-6,
+# gradients <= 1.9e-6 at k = 319).
+LARGE_CASES = [(2, 65, 65, 160, TOL), (2, 96, 96, 200, TOL), (2, 127, 127, 256, TOL), (1, 128, 128, 256, TOL),
+               (1, 150, 150, 300, TOL), (1, 200, 200, 400, TOL), (1, 223, 223, 450, TOL),
+               (1, 224, 224, 450, TOL), (1, 300, 300, 600, TOL), (1, 319, 319, 640, TOL),
+               (2, 100, 40, 200, TOL), (2, 30, 100, 128, TOL)]
 
 
 @pytest.mark.parametrize("mask", [0, 1])
@@ -356,6 +358,42 @@ def test_pipeline_headline_workload_full_size(F, dev, bwd):
         assert rel_fro(dF[P + p], dFy) <= TOL, (p, rel_fro(dF[P + p], dFy))
 
 
+def test_pipeline_headline_shape_regulariser_weighted(F, dev):
+    """Headline shape (32 pairs, n=5000, k=50, d=256, resolvent mask) with lambda from 1 to 4, where lambda
+    times the mean mask entry is 1-5% of the mean diagonal of A A^T (at lambda = 1e-3 it is ~1e-5 of it,
+    and C is nearly the lambda = 0 solution):
+    C and dF of sampled pairs against the oracle, and the regulariser visibly moves the oracle's C."""
+    b = synth.make_batch("headline-shape-lambda1", 12, 32, 5000, 50, 256, mask=synth.MASK_RESOLVENT, gamma=0.5,
+                         lam=np.geomspace(1.0, 4.0, 32))
+    C, info, dF = _pipeline_gpu(F, b, dev, "stored")
+    assert (info == 0).all()
+    P = b.pairs
+    for p in (0, 13, P - 1):
+        Cr, ir, dFx, dFy = _pipeline_oracle_pair(b, p)
+        assert rel_fro(C[p], Cr) <= TOL, (p, rel_fro(C[p], Cr))
+        assert rel_fro(dF[p], dFx) <= TOL, (p, rel_fro(dF[p], dFx))
+        assert rel_fro(dF[P + p], dFy) <= TOL, (p, rel_fro(dF[P + p], dFy))
+    A, B, D, Cr, _ = oracle.forward_pair(b.phi[0], b.mass[0], b.feat[0], b.phi[P], b.mass[P], b.feat[P], b.evals[0],
+                                         b.evals[P], float(b.lam[0]), b.mask, b.gamma)
+    C0, _ = oracle.solve(A, B, D, 0.0)
+    assert rel_fro(Cr, C0) >= 1e-2  # the mask term shapes the solution
+
+
+def test_pipeline_large_workload_full_size(F, dev):
+    """Large-basis workload at full size: n=100000, k=300, d=512, resolvent mask, factor recomputation in the
+    backward (two pairs: the kernels' split counts and tile ranges depend on n, k and d, not on the number
+    of pairs); C and dF of pair 1 against the oracle."""
+    b = synth.workload_large(pairs=2)
+    print("large workload", b.pairs, b.n, b.k, b.d, flush=True)
+    C, info, dF = _pipeline_gpu(F, b, dev, "recompute")
+    assert (info == 0).all()
+    P, p = b.pairs, 1
+    Cr, ir, dFx, dFy = _pipeline_oracle_pair(b, p)
+    errs = (rel_fro(C[p], Cr), rel_fro(dF[p], dFx), rel_fro(dF[P + p], dFy))
+    print("large pair", p, "errors C, dF_x, dF_y", errs, flush=True)
+    assert max(errs) <= TOL, errs
+
+
 def test_pipeline_plain_workload_full_size(F, dev):
     """1 pair, n=5000, k=30, d=128, Laplacian mask, forward."""
     import torch
@@ -486,13 +524,15 @@ def test_fp64_normal_matrix_branch(F, dev):
 BF16_PATH_TOL = 2e-3  # stated bar of the bf16-projection path (C and dF against the oracle on the same bf16 inputs)
 
 
-def test_mixed_precision_pipeline(F, dev):
+@pytest.mark.parametrize("pairs,n", [(2, 6000), (4, 50000)])
+def test_mixed_precision_pipeline(F, dev, pairs, n):
     """bf16 projections, float32 row solves with one float64-residual refinement step and the float64
-    normal matrix above a condition estimate of 1e6, backward through the bf16 projection: per-pair C and
-    dF against the oracle fed the same bf16-rounded inputs (reduced n; k, d and the spectra of the
-    mixed-precision workload)."""
+    normal matrix above a condition estimate of 1e6, backward through the bf16 projection, at the mixed
+    workload's k, d and spectra (n=50000 is its full size; n=6000 a reduced one).  Per pair, C and dF
+    against the oracle fed the same bf16-rounded inputs (the path's own error), and against the oracle fed
+    the unrounded float32 inputs (the path's error including the bf16 rounding of basis and features)."""
     import torch
-    b = synth.workload_mixed(pairs=2, n=6000)
+    b = synth.workload_mixed(pairs=pairs, n=n)
     P = b.pairs
     phi = torch.from_numpy(b.phi_bf16.view(np.int16)).to(dev).view(torch.bfloat16)
     feat = torch.from_numpy(b.feat_bf16.view(np.int16)).to(dev).view(torch.bfloat16)
@@ -505,14 +545,16 @@ def test_mixed_precision_pipeline(F, dev):
                           b.mask, b.gamma, fac, dA=dAB[:P], dB=dAB[P:])
     dF = N(F.fmap_project_backward(phi, mass, dAB))
     C, info = N(C), N(info)
-    ph, fe = b.phi_consumed(), b.feat_consumed()
-    for p in range(P):
-        A, B, D, Cr, ir = oracle.forward_pair(ph[p], b.mass[p], fe[p], ph[P + p], b.mass[P + p], fe[P + p],
-                                              b.evals_x[p], b.evals_y[p], float(b.lam[p]), b.mask, b.gamma)
-        dA, dB, _ = oracle.solve_backward(A, B, Cr, D, float(b.lam[p]), b.dC[p])
-        errs = (rel_fro(C[p], Cr), rel_fro(dF[p], oracle.project_backward(ph[p], b.mass[p], dA)),
-                rel_fro(dF[P + p], oracle.project_backward(ph[P + p], b.mass[P + p], dB)))
-        print("mixed pair", p, "errors C, dF_x, dF_y:", errs, "cond", float(N(cond)[p]), flush=True)
-        assert np.array_equal(info[p], ir)
-        assert max(errs) <= BF16_PATH_TOL
-        assert errs[0] <= 1e-4  # the refinement step leaves the projection's float32 sums as the error
+    for p in sorted({0, P - 1}):
+        for label, ph, fe in (("same bf16 inputs", b.phi_consumed(), b.feat_consumed()),
+                              ("unrounded inputs", b.phi, b.feat)):
+            A, B, D, Cr, ir = oracle.forward_pair(ph[p], b.mass[p], fe[p], ph[P + p], b.mass[P + p], fe[P + p],
+                                                  b.evals_x[p], b.evals_y[p], float(b.lam[p]), b.mask, b.gamma)
+            dA, dB, _ = oracle.solve_backward(A, B, Cr, D, float(b.lam[p]), b.dC[p])
+            errs = (rel_fro(C[p], Cr), rel_fro(dF[p], oracle.project_backward(ph[p], b.mass[p], dA)),
+                    rel_fro(dF[P + p], oracle.project_backward(ph[P + p], b.mass[P + p], dB)))
+            print("mixed pair", p, label, "errors C, dF_x, dF_y:", errs, "cond", float(N(cond)[p]), flush=True)
+            assert np.array_equal(info[p], ir)
+            assert max(errs) <= BF16_PATH_TOL, (p, label, errs)
+            if label == "same bf16 inputs":
+                assert errs[0] <= 1e-4  # the refinement step leaves the projection's float32 sums as the error

@@ -79,6 +79,59 @@ def test_plan_ragged_forward_backward(F, dev, mask, recompute):
     plan.close()
 
 
+# the large-k groups of the uneven workload: k = 120 (four K steps of 32 in the backward projection items)
+# and k = 150 (five), beside a register-solve group; n spans several vertex tiles with ragged tails
+LARGE_GROUPS = dict(pairs=6, d=256, n_lo=900, n_hi=4100, ks=(50, 120, 150))
+
+
+@pytest.mark.parametrize("recompute", [False, True])
+def test_plan_large_k_groups(F, dev, recompute):
+    import torch
+    pairs = synth.workload_ragged(**LARGE_GROUPS)
+    assert {p.k for p in pairs} >= {120, 150}
+    print("plan large-k groups:", [(p.n_x, p.n_y, p.k) for p in pairs], "recompute", recompute, flush=True)
+    dpairs = _device_pairs(pairs, dev)
+    plan = F.FmapPlan(dpairs, synth.MASK_LAPLACIAN, 0.5, backward=True, recompute=recompute, want_AB=True)
+    for i, p in enumerate(pairs):
+        plan.dC[i].copy_(torch.from_numpy(p.dC))
+    plan.forward()
+    plan.backward()
+    torch.cuda.synchronize()
+    _check(plan, pairs, [_oracle(p, synth.MASK_LAPLACIAN, 0.5) for p in pairs], with_AB=True)
+    plan.close()
+
+
+def test_plan_ragged_workload_full_size(F, dev):
+    """The uneven workload at full size: 64 pairs, n ~ U{2000..20000} per shape, k in {30, 50, 80, 120},
+    d = 256, Laplacian mask, lambda per pair; one captured forward and backward.  Checked against the
+    oracle: the first pair of every k group and the pair with the most vertices."""
+    import torch
+    pairs = synth.workload_ragged()
+    dpairs = _device_pairs(pairs, dev)
+    plan = F.FmapPlan(dpairs, synth.MASK_LAPLACIAN, 0.5, backward=True, want_AB=True)
+    for i, p in enumerate(pairs):
+        plan.dC[i].copy_(torch.from_numpy(p.dC))
+    plan.forward()
+    plan.backward()
+    torch.cuda.synchronize()
+    pick = sorted({next(i for i, p in enumerate(pairs) if p.k == k) for k in {p.k for p in pairs}} |
+                  {max(range(len(pairs)), key=lambda i: pairs[i].n_x + pairs[i].n_y)})
+    print("plan full-size ragged: checking pairs", [(i, pairs[i].n_x, pairs[i].n_y, pairs[i].k) for i in pick],
+          flush=True)
+    sel = [pairs[i] for i in pick]
+
+    class View:  # the checked pairs' slots of the plan
+        C = [plan.C[i] for i in pick]
+        info = [plan.info[i] for i in pick]
+        A = [plan.A[i] for i in pick]
+        B = [plan.B[i] for i in pick]
+        dF_x = [plan.dF_x[i] for i in pick]
+        dF_y = [plan.dF_y[i] for i in pick]
+
+    _check(View, sel, [_oracle(p, synth.MASK_LAPLACIAN, 0.5) for p in sel], with_AB=True)
+    plan.close()
+
+
 # shapes of a few stages plus a tail (k = 68: sliced forward and the large-k backward), and shapes below
 # one stage (n < 32: the general kernels only)
 SMALL = [dict(pairs=5, d=256, n_lo=70, n_hi=140, ks=(8, 30, 68)), dict(pairs=3, d=64, n_lo=10, n_hi=31, ks=(8,))]
@@ -141,6 +194,14 @@ def test_plan_tuning_cache_round_trip(F, dev, tmp_path):
     t2 = p2.tuning()
     assert t2["from_cache"] and {k: t2[k] for k in ("chunk", "grid", "systems_per_wg")} == \
         {k: t1[k] for k in ("chunk", "grid", "systems_per_wg")}
+    g1, g2 = p1.groups(), p2.groups()
+    assert [g["k"] for g in g1] == [20, 40] and g1 == g2
+    assert all(g["systems_per_wg"] in (1, 2, 4) for g in g1)
+    # a plan with a backward pass has its own cache entry (the backward parameters are tuned for it)
+    p3 = F.FmapPlan(dpairs, synth.MASK_RESOLVENT, 0.5, backward=True, tune_cache=cache)
+    assert not p3.tuning()["from_cache"]
+    assert cache.read_text().count("\n") == 2
+    p3.close()
     p1.forward()
     p2.forward()
     torch.cuda.synchronize()
