@@ -15,6 +15,9 @@ Functions and the passages they follow (Sec. 3.1 of the paper):
   solve              Eqs. (4)-(7), row-decoupled normal equations, Cholesky
   solve_backward     reverse mode of `solve` (derived)
   pipeline_batch     the whole forward + backward pass over a batch of pairs
+  solve_resolutions  maps at several spectral resolutions from one projection:
+                     resolution (k_x', k_y') is the solve restricted to the
+                     first k_x' source and k_y' target eigenpairs
 
 Pins: every function is checked in ``tests/test_oracle_pins.py`` against closed
 forms, invariants, a Kronecker brute force, library least squares, hand-worked
@@ -167,3 +170,15 @@ def forward_pair(phi_x, mass_x, feat_x, phi_y, mass_y, feat_y, ex, ey, lam, mask
     D = mask(ex, ey, mask_kind, gamma)
     C, info = solve(A, B, D, lam)
     return A, B, D, C, info
+
+
+def solve_resolutions(A, B, evals_x, evals_y, lam: float, mask_kind: int, gamma: float, kxs, kys):
+    """Maps at several spectral resolutions from one pair of spectral descriptors: for each r, the solve of
+    Eqs. (4)-(7) on the first kxs[r] rows of A, the first kys[r] rows of B and the eigenvalues truncated
+    alike (the mask, and the resolvent's normaliser, are those of the truncated spectra).  Returns a list
+    of (C_r [kys[r], kxs[r]], info_r)."""
+    out = []
+    for kx, ky in zip(kxs, kys):
+        D = mask(np.asarray(evals_x)[:kx], np.asarray(evals_y)[:ky], mask_kind, gamma)
+        out.append(solve(np.asarray(A)[:kx], np.asarray(B)[:ky], D, lam))
+    return out

@@ -369,3 +369,42 @@ def test_pipeline_batch_matches_composition():
         dA, dB, _ = oracle.solve_backward(A, B, Cp, D, float(b.lam[p]), b.dC[p])
         np.testing.assert_array_equal(dF[p], oracle.project_backward(b.phi[p], b.mass[p], dA))
         np.testing.assert_array_equal(dF[P + p], oracle.project_backward(b.phi[P + p], b.mass[P + p], dB))
+
+
+# ----------------------------------------------------------------------------- several resolutions
+
+def test_resolutions_full_is_plain_solve():
+    A, B, ex, ey = _problem(41, 9, 20)
+    (C, info), = oracle.solve_resolutions(A, B, ex, ey, 1e-2, L, 0.5, [9], [9])
+    C0, _ = oracle.solve(A, B, oracle.mask(ex, ey, L), 1e-2)
+    np.testing.assert_array_equal(C, C0)
+
+
+def test_resolutions_orthogonal_rows_leading_blocks():
+    """A with orthogonal rows (A A^T = diag(s)), Laplacian mask: C_ij = R_ij / (s_j + lam D_ij) depends on
+    i and j only, so the map at resolution (kx', ky') is the leading ky' x kx' block of the full map."""
+    rng = np.random.default_rng(42)
+    k, d = 12, 30
+    Q = synth.random_orthogonal(rng, d)[:k]
+    s = rng.uniform(0.5, 2.0, k)
+    A = np.sqrt(s)[:, None] * Q
+    B = rng.standard_normal((k, d))
+    ex, ey = synth.eigenvalues_linear(rng, k), synth.eigenvalues_linear(rng, k)
+    lam = 0.3
+    full, = oracle.solve_resolutions(A, B, ex, ey, lam, L, 0.5, [k], [k])
+    R = B @ A.T
+    D = (ey[:, None] - ex[None, :]) ** 2
+    np.testing.assert_allclose(full[0], R / (s[None, :] + lam * D), rtol=0, atol=1e-12)
+    for kx, ky in ((5, 5), (12, 3), (4, 9), (1, 1)):
+        (C, _), = oracle.solve_resolutions(A, B, ex, ey, lam, L, 0.5, [kx], [ky])
+        np.testing.assert_allclose(C, full[0][:ky, :kx], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("mask_kind", [L, R])
+def test_resolutions_brute_force(mask_kind):
+    """A truncated resolution against the Kronecker least squares on the truncated problem."""
+    A, B, ex, ey = _problem(43, 8, 14)
+    for kx, ky in ((6, 4), (3, 8)):
+        (C, _), = oracle.solve_resolutions(A, B, ex, ey, 0.05, mask_kind, 0.5, [kx], [ky])
+        D = oracle.mask(ex[:kx], ey[:ky], mask_kind, 0.5)
+        np.testing.assert_allclose(C, _brute_force(A[:kx], B[:ky], D, 0.05), rtol=0, atol=1e-11)
