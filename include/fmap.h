@@ -82,6 +82,21 @@ fmap_status fmap_project(const void *phi, const float *mass, const void *feat, i
                          int64_t n, int64_t k, int64_t d, float *A, void *workspace, size_t workspace_bytes,
                          void *stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,  */
+/* tight serving loops, harnesses that forbid allocation): fmap_project with  */
+/* no workspace argument.  Its split-K partial sums live in a library-owned    */
+/* device array of FMAP_NOALLOC_SCRATCH_BYTES (32 MiB) per device, held from   */
+/* the library's load until the process ends.  Same arguments, kernels and     */
+/* results as fmap_project.  Returns FMAP_ERR_WORKSPACE when                   */
+/* fmap_project_workspace_bytes(batch, n, k, d, in_dtype) exceeds that size,   */
+/* FMAP_ERR_HIP if the array's device address cannot be obtained.  It calls no */
+/* allocator.  All calls on one device share the array: calls that overlap in  */
+/* time on one device (different streams or threads) race and must not be     */
+/* issued.                                                                     */
+#define FMAP_NOALLOC_SCRATCH_BYTES (32u << 20)
+fmap_status fmap_project_noalloc(const void *phi, const float *mass, const void *feat, int32_t in_dtype,
+                                 int64_t batch, int64_t n, int64_t k, int64_t d, float *A, void *stream);
+
 /* Adjoint of the projection (the chain rule of Eq. (1)):                      */
 /*     dF[b] = diag(mass[b]) Phi[b] dA[b].                                      */
 /* phi [batch][n][k] in `phi_dtype`, mass [batch][n], dA [batch][k][d] float,    */

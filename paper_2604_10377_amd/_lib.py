@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "FMAP_OK", 1: "FMAP_ERR_NULL", 2: "FMAP_ERR_SHAPE", 3: "FMAP_
                 5: "FMAP_ERR_WORKSPACE", 6: "FMAP_ERR_UNSUPPORTED", 7: "FMAP_ERR_HIP"}
 FMAP_MASK_LAPLACIAN, FMAP_MASK_RESOLVENT = 0, 1
 FMAP_F32, FMAP_BF16 = 0, 1
+FMAP_NOALLOC_SCRATCH_BYTES = 32 << 20  # include/fmap.h
 
 # Every symbol include/fmap.h declares, with (restype, argtypes).
 _vp, _i32, _i64, _f32, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
@@ -25,6 +26,7 @@ SIGNATURES = {
     "fmap_status_str": (ctypes.c_char_p, [_i32]),
     "fmap_project_workspace_bytes": (_sz, [_i64, _i64, _i64, _i64, _i32]),
     "fmap_project": (_i32, [_vp, _vp, _vp, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _sz, _vp]),
+    "fmap_project_noalloc": (_i32, [_vp, _vp, _vp, _i32, _i64, _i64, _i64, _i64, _vp, _vp]),
     "fmap_project_backward": (_i32, [_vp, _vp, _i32, _vp, _i64, _i64, _i64, _i64, _vp, _vp]),
     "fmap_solve_workspace_bytes": (_sz, [_i64, _i64, _i64, _i64]),
     "fmap_factor_floats": (_sz, [_i64, _i64]),

@@ -106,6 +106,22 @@ def fmap_project(phi: torch.Tensor, mass: torch.Tensor, feat: torch.Tensor, A: O
     return A
 
 
+def fmap_project_noalloc(phi: torch.Tensor, mass: torch.Tensor, feat: torch.Tensor,
+                         A: torch.Tensor) -> torch.Tensor:
+    """fmap_project with the library's built-in scratch array instead of a workspace (no device allocation
+    by the library; A is the caller's).  Calls overlapping in time on one device must not be issued."""
+    dev = phi.device
+    b, n, k = phi.shape
+    d = feat.shape[-1]
+    _need(phi, "phi", (torch.float32, torch.bfloat16), (b, n, k), dev)
+    _need(feat, "feat", phi.dtype, (b, n, d), dev)
+    _need(mass, "mass", torch.float32, (b, n), dev)
+    _need(A, "A", torch.float32, (b, k, d), dev)
+    _lib.check("fmap_project_noalloc", _lib.lib().fmap_project_noalloc(
+        _ptr(phi), _ptr(mass), _ptr(feat), _dtype_code(phi), b, n, k, d, _ptr(A), _stream(dev)))
+    return A
+
+
 def fmap_project_backward(phi: torch.Tensor, mass: torch.Tensor, dA: torch.Tensor,
                           dF: Optional[torch.Tensor] = None) -> torch.Tensor:
     """dF = diag(mass) Phi dA per batch item."""
