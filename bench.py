@@ -39,7 +39,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--warmup-seconds", type=float, default=1.5,
                     help="untimed replays for this much wall time before the counted warm-up")
-    ap.add_argument("--workload", default="headline", choices=["headline", "plain", "mixed", "large", "ragged"])
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "plain", "mixed", "large", "ragged", "overlap", "gradfeat"])
+    ap.add_argument("--variant", default="A", choices=["A", "B"], help="gradient-feature variant (gradfeat)")
     ap.add_argument("--bwd", default=None, choices=["stored", "recompute"],
                     help="backward mode (default: recompute for the large workload, stored otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -551,6 +553,124 @@ def plain_leg(args, F, b, dev, inputs, opts):
     return P / (ms * 1e-3), ms, stats, steps
 
 
+def timed_calls(fn, args, stream):
+    """Warm-up (time-based, then W calls) and K calls between per-call events: (mean ms, stats)."""
+    warm_up(lambda i: fn(), args)
+    return timed_steps(lambda i: fn(), args.steps, stream)
+
+
+def bench_overlap(args, F, dev):
+    """Overlap metrics of an evaluation batch (1024 shapes of 2000-20000 vertices): one call per step."""
+    import torch
+    from oracle import overlap as ov
+    from paper_2604_10377_amd import synth
+    b = synth.workload_overlap()
+    S, total = b.offsets.shape[0] - 1, int(b.offsets[-1])
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    sc, tr, off = t(b.scores), t(b.truth), t(b.offsets)
+    counts = torch.empty((S, 4), dtype=torch.int64, device=dev)
+    mets = torch.empty((S, 7), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    call = lambda: F.fmap_overlap_metrics(sc, tr, off, 0.5, counts=counts, metrics=mets)
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            call()
+        torch.cuda.synchronize()
+        print(f"profiled {args.profile_steps} overlap-metric calls", flush=True)
+        return
+    ms, stats = timed_calls(call, args, stream)
+    nbytes = total * 5 + 8 * (S + 1) + S * (4 * 8 + 7 * 4)
+    roof = roofline_entry(0.0, nbytes, ms * 1e-3, FP32_PEAK_TFLOPS)
+    roof["kernel"] = "fmap_overlap_metrics (clear, count, metrics kernels; the count pass carries the bytes)"
+    roof["traffic"] = None
+    counts.zero_()
+    call()
+    torch.cuda.synchronize()
+    c, m = counts.cpu().numpy(), mets.cpu().numpy()
+    sel = list(range(0, S, max(1, S // 16)))
+    exact = True
+    for s_ in sel:
+        a, z = int(b.offsets[s_]), int(b.offsets[s_ + 1])
+        rc = ov.confusion_counts(b.scores[a:z], b.truth[a:z], 0.5)
+        exact &= tuple(c[s_]) == rc and np.array_equal(m[s_], ov.metrics_from_counts(*rc).astype(np.float32))
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0, done = time.perf_counter(), 0
+        while time.perf_counter() - t0 < min(args.cpu_seconds, 5.0):
+            ov.overlap_batch(b.scores[:b.offsets[64]], b.truth[:b.offsets[64]], b.offsets[:65], 0.5)
+            done += 64
+        el = time.perf_counter() - t0
+        cpu = {"value": round(done / el, 1), "unit": "shapes/s", "cores": 1, "kind": "oracle",
+               "sample": f"{done} shapes (the first 64 of the batch, repeated) in {el:.1f} s, numpy float64",
+               "cpu_model": cpu_model()}
+    out = {"metric": "overlap-metric evaluations/sec (confusion counts + 7 metrics per shape)",
+           "value": round(S / (ms * 1e-3), 1), "unit": "shapes/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 5), "step_ms": stats, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32-scores/u8-labels/i64-counts", "data": "synthetic",
+           "config": {"workload": "overlap-1024", "shapes": S, "vertices": total, "threshold": 0.5},
+           "roofline": roof, "cpu_baseline": cpu,
+           "accuracy_vs_oracle": {"bit_exact": bool(exact), "shapes_checked": len(sel)}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_gradfeat(args, F, dev):
+    """Spatial-gradient features of the headline batch's vertices (160000 x 128 channels): one call per step."""
+    import torch
+    from oracle import gradfeat as gf
+    from paper_2604_10377_amd import synth
+    z, Ar, Ai = synth.workload_gradfeat()
+    V, D = z.shape[0], z.shape[1]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    # three input copies, rotated, so that the z reads are not served from the last-level cache
+    zs = [t(z)] + [t(z).clone() for _ in range(2)]
+    tAr, tAi = t(Ar), t(Ai)
+    g = torch.empty((V, D), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    k = [0]
+
+    def call():
+        F.fmap_gradient_features(zs[k[0] % 3], tAr, tAi, args.variant, g=g)
+        k[0] += 1
+
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            call()
+        torch.cuda.synchronize()
+        print(f"profiled {args.profile_steps} gradient-feature calls", flush=True)
+        return
+    ms, stats = timed_calls(call, args, stream)
+    flops = 8.0 * D * D * V + 3.0 * D * V
+    nbytes = V * D * 12 + 2 * D * D * 4
+    roof = roofline_entry(flops, nbytes, ms * 1e-3, FP32_PEAK_TFLOPS)
+    roof["kernel"] = f"gradfeat_mfma_kernel<{D}> (float32 matrix cores)"
+    roof["traffic"] = None
+    F.fmap_gradient_features(zs[0], tAr, tAi, args.variant, g=g)
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(0).choice(V, 2000, replace=False)
+    ref = gf.gradient_features(z[rows], Ar, Ai, args.variant)
+    got = g.cpu().numpy()[rows]
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0, done = time.perf_counter(), 0
+        while time.perf_counter() - t0 < min(args.cpu_seconds, 5.0):
+            gf.gradient_features(z[:20000], Ar, Ai, args.variant)
+            done += 20000
+        el = time.perf_counter() - t0
+        cpu = {"value": round(done / el, 1), "unit": "vertices/s", "cores": int(os.environ.get("OMP_NUM_THREADS", 0))
+               or len(os.sched_getaffinity(0)), "kind": "oracle",
+               "sample": f"{done} vertices (20000-vertex slices) in {el:.1f} s, numpy float64 (BLAS threads)",
+               "cpu_model": cpu_model()}
+    out = {"metric": f"spatial-gradient feature vertices/sec (variant {args.variant}, D={D})",
+           "value": round(V / (ms * 1e-3), 1), "unit": "vertices/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 5), "step_ms": stats, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"gradfeat-v{V}-d{D}", "vertices": V, "channels": D, "variant": args.variant},
+           "roofline": roof, "cpu_baseline": cpu,
+           "accuracy_vs_oracle": {"g": float(f"{err:.3e}"), "rows_checked": len(rows)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.oracle_one_pair:
@@ -574,6 +694,10 @@ def main():
         return
     if args.workload == "ragged":
         return bench_ragged(args, F, dev)
+    if args.workload == "overlap":
+        return bench_overlap(args, F, dev)
+    if args.workload == "gradfeat":
+        return bench_gradfeat(args, F, dev)
     if args.bwd is None:
         args.bwd = "recompute" if args.workload == "large" else "stored"
     b = make_workload(args.workload)

@@ -156,6 +156,44 @@ fmap_status fmap_solve_backward(const float *dC, const float *A, const float *B,
                                 size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* DiffusionNet spatial-gradient features (Sec. 3.2), the step upstream of the  */
+/* projection.  Per vertex the D channels hold complex gradients z = x + i y,   */
+/* interleaved: z [vertices][channels][2] float (x_j, y_j).  With A_re, A_im    */
+/* [channels][channels] float ((A z)_c = sum_j A[c][j] z_j):                    */
+/*     (A z)_re = A_re x - A_im y                                               */
+/*     (A z)_im = A_re y + A_im x   (FMAP_GRADFEAT_A)                           */
+/*              = A_re x + A_im y   (FMAP_GRADFEAT_B)                           */
+/*     g = x * (A z)_re + y * (A z)_im        g [vertices][channels] float      */
+/* Variant A is Re(conj(z) * (A z)), a learned rotation and isotropic scaling   */
+/* of each tangent vector; variant B fixes the rotation at +-45 degrees and     */
+/* allows anisotropic scaling.  Float32 arithmetic (float32 matrix cores for    */
+/* channels in {32, 64, 128, 256} and 16-byte aligned z; a plain kernel         */
+/* otherwise).  Forward only.                                                   */
+/* ------------------------------------------------------------------------ */
+#define FMAP_GRADFEAT_A 0
+#define FMAP_GRADFEAT_B 1
+fmap_status fmap_gradient_features(const float *z, const float *A_re, const float *A_im, int32_t variant,
+                                   int64_t vertices, int64_t channels, float *g, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Overlap-prediction metrics (Sec. 3.3), for a batch of shapes of uneven size. */
+/* Shape s owns vertices [offsets[s], offsets[s+1]) of the concatenated arrays  */
+/* scores [total] float and truth [total] uint8 (nonzero = truly overlapping);  */
+/* offsets [shapes + 1] int64 (device), nondecreasing from 0 to total (other    */
+/* contents give unspecified counts but no out-of-range access).  A vertex is   */
+/* predicted overlapping iff its score > threshold (float32; NaN is negative).  */
+/* Outputs (device, overwritten): counts [shapes][4] int64 = TP, FP, FN, TN,    */
+/* exact; metrics [shapes][7] float = accuracy, precision, recall               */
+/* (sensitivity), specificity, IoU, F1 and balanced accuracy (the mean of       */
+/* sensitivity and specificity), computed in double from the counts and        */
+/* rounded once.  A ratio with a zero denominator is 0; balanced accuracy       */
+/* averages the class recalls that are defined (one class only: its recall).   */
+/* scores and truth may be NULL when total == 0.                                */
+/* ------------------------------------------------------------------------ */
+fmap_status fmap_overlap_metrics(const float *scores, const uint8_t *truth, const int64_t *offsets, int64_t shapes,
+                                 int64_t total, float threshold, int64_t *counts, float *metrics, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Uneven batches (shape pairs with different n and k): a plan.                */
 /* The rows of all pairs are batch dimensions (Eq. (8)); pairs of equal k are   */
 /* grouped, the projections of every shape run as one persistent launch over   */

@@ -34,6 +34,8 @@ SIGNATURES = {
                           _vp, _vp, _sz, _vp]),
     "fmap_solve_backward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _f32, _i64, _i64, _i64, _i64, _vp, _vp,
                                    _vp, _vp, _vp, _vp, _sz, _vp]),
+    "fmap_gradient_features": (_i32, [_vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp]),
+    "fmap_overlap_metrics": (_i32, [_vp, _vp, _vp, _i64, _i64, _f32, _vp, _vp, _vp]),
     "fmap_plan_create": (_i32, [_vp, _i32, _i64, _i32, _f32, _i32, ctypes.c_char_p, _vp, _vp]),
     "fmap_plan_forward": (_i32, [_vp, _vp]),
     "fmap_plan_backward": (_i32, [_vp, _vp]),

@@ -200,6 +200,55 @@ def fmap_solve_backward(dC: torch.Tensor, A: torch.Tensor, B: torch.Tensor, C: t
     return dA, dB, dlam
 
 
+# ---------------------------------------------------------------------------- gradient features
+
+def fmap_gradient_features(z: torch.Tensor, A_re: torch.Tensor, A_im: torch.Tensor, variant: str = "A",
+                           g: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """DiffusionNet spatial-gradient features (Sec. 3.2): z [V, D, 2] float32 (x, y of each channel's tangent
+    vector), A_re, A_im [D, D]; variant "A" (complex product) or "B"; returns g [V, D]."""
+    dev = z.device
+    V, D, _ = z.shape
+    _need(z, "z", torch.float32, (V, D, 2), dev)
+    _need(A_re, "A_re", torch.float32, (D, D), dev)
+    _need(A_im, "A_im", torch.float32, (D, D), dev)
+    if variant not in ("A", "B"):
+        raise ValueError("variant must be 'A' or 'B'")
+    if g is None:
+        g = torch.empty((V, D), dtype=torch.float32, device=dev)
+    _need(g, "g", torch.float32, (V, D), dev)
+    _lib.check("fmap_gradient_features", _lib.lib().fmap_gradient_features(
+        _ptr(z), _ptr(A_re), _ptr(A_im), 0 if variant == "A" else 1, V, D, _ptr(g), _stream(dev)))
+    return g
+
+
+# ---------------------------------------------------------------------------- overlap metrics
+
+OVERLAP_METRICS = ("accuracy", "precision", "recall", "specificity", "iou", "f1", "balanced_accuracy")
+
+
+def fmap_overlap_metrics(scores: torch.Tensor, truth: torch.Tensor, offsets: torch.Tensor, threshold: float = 0.5,
+                         counts: Optional[torch.Tensor] = None, metrics: Optional[torch.Tensor] = None):
+    """Per-shape confusion counts [S, 4] int64 (TP, FP, FN, TN) and metrics [S, 7] float32 (OVERLAP_METRICS
+    order) of a thresholded score against the ground-truth overlap (Sec. 3.3).  scores [total] float32,
+    truth [total] uint8, offsets [S + 1] int64 on the same device."""
+    dev = offsets.device
+    S = offsets.shape[0] - 1
+    total = scores.shape[0]
+    _need(scores, "scores", torch.float32, (total,), dev)
+    _need(truth, "truth", torch.uint8, (total,), dev)
+    _need(offsets, "offsets", torch.int64, (S + 1,), dev)
+    if counts is None:
+        counts = torch.empty((S, 4), dtype=torch.int64, device=dev)
+    if metrics is None:
+        metrics = torch.empty((S, 7), dtype=torch.float32, device=dev)
+    _need(counts, "counts", torch.int64, (S, 4), dev)
+    _need(metrics, "metrics", torch.float32, (S, 7), dev)
+    _lib.check("fmap_overlap_metrics", _lib.lib().fmap_overlap_metrics(
+        _ptr(scores), _ptr(truth), _ptr(offsets), S, total, float(threshold), _ptr(counts), _ptr(metrics),
+        _stream(dev)))
+    return counts, metrics
+
+
 # ---------------------------------------------------------------------------- autograd
 
 class FmapSolveFn(torch.autograd.Function):

@@ -286,3 +286,52 @@ def small_problem(seed: int, k: int, d: int, *, kx: Optional[int] = None, lam: f
     ex = eigenvalues_linear(rng, kx)
     ey = eigenvalues_linear(rng, k)
     return A, B, ex, ey, lam, mask
+
+
+@dataclasses.dataclass
+class OverlapBatch:
+    """Scores and ground-truth overlap labels of S shapes, concatenated (shape s owns
+    [offsets[s], offsets[s+1]))."""
+    scores: np.ndarray   # [total] float32
+    truth: np.ndarray    # [total] uint8
+    offsets: np.ndarray  # [S + 1] int64
+    ratios: np.ndarray   # [S] overlap ratio r the labels were drawn with
+
+
+def workload_overlap(shapes: int = 1024, n_lo: int = 2000, n_hi: int = 20000, tag: int = 6) -> OverlapBatch:
+    """Overlap predictions of a partial-matching evaluation batch.
+
+    Per shape: n ~ U{n_lo..n_hi} vertices, overlap ratio r ~ U[0, 1], exactly round(r n) vertices
+    labelled overlapping (in a random order), and a noisy predictor's score
+    sigmoid(a (2 t - 1) + N(0, 1)) with a per-shape skill a ~ U[0, 3] (a = 0: a coin flip).
+    """
+    ns, ts, ss, rs = [], [], [], []
+    for s in range(shapes):
+        rng = rng_for(tag, s, 0, 0)
+        n = int(rng.integers(n_lo, n_hi + 1))
+        r = float(rng.uniform(0.0, 1.0))
+        t = np.zeros(n, np.uint8)
+        t[: int(round(r * n))] = 1
+        rng.shuffle(t)
+        a = rng.uniform(0.0, 3.0)
+        score = 1.0 / (1.0 + np.exp(-(a * (2.0 * t - 1.0) + rng.standard_normal(n))))
+        ns.append(n)
+        ts.append(t)
+        ss.append(score.astype(np.float32))
+        rs.append(r)
+    off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    return OverlapBatch(np.concatenate(ss) if ss else np.zeros(0, np.float32),
+                        np.concatenate(ts) if ts else np.zeros(0, np.uint8), off, np.asarray(rs))
+
+
+def workload_gradfeat(vertices: int = 160_000, channels: int = 128, tag: int = 7):
+    """Inputs of DiffusionNet's spatial-gradient features: per-vertex complex gradients z [V, D, 2] ~ N(0, 1)
+    (x, y interleaved per channel) and weights A_re, A_im [D, D] ~ U(-1/sqrt(D), 1/sqrt(D)) (the default
+    initialisation of a bias-free linear layer).  The default V is the headline batch's vertex count
+    (32 shapes of 5000 vertices), D = 128 the usual DiffusionNet width."""
+    rng = rng_for(tag, vertices, channels, 0)
+    z = rng.standard_normal((vertices, channels, 2)).astype(np.float32)
+    s = 1.0 / np.sqrt(channels)
+    A_re = rng.uniform(-s, s, (channels, channels)).astype(np.float32)
+    A_im = rng.uniform(-s, s, (channels, channels)).astype(np.float32)
+    return z, A_re, A_im

@@ -161,5 +161,16 @@ def test_plan_validation(L):
     assert L.fmap_plan_backward(NULL, None) == 1
     assert L.fmap_plan_tuning(NULL, NULL, NULL, NULL, NULL) == 1
     assert L.fmap_plan_groups(NULL, NULL) == 1
+    # gradient features: host validation
+    assert L.fmap_gradient_features(NULL, FAKE, FAKE, 0, 10, 8, FAKE, None) == 1
+    assert L.fmap_gradient_features(FAKE, FAKE, FAKE, 2, 10, 8, FAKE, None) == 3
+    assert L.fmap_gradient_features(FAKE, FAKE, FAKE, 0, 0, 8, FAKE, None) == 2
+    assert L.fmap_gradient_features(FAKE, FAKE, FAKE, 1, 10, 5000, FAKE, None) == 2
+    # overlap metrics: host validation
+    assert L.fmap_overlap_metrics(FAKE, FAKE, NULL, 2, 10, 0.5, FAKE, FAKE, None) == 1
+    assert L.fmap_overlap_metrics(NULL, FAKE, FAKE, 2, 10, 0.5, FAKE, FAKE, None) == 1
+    assert L.fmap_overlap_metrics(FAKE, FAKE, FAKE, 0, 10, 0.5, FAKE, FAKE, None) == 2
+    assert L.fmap_overlap_metrics(FAKE, FAKE, FAKE, 2, -1, 0.5, FAKE, FAKE, None) == 2
+    assert L.fmap_overlap_metrics(FAKE, FAKE, FAKE, 2, 10, float("nan"), FAKE, FAKE, None) == 3
     assert L.fmap_plan_group(NULL, 0, NULL, NULL, NULL) == 1
     assert L.fmap_plan_destroy(NULL) == 1
