@@ -15,6 +15,8 @@ Functions and the passages they follow (Sec. 3.1 of the paper):
   solve              Eqs. (4)-(7), row-decoupled normal equations, Cholesky
   solve_backward     reverse mode of `solve` (derived)
   pipeline_batch     the whole forward + backward pass over a batch of pairs
+  project_pinv       Eq. (1) with the projector given directly: A = P^T F for
+                     P = (Phi^+)^T, and its adjoint dF = P dA
   solve_resolutions  maps at several spectral resolutions from one projection:
                      resolution (k_x', k_y') is the solve restricted to the
                      first k_x' source and k_y' target eigenpairs
@@ -182,3 +184,15 @@ def solve_resolutions(A, B, evals_x, evals_y, lam: float, mask_kind: int, gamma:
         D = mask(np.asarray(evals_x)[:kx], np.asarray(evals_y)[:ky], mask_kind, gamma)
         out.append(solve(np.asarray(A)[:kx], np.asarray(B)[:ky], D, lam))
     return out
+
+
+def project_pinv(pinv_t, feat) -> np.ndarray:
+    """A = P^T F for one shape with the projector given directly, P = (Phi^+)^T [n,k], feat [n,d] -> [k,d]."""
+    P, F = _f64(pinv_t), _f64(feat)
+    assert P.shape[0] == F.shape[0]
+    return P.T @ F
+
+
+def project_pinv_backward(pinv_t, dA) -> np.ndarray:
+    """dF = P dA for one shape: P [n,k], dA [k,d] -> [n,d]."""
+    return _f64(pinv_t) @ _f64(dA)

@@ -408,3 +408,32 @@ def test_resolutions_brute_force(mask_kind):
         (C, _), = oracle.solve_resolutions(A, B, ex, ey, 0.05, mask_kind, 0.5, [kx], [ky])
         D = oracle.mask(ex[:kx], ey[:ky], mask_kind, 0.5)
         np.testing.assert_allclose(C, _brute_force(A[:kx], B[:ky], D, 0.05), rtol=0, atol=1e-11)
+
+
+# ----------------------------------------------------------------------------- projector given directly
+
+def test_project_pinv_moore_penrose():
+    """With the Moore-Penrose pseudo-inverse of a basis (numpy's pinv), A = Phi^+ F is Eq. (1) as the paper
+    writes it; with P = diag(M) Phi (the mass-weighted pseudo-inverse, transposed) it is the projection."""
+    rng = np.random.default_rng(51)
+    n, k, d = 300, 12, 7
+    Phi = rng.standard_normal((n, k))
+    F = rng.standard_normal((n, d))
+    pinv = np.linalg.pinv(Phi)
+    np.testing.assert_allclose(oracle.project_pinv(pinv.T, F), pinv @ F, rtol=0, atol=1e-12)
+    mass = rng.uniform(0.5, 1.5, n) / n
+    np.testing.assert_allclose(oracle.project_pinv(mass[:, None] * Phi, F), oracle.project(Phi, mass, F),
+                               rtol=0, atol=1e-12)
+    # F = Phi X: the pseudo-inverse recovers X (full column rank)
+    X = rng.standard_normal((k, d))
+    np.testing.assert_allclose(oracle.project_pinv(pinv.T, Phi @ X), X, rtol=0, atol=1e-10)
+
+
+def test_project_pinv_adjoint():
+    rng = np.random.default_rng(52)
+    P = rng.standard_normal((50, 6))
+    F = rng.standard_normal((50, 4))
+    G = rng.standard_normal((6, 4))
+    lhs = np.sum(oracle.project_pinv(P, F) * G)
+    rhs = np.sum(F * oracle.project_pinv_backward(P, G))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
