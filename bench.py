@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--warmup-seconds", type=float, default=1.5,
                     help="untimed replays for this much wall time before the counted warm-up")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "plain", "mixed", "large", "ragged", "overlap", "gradfeat"])
+                    choices=["headline", "plain", "mixed", "large", "ragged", "overlap", "gradfeat", "multires"])
     ap.add_argument("--variant", default="A", choices=["A", "B"], help="gradient-feature variant (gradfeat)")
     ap.add_argument("--bwd", default=None, choices=["stored", "recompute"],
                     help="backward mode (default: recompute for the large workload, stored otherwise)")
@@ -671,6 +671,91 @@ def bench_gradfeat(args, F, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_multires(args, F, dev):
+    """One projection at k = 120 and maps at resolutions 30, 50, 80 and 120 (32 pairs, n = 5000, d = 256,
+    Laplacian mask): the two library calls captured as one graph per input set, three sets rotated."""
+    import torch
+    import oracle
+    from paper_2604_10377_amd import synth
+    b = synth.make_batch("multires-k120-d256", 14, 32, 5000, 120, 256, mask=synth.MASK_LAPLACIAN, with_grad=False)
+    P, n, k, d = b.pairs, b.n, b.k, b.d
+    res = [(30, 30), (50, 50), (80, 80), (120, 120)]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    sets = [(t(b.phi), t(b.mass), t(b.feat)) for _ in range(3)]
+    ex, ey, lam = t(b.evals_x), t(b.evals_y), t(b.lam)
+    AB = [torch.empty((2 * P, k, d), dtype=torch.float32, device=dev) for _ in range(3)]
+    wsp = torch.empty(max(F.fmap_project_workspace_bytes(2 * P, n, k, d), 256), dtype=torch.uint8, device=dev)
+    outs = [None] * 3
+
+    def run(i):
+        phi, mass, feat = sets[i % 3]
+        F.fmap_project(phi, mass, feat, A=AB[i % 3], workspace=wsp)
+        outs[i % 3] = F.fmap_solve_resolutions(AB[i % 3][:P], AB[i % 3][P:], ex, ey, lam, b.mask, b.gamma, res)
+
+    for i in range(3):
+        run(i)
+    torch.cuda.synchronize()
+    graphs = []
+    for i in range(3):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            run(i)
+        graphs.append(g)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    replay = lambda i: graphs[i % 3].replay()
+    warm_up(replay, args)
+    ms, stats = timed_steps(replay, args.steps, stream)
+    # phases alone (eager): projection, then the four solves
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    K = max(3, min(args.steps, 50))
+    tp = ts = 0.0
+    for i in range(K):
+        phi, mass, feat = sets[i % 3]
+        e[0].record(stream)
+        F.fmap_project(phi, mass, feat, A=AB[0], workspace=wsp)
+        e[1].record(stream)
+        F.fmap_solve_resolutions(AB[0][:P], AB[0][P:], ex, ey, lam, b.mask, b.gamma, res)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        tp += e[0].elapsed_time(e[1]) / K
+        ts += e[1].elapsed_time(e[2]) / K
+    sb = SimpleNamespace_(pairs=P, n=n, k=k, d=d)
+    flops, nbytes = phase_costs(sb, False)["project"]
+    roof = roofline_entry(flops, nbytes, tp * 1e-3, matrix_peak("project", sb, False)[0])
+    roof["kernel"] = "fmap_project at k = 120 (float32 emulated on the bf16 matrix cores)"
+    roof["traffic"] = None
+    roof["phase_us"] = {"project": round(tp * 1e3, 2), "solve_resolutions": round(ts * 1e3, 2)}
+    # accuracy of pairs 0 and P-1 at every resolution, from one replay into NaN-filled outputs
+    for C, info in outs[0]:
+        C.fill_(float("nan"))
+    replay(0)
+    torch.cuda.synchronize()
+    worst = 0.0
+    rel = lambda x, r: float(np.linalg.norm(x - r) / np.linalg.norm(r))
+    for p in (0, P - 1):
+        A = oracle.project(b.phi[p], b.mass[p], b.feat[p])
+        B = oracle.project(b.phi[P + p], b.mass[P + p], b.feat[P + p])
+        refs = oracle.solve_resolutions(A, B, b.evals_x[p], b.evals_y[p], float(b.lam[p]), b.mask, b.gamma,
+                                        [r[0] for r in res], [r[1] for r in res])
+        for (C, _), (Cr, _) in zip(outs[0], refs):
+            worst = max(worst, rel(C[p].cpu().numpy(), Cr))
+    out = {"metric": "multi-resolution functional map sets/sec (projection at k=120 + maps at k=30,50,80,120)",
+           "value": round(P / (ms * 1e-3), 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 5), "step_ms": stats, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": b.name, "pairs": P, "n": n, "k_max": k, "d": d, "resolutions": res,
+                      "mask": "laplacian", "graph": True},
+           "roofline": roof, "cpu_baseline": None,
+           "accuracy_vs_oracle": {"C": float(f"{worst:.3e}"), "pairs": [0, P - 1], "resolutions": len(res)}}
+    print(json.dumps(out), flush=True)
+
+
+def SimpleNamespace_(**kw):
+    from types import SimpleNamespace
+    return SimpleNamespace(**kw)
+
+
 def main():
     args = parse()
     if args.oracle_one_pair:
@@ -698,6 +783,8 @@ def main():
         return bench_overlap(args, F, dev)
     if args.workload == "gradfeat":
         return bench_gradfeat(args, F, dev)
+    if args.workload == "multires":
+        return bench_multires(args, F, dev)
     if args.bwd is None:
         args.bwd = "recompute" if args.workload == "large" else "stored"
     b = make_workload(args.workload)

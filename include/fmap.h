@@ -104,6 +104,20 @@ fmap_status fmap_project_noalloc(const void *phi, const float *mass, const void 
 fmap_status fmap_project_backward(const void *phi, const float *mass, int32_t phi_dtype, const float *dA,
                                   int64_t batch, int64_t n, int64_t k, int64_t d, float *dF, void *stream);
 
+/* Eq. (1) with the projector given directly.  The paper writes A = Phi^+ F with */
+/* the pseudo-inverse; a caller holding Phi^+ ([k][n] per shape) passes its      */
+/* transpose P = (Phi^+)^T [batch][n][k] (Phi^+ read column-major) in `in_dtype`,  */
+/* feat [batch][n][d] in the same dtype:  A[b] = P[b]^T F[b] [batch][k][d] float. */
+/* The backward is dF[b] = P[b] dA[b].  Same kernels as fmap_project with unit   */
+/* vertex weights, which the call writes into the workspace (its first           */
+/* batch * n floats; the backward needs only those).                             */
+size_t fmap_project_pinv_workspace_bytes(int64_t batch, int64_t n, int64_t k, int64_t d, int32_t in_dtype);
+fmap_status fmap_project_pinv(const void *pinv_t, const void *feat, int32_t in_dtype, int64_t batch, int64_t n,
+                              int64_t k, int64_t d, float *A, void *workspace, size_t workspace_bytes, void *stream);
+fmap_status fmap_project_pinv_backward(const void *pinv_t, int32_t pinv_dtype, const float *dA, int64_t batch,
+                                       int64_t n, int64_t k, int64_t d, float *dF, void *workspace,
+                                       size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Regularised solve, Eqs. (2)-(9).  For every pair p and row i < k_y:          */
 /*     (A A^T + lambda[p] diag(D_i)) c_i = A b_i            (Eq. (5))          */
@@ -154,6 +168,27 @@ fmap_status fmap_solve_backward(const float *dC, const float *A, const float *B,
                                 float gamma, int64_t pairs, int64_t kx, int64_t ky, int64_t d, const float *factors,
                                 float *dA, float *dB, float *dlambda, int32_t *info, void *workspace,
                                 size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Maps at several spectral resolutions from one projection (multi-resolution   */
+/* pipelines project once onto the first k eigenfunctions).  Resolution r is    */
+/* the fmap_solve problem restricted to the first kxs[r] source and kys[r]      */
+/* target eigenpairs: the leading rows of A [pairs][kx][d] and B [pairs][ky][d] */
+/* and the leading eigenvalues (the mask and the resolvent normaliser are those */
+/* of the truncated spectra).  kxs, kys [host, nres entries]: 1 <= kxs[r] <= kx, */
+/* 1 <= kys[r] <= ky, 1 <= nres <= 64.  C [host, nres device pointers]:         */
+/* C[r] [pairs][kys[r]][kxs[r]] float.  info: NULL, or [host, nres] device      */
+/* pointers [pairs][kys[r]] int32, each may be NULL (conventions of fmap_solve). */
+/* Forward only, no factors.  workspace:                                        */
+/* fmap_solve_resolutions_workspace_bytes(...) bytes (0 for invalid arguments). */
+/* ------------------------------------------------------------------------ */
+size_t fmap_solve_resolutions_workspace_bytes(int64_t pairs, int64_t kx, int64_t ky, int64_t d, int32_t nres,
+                                              const int32_t *kxs, const int32_t *kys);
+fmap_status fmap_solve_resolutions(const float *A, const float *B, const float *evals_x, const float *evals_y,
+                                   const float *lambda, int32_t mask_kind, float gamma, int64_t pairs, int64_t kx,
+                                   int64_t ky, int64_t d, int32_t nres, const int32_t *kxs, const int32_t *kys,
+                                   float *const *C, int32_t *const *info, void *workspace, size_t workspace_bytes,
+                                   void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* DiffusionNet spatial-gradient features (Sec. 3.2), the step upstream of the  */

@@ -34,6 +34,12 @@ SIGNATURES = {
                           _vp, _vp, _sz, _vp]),
     "fmap_solve_backward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _f32, _i64, _i64, _i64, _i64, _vp, _vp,
                                    _vp, _vp, _vp, _vp, _sz, _vp]),
+    "fmap_project_pinv_workspace_bytes": (_sz, [_i64, _i64, _i64, _i64, _i32]),
+    "fmap_project_pinv": (_i32, [_vp, _vp, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _sz, _vp]),
+    "fmap_project_pinv_backward": (_i32, [_vp, _i32, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _sz, _vp]),
+    "fmap_solve_resolutions_workspace_bytes": (_sz, [_i64, _i64, _i64, _i64, _i32, _vp, _vp]),
+    "fmap_solve_resolutions": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _f32, _i64, _i64, _i64, _i64, _i32, _vp, _vp,
+                                      _vp, _vp, _vp, _sz, _vp]),
     "fmap_gradient_features": (_i32, [_vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp]),
     "fmap_overlap_metrics": (_i32, [_vp, _vp, _vp, _i64, _i64, _f32, _vp, _vp, _vp]),
     "fmap_plan_create": (_i32, [_vp, _i32, _i64, _i32, _f32, _i32, ctypes.c_char_p, _vp, _vp]),

@@ -8,17 +8,21 @@
 // sensitivity and specificity.
 //
 // The count is one streaming pass (5 bytes per vertex, HBM-bound).  Each wave
-// walks rows of 256 consecutive vertices, four per lane, keeping per-lane
-// counts for the shape it is in; when it leaves a shape it adds the counts of
-// the wave to that shape's slot with 64-bit integer atomics, so the totals do
-// not depend on the order in which workgroups finish.  Rows that cross a shape
-// boundary are counted vertex by vertex.  The slots are cleared by a kernel
+// owns a contiguous run of rows of 256 vertices (four per lane, one 16-byte
+// score load and one 4-byte label load per lane, the next row in flight while
+// the current one is counted) and keeps per-lane counts for the shape it is
+// in; when it leaves a shape it adds the wave's counts to that shape's slot
+// with 64-bit integer atomics, so the totals do not depend on the order in
+// which waves finish.  The shape of a wave's first vertex is found by a
+// 64-way parallel search over the offsets; later shapes by walking forward.
+// Rows that cross a shape boundary are counted vertex by vertex.  The slots are cleared by a kernel
 // (no memset node under graph capture), and a last kernel turns the counts
 // into the metrics in float64.
 #include "../../include/fmap.h"
 
 #include <algorithm>
 
+#include "fmap_device.h"
 #include "fmap_launch.h"
 
 namespace fmap {
@@ -28,14 +32,28 @@ namespace {
 constexpr int OV_THREADS = 256;
 constexpr int OV_ROW = 256;  // vertices per wave row (4 per lane)
 
-// Largest s in [0, S) with off[s] <= v (off nondecreasing; clamps for any contents).
-__device__ __forceinline__ int shape_of(const int64_t *__restrict__ off, int S, int64_t v)
+// Largest s in [0, S) with off[s] <= v (off nondecreasing; clamps for any contents), found by the whole
+// wave: each round the 64 lanes test 64 evenly spaced candidates (one load each, all in flight together)
+// and a ballot narrows the range 64-fold, so 1024 shapes take two rounds of loads.  v is wave-uniform.
+__device__ __forceinline__ int wave_shape_of(const int64_t *__restrict__ off, int S, int64_t v, int lane)
 {
-    int lo = 0, hi = S - 1;
+    int lo = 0, hi = S - 1;  // answer in [lo, hi]
     while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= v) lo = mid;
-        else hi = mid - 1;
+        const int span = hi - lo;
+        const int step = (span + 63) / 64;
+        const int cand = min(lo + 1 + lane * step, hi);  // candidates above lo
+        const bool le = off[cand] <= v;
+        const unsigned long long m = __ballot(le);
+        // candidates increase with the lane index and off is nondecreasing, so the lanes with le form a prefix
+        const int cnt = __popcll(m);
+        if (cnt == 0) {
+            hi = lo;  // even the first candidate is above v: the answer is lo
+        } else {
+            const int last = min(lo + 1 + (cnt - 1) * step, hi);  // largest candidate with off <= v
+            const int next = min(lo + 1 + cnt * step, hi + 1);    // smallest candidate above v (or past hi)
+            lo = last;
+            hi = next - 1;
+        }
     }
     return lo;
 }
@@ -54,78 +72,92 @@ __global__ __launch_bounds__(256) void overlap_clear_kernel(unsigned long long *
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) counts[e] = 0ull;
 }
 
-// counts [S][4] = TP, FP, FN, TN
+// counts [S][4] = TP, FP, FN, TN.  Wave w of the launch owns rows [w R, (w + 1) R) (R = rows_per_wave).
+// VEC: score is 16-byte and truth 4-byte aligned (whole rows read with one load each per lane).
+template <bool VEC>
 __global__ __launch_bounds__(OV_THREADS) void overlap_count_kernel(const float *__restrict__ score,
                                                                    const uint8_t *__restrict__ truth,
                                                                    const int64_t *__restrict__ off, int S,
-                                                                   int64_t total, float thr, int64_t rows_per_wg,
+                                                                   int64_t total, float thr, int64_t rows_per_wave,
                                                                    unsigned long long *__restrict__ counts)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * rows_per_wg;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * (OV_THREADS / 64) + (threadIdx.x >> 6);
     const int64_t nrows = (total + OV_ROW - 1) / OV_ROW;
-    const int64_t row1 = min(row0 + rows_per_wg, nrows);
-    int cur = -1;                 // shape of the per-lane counts (wave-uniform)
-    int64_t cur_lo = 0, cur_hi = -1;  // its vertex range [cur_lo, cur_hi)
-    unsigned c[4] = {0u, 0u, 0u, 0u};
-    auto flush = [&]() {
-        if (cur >= 0) {
+    const int64_t row0 = gw * rows_per_wave;
+    const int64_t row1 = min(row0 + rows_per_wave, nrows);
+    if (row0 >= row1) return;
+    auto load = [&](int64_t row, float (&sc)[4], uint32_t &gt) {
+        const int64_t v0 = row * OV_ROW + 4 * lane;
+        if (VEC && v0 + 3 < total) {
+            const f32x4 x = *reinterpret_cast<const f32x4 *>(score + v0);
+            sc[0] = x[0];
+            sc[1] = x[1];
+            sc[2] = x[2];
+            sc[3] = x[3];
+            gt = *reinterpret_cast<const uint32_t *>(truth + v0);
+        } else {
+            gt = 0u;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const unsigned t = wave_sum_u32(c[q]);
-                if (lane == 0 && t) atomicAdd(&counts[4 * (int64_t)cur + q], (unsigned long long)t);
-                c[q] = 0u;
+            for (int e = 0; e < 4; ++e) {
+                const int64_t v = min(v0 + e, total - 1);
+                sc[e] = score[v];
+                gt |= (uint32_t)truth[v] << (8 * e);
             }
         }
     };
-    for (int64_t row = row0 + wave; row < row1; row += OV_THREADS / 64) {
+    // shape of the first row's first vertex, its range, and the per-lane counts for it
+    int cur = wave_shape_of(off, S, row0 * OV_ROW, lane);
+    int64_t cur_lo = off[cur], cur_hi = off[cur + 1];
+    unsigned c[4] = {0u, 0u, 0u, 0u};
+    auto flush = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const unsigned t = wave_sum_u32(c[q]);
+            if (lane == 0 && t) atomicAdd(&counts[4 * (int64_t)cur + q], (unsigned long long)t);
+            c[q] = 0u;
+        }
+    };
+    float sc[4], sn[4];
+    uint32_t gt, gn;
+    load(row0, sc, gt);
+    for (int64_t row = row0; row < row1; ++row) {
+        if (row + 1 < row1) load(row + 1, sn, gn);  // next row in flight while this one is counted
         const int64_t base = row * OV_ROW;
         const int64_t v0 = base + 4 * lane;
         const int64_t last = min(base + OV_ROW, total) - 1;
-        // the four vertices of this lane: unconditional loads from clamped indices, masked afterwards
-        float sc[4];
-        uint8_t gt[4];
+        if (base >= cur_lo && last < cur_hi) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t v = min(v0 + e, total - 1);
-            sc[e] = score[v];
-            gt[e] = truth[v];
-        }
-        if (!(base >= cur_lo && last < cur_hi)) {
-            // the row leaves the current shape: find the shape of its first vertex
-            const int s0 = shape_of(off, S, base);
-            const int64_t lo = off[s0], hi = off[s0 + 1];
+            for (int e = 0; e < 4; ++e) {
+                if (v0 + e <= last) {
+                    const bool pos = sc[e] > thr, t = ((gt >> (8 * e)) & 0xffu) != 0u;
+                    c[pos ? (t ? 0 : 1) : (t ? 2 : 3)] += 1u;
+                }
+            }
+        } else {
+            // the row reaches past the current shape: count it vertex by vertex, walking the shapes forward
+            // from the current one (each lane to the shape of its vertex), then move the current shape on
             flush();
-            if (base >= lo && last < hi) {
-                cur = s0;
-                cur_lo = lo;
-                cur_hi = hi;
-            } else {
-                // the row crosses a shape boundary (or lies outside the offsets): vertex by vertex
-                cur = -1;
-                cur_hi = -1;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int64_t v = v0 + e;
-                    if (v <= last) {
-                        const int s = shape_of(off, S, v);
-                        if (v >= off[s] && v < off[s + 1]) {
-                            const bool pos = sc[e] > thr, t = gt[e] != 0;
-                            atomicAdd(&counts[4 * (int64_t)s + (pos ? (t ? 0 : 1) : (t ? 2 : 3))], 1ull);
-                        }
+            for (int e = 0; e < 4; ++e) {
+                const int64_t v = v0 + e;
+                if (v <= last) {
+                    int s = cur;
+                    while (s + 1 < S && off[s + 1] <= v) ++s;
+                    if (v >= off[s] && v < off[s + 1]) {
+                        const bool pos = sc[e] > thr, t = ((gt >> (8 * e)) & 0xffu) != 0u;
+                        atomicAdd(&counts[4 * (int64_t)s + (pos ? (t ? 0 : 1) : (t ? 2 : 3))], 1ull);
                     }
                 }
-                continue;
             }
+            const int64_t nb = base + OV_ROW;  // first vertex of the next row
+            while (cur + 1 < S && off[cur + 1] <= nb) ++cur;
+            cur_lo = off[cur];
+            cur_hi = off[cur + 1];
         }
-        // the whole row lies in shape cur
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            if (v0 + e <= last) {
-                const bool pos = sc[e] > thr, t = gt[e] != 0;
-                c[pos ? (t ? 0 : 1) : (t ? 2 : 3)] += 1u;
-            }
-        }
+        for (int e = 0; e < 4; ++e) sc[e] = sn[e];
+        gt = gn;
     }
     flush();
 }
@@ -162,13 +194,19 @@ hipError_t launch_overlap(const float *score, const uint8_t *truth, const int64_
     hipLaunchKernelGGL(overlap_clear_kernel, dim3((unsigned)std::min<int64_t>((nc + 255) / 256, 1024)), dim3(256), 0,
                        st, cnt, nc);
     if (total > 0) {
-        // about 8 workgroups per CU, at least 4 rows per wave
+        // each wave a contiguous run of rows: about 16 waves per CU, at least 8 rows each
         const int64_t nrows = (total + OV_ROW - 1) / OV_ROW;
-        const int64_t want = 8 * (int64_t)device_cus();
-        int64_t rows = std::max<int64_t>(16, (nrows + want - 1) / want);
-        const int64_t grid = (nrows + rows - 1) / rows;
-        hipLaunchKernelGGL(overlap_count_kernel, dim3((unsigned)grid), dim3(OV_THREADS), 0, st, score, truth, offsets,
-                           (int)S, total, thr, rows, cnt);
+        const int64_t waves = 16 * (int64_t)device_cus();
+        const int64_t rpw = std::max<int64_t>(8, (nrows + waves - 1) / waves);
+        const int64_t nw = (nrows + rpw - 1) / rpw;
+        const unsigned grid = (unsigned)((nw + OV_THREADS / 64 - 1) / (OV_THREADS / 64));
+        const bool vec = (((uintptr_t)score) & 15) == 0 && (((uintptr_t)truth) & 3) == 0;
+        if (vec)
+            hipLaunchKernelGGL(overlap_count_kernel<true>, dim3(grid), dim3(OV_THREADS), 0, st, score, truth, offsets,
+                               (int)S, total, thr, rpw, cnt);
+        else
+            hipLaunchKernelGGL(overlap_count_kernel<false>, dim3(grid), dim3(OV_THREADS), 0, st, score, truth,
+                               offsets, (int)S, total, thr, rpw, cnt);
     }
     hipLaunchKernelGGL(overlap_metrics_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, st, cnt, (int)S,
                        metrics);

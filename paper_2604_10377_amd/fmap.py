@@ -200,6 +200,71 @@ def fmap_solve_backward(dC: torch.Tensor, A: torch.Tensor, B: torch.Tensor, C: t
     return dA, dB, dlam
 
 
+# ---------------------------------------------------------------------------- projector input, resolutions
+
+def fmap_project_pinv(pinv_t: torch.Tensor, feat: torch.Tensor, A: Optional[torch.Tensor] = None,
+                      workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """A = P^T F per batch item with the projector given directly: pinv_t [b, n, k] = (Phi^+)^T."""
+    dev = pinv_t.device
+    b, n, k = pinv_t.shape
+    d = feat.shape[-1]
+    _need(pinv_t, "pinv_t", (torch.float32, torch.bfloat16), (b, n, k), dev)
+    _need(feat, "feat", pinv_t.dtype, (b, n, d), dev)
+    if A is None:
+        A = torch.empty((b, k, d), dtype=torch.float32, device=dev)
+    _need(A, "A", torch.float32, (b, k, d), dev)
+    dt = _dtype_code(pinv_t)
+    workspace = _workspace(int(_lib.lib().fmap_project_pinv_workspace_bytes(b, n, k, d, dt)), dev, workspace)
+    _lib.check("fmap_project_pinv", _lib.lib().fmap_project_pinv(
+        _ptr(pinv_t), _ptr(feat), dt, b, n, k, d, _ptr(A), _ptr(workspace), _wsbytes(workspace), _stream(dev)))
+    return A
+
+
+def fmap_project_pinv_backward(pinv_t: torch.Tensor, dA: torch.Tensor, dF: Optional[torch.Tensor] = None,
+                               workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dF = P dA per batch item (reverse mode of fmap_project_pinv)."""
+    dev = pinv_t.device
+    b, n, k = pinv_t.shape
+    d = dA.shape[-1]
+    _need(pinv_t, "pinv_t", (torch.float32, torch.bfloat16), (b, n, k), dev)
+    _need(dA, "dA", torch.float32, (b, k, d), dev)
+    if dF is None:
+        dF = torch.empty((b, n, d), dtype=torch.float32, device=dev)
+    _need(dF, "dF", torch.float32, (b, n, d), dev)
+    workspace = _workspace(b * n * 4, dev, workspace)
+    _lib.check("fmap_project_pinv_backward", _lib.lib().fmap_project_pinv_backward(
+        _ptr(pinv_t), _dtype_code(pinv_t), _ptr(dA), b, n, k, d, _ptr(dF), _ptr(workspace), _wsbytes(workspace),
+        _stream(dev)))
+    return dF
+
+
+def fmap_solve_resolutions(A: torch.Tensor, B: torch.Tensor, evals_x: torch.Tensor, evals_y: torch.Tensor,
+                           lam: torch.Tensor, mask_kind: int, gamma: float, resolutions, *,
+                           workspace: Optional[torch.Tensor] = None):
+    """Maps at several resolutions [(kx', ky'), ...] from one projection; returns [(C_r, info_r), ...]."""
+    dev = A.device
+    P, kx, d = A.shape
+    ky = B.shape[1]
+    _need(A, "A", torch.float32, (P, kx, d), dev)
+    _need(B, "B", torch.float32, (P, ky, d), dev)
+    _need(evals_x, "evals_x", torch.float32, (P, kx), dev)
+    _need(evals_y, "evals_y", torch.float32, (P, ky), dev)
+    _need(lam, "lam", torch.float32, (P,), dev)
+    nres = len(resolutions)
+    kxs = (ctypes.c_int32 * nres)(*[int(r[0]) for r in resolutions])
+    kys = (ctypes.c_int32 * nres)(*[int(r[1]) for r in resolutions])
+    Cs = [torch.empty((P, int(r[1]), int(r[0])), dtype=torch.float32, device=dev) for r in resolutions]
+    infos = [torch.empty((P, int(r[1])), dtype=torch.int32, device=dev) for r in resolutions]
+    cptr = (ctypes.c_void_p * nres)(*[c.data_ptr() for c in Cs])
+    iptr = (ctypes.c_void_p * nres)(*[x.data_ptr() for x in infos])
+    nbytes = int(_lib.lib().fmap_solve_resolutions_workspace_bytes(P, kx, ky, d, nres, kxs, kys))
+    workspace = _workspace(nbytes, dev, workspace)
+    _lib.check("fmap_solve_resolutions", _lib.lib().fmap_solve_resolutions(
+        _ptr(A), _ptr(B), _ptr(evals_x), _ptr(evals_y), _ptr(lam), int(mask_kind), float(gamma), P, kx, ky, d, nres,
+        kxs, kys, cptr, iptr, _ptr(workspace), _wsbytes(workspace), _stream(dev)))
+    return list(zip(Cs, infos))
+
+
 # ---------------------------------------------------------------------------- gradient features
 
 def fmap_gradient_features(z: torch.Tensor, A_re: torch.Tensor, A_im: torch.Tensor, variant: str = "A",

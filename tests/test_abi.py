@@ -161,6 +161,27 @@ def test_plan_validation(L):
     assert L.fmap_plan_backward(NULL, None) == 1
     assert L.fmap_plan_tuning(NULL, NULL, NULL, NULL, NULL) == 1
     assert L.fmap_plan_groups(NULL, NULL) == 1
+    # several resolutions and the projector input: host validation
+    kx1 = (ctypes.c_int32 * 1)(5)
+    kbad = (ctypes.c_int32 * 1)(9)
+    assert L.fmap_solve_resolutions_workspace_bytes(2, 8, 8, 16, 1, kx1, kx1) > 0
+    assert L.fmap_solve_resolutions_workspace_bytes(2, 8, 8, 16, 1, kbad, kx1) == 0
+    assert L.fmap_solve_resolutions_workspace_bytes(2, 8, 8, 16, 0, kx1, kx1) == 0
+    cp = (ctypes.c_void_p * 1)(0x1000)
+    res = lambda **kw: L.fmap_solve_resolutions(*[kw.get(n, v) for n, v in (
+        ("A", FAKE), ("B", FAKE), ("ex", FAKE), ("ey", FAKE), ("lam", FAKE), ("mask", 0), ("gamma", 0.5), ("P", 2),
+        ("kx", 8), ("ky", 8), ("d", 16), ("nres", 1), ("kxs", kx1), ("kys", kx1), ("C", cp), ("info", None),
+        ("ws", FAKE), ("wsb", 1 << 30), ("st", None))])
+    assert res(A=NULL) == 1
+    assert res(kxs=kbad) == 2
+    assert res(nres=0) == 2
+    assert res(mask=3) == 3
+    assert res(wsb=0) == 5
+    assert L.fmap_project_pinv(NULL, FAKE, 0, 1, 10, 4, 4, FAKE, FAKE, 1 << 20, None) == 1
+    assert L.fmap_project_pinv(FAKE, FAKE, 7, 1, 10, 4, 4, FAKE, FAKE, 1 << 20, None) == 4
+    assert L.fmap_project_pinv(FAKE, FAKE, 0, 1, 10, 4, 4, FAKE, FAKE, 0, None) == 5
+    assert L.fmap_project_pinv_backward(FAKE, 0, FAKE, 1, 10, 4, 4, FAKE, FAKE, 0, None) == 5
+    assert L.fmap_project_pinv_workspace_bytes(2, 100, 8, 16, 0) >= 2 * 100 * 4
     # gradient features: host validation
     assert L.fmap_gradient_features(NULL, FAKE, FAKE, 0, 10, 8, FAKE, None) == 1
     assert L.fmap_gradient_features(FAKE, FAKE, FAKE, 2, 10, 8, FAKE, None) == 3
