@@ -51,6 +51,7 @@ def parse():
                     help="sub-batches per step, staggered on their own streams (1: one sequence of calls)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-pair float32 leg")
     ap.add_argument("--oracle-one-pair", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cache-dir", default=None, help="keep generated workloads here (.npy) and reuse them")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many eager steps (for rocprofv3), no JSON")
     ap.add_argument("--copy-probe", action="store_true",
@@ -59,15 +60,36 @@ def parse():
 
 
 def make_workload(name: str, pairs=None):
+    """The named workload; with --cache-dir, generated once and reloaded from .npy files afterwards (the
+    profiler passes each start a fresh process)."""
     from paper_2604_10377_amd import synth
     kw = {} if pairs is None else {"pairs": pairs}
+    cache = os.environ.get("FMAP_BENCH_CACHE")
+    fields = ("phi", "mass", "feat", "evals", "lam", "dC", "phi_bf16", "feat_bf16")
+    if cache and pairs is None:
+        d = os.path.join(cache, name)
+        if os.path.exists(os.path.join(d, "meta.json")):
+            meta = json.load(open(os.path.join(d, "meta.json")))
+            arr = {f: (np.load(os.path.join(d, f + ".npy")) if meta["has"][f] else None) for f in fields}
+            return synth.PairBatch(meta["name"], meta["pairs"], meta["n"], meta["k"], meta["d"], meta["mask"],
+                                   meta["gamma"], **arr)
     if name == "headline":
-        return synth.workload_headline(**kw)
-    if name == "plain":
-        return synth.workload_plain()
-    if name == "mixed":
-        return synth.workload_mixed(**kw)
-    return synth.workload_large(**kw)
+        b = synth.workload_headline(**kw)
+    elif name == "plain":
+        b = synth.workload_plain()
+    elif name == "mixed":
+        b = synth.workload_mixed(**kw)
+    else:
+        b = synth.workload_large(**kw)
+    if cache and pairs is None:
+        d = os.path.join(cache, name)
+        os.makedirs(d, exist_ok=True)
+        for f in fields:
+            if getattr(b, f) is not None:
+                np.save(os.path.join(d, f + ".npy"), getattr(b, f))
+        json.dump({"name": b.name, "pairs": b.pairs, "n": b.n, "k": b.k, "d": b.d, "mask": b.mask, "gamma": b.gamma,
+                   "has": {f: getattr(b, f) is not None for f in fields}}, open(os.path.join(d, "meta.json"), "w"))
+    return b
 
 
 # solve options per workload: the mixed-precision workload runs one float64-residual
@@ -758,6 +780,8 @@ def SimpleNamespace_(**kw):
 
 def main():
     args = parse()
+    if args.cache_dir:
+        os.environ["FMAP_BENCH_CACHE"] = args.cache_dir
     if args.oracle_one_pair:
         return oracle_one_pair(args.workload)
     if args.gpus != 1:

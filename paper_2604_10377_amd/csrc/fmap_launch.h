@@ -107,10 +107,11 @@ void launch_trisolve_stored(const float *Lin, const float *rhs, const float *ex,
 void launch_trisolve_small(const float *Lin, const float *rhs, const float *ex, const float *ey, const float *lam,
                            int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, int *info,
                            const float *Cfwd, float *dlam_part, const float *addend, hipStream_t st);
-void launch_rowsolve_tiled(int mode, const float *K, const float *Lin, const float *rhs, const float *ex,
-                           const float *ey, const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx,
-                           int64_t ky, float *out, float *Lout, int *info, const float *Cfwd, float *dlam_part,
-                           float *tile_ws, hipStream_t st, const float *addend = nullptr);
+// Row systems for 64 < k_x <= kMaxK: mode 0 forward (factors to Lout if non-NULL), mode 2 reverse mode with
+// refactorisation (V rows, per-row dlambda terms).  tile_ws: tiled_workspace_bytes(P, k_x, k_y) bytes.
+void launch_rowsolve_tiled(int mode, const float *K, const float *rhs, const float *ex, const float *ey,
+                           const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out,
+                           float *Lout, int *info, const float *Cfwd, float *dlam_part, float *tile_ws, hipStream_t st);
 size_t tiled_workspace_bytes(int64_t P, int64_t kx, int64_t ky);
 void launch_adjoint_general(const float *V, const float *C, const float *A, const float *B, int64_t P, int64_t kx,
                             int64_t ky, int64_t d, float *Wbuf, const float *dlam_part, float *dlam, float *dA,

@@ -613,8 +613,8 @@ hipError_t launch_solve(const float *A, const float *B, const float *ex, const f
         launch_rowsolve<RS_FWD>(K, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info, nullptr,
                                 nullptr, st, rs_waves);
     else
-        launch_rowsolve_tiled(RS_FWD, K, nullptr, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info,
-                              nullptr, nullptr, tiles, st);
+        launch_rowsolve_tiled(RS_FWD, K, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info, nullptr,
+                              nullptr, tiles, st);
     // iterative refinement: rho = R64 - C K64 - lambda D o C in float64, C += S^{-1} rho with the float32 factors
     float *rho = (float *)(base + L.V);
     for (int it = 0; it < refine_steps; ++it) {
@@ -649,8 +649,8 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
             launch_rowsolve<RS_BWD_RECOMPUTE>(K, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, nullptr,
                                               info, C, dl, st, rs_waves);
         else
-            launch_rowsolve_tiled(RS_BWD_RECOMPUTE, K, nullptr, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V,
-                                  nullptr, info, C, dl, (float *)(base + L.tiles), st);
+            launch_rowsolve_tiled(RS_BWD_RECOMPUTE, K, dC, ex, ey, lam, mask_kind, gamma, P, kx, ky, V, nullptr, info, C,
+                                  dl, (float *)(base + L.tiles), st);
     }
     if (kx <= kSmallK && ky <= kSmallK) {
         // 32-column blocks: twice the workgroups of 64-column ones (W is recomputed per block, k^3 flops)

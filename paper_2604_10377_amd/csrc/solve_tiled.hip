@@ -1,22 +1,28 @@
 // Row systems of order 64 < k_x <= 319 (Eqs. (5)-(7) at large spectral
 // resolution), and the adjoint products for any k.
 //
-// One 512-thread workgroup per row system (pair p, row i), persistent over the
-// systems of the launch.  The lower triangle of S_i = K + lambda diag(D_i) is
-// cut into 32x32 tiles, stored in LDS when they fit (k_x <= 223: 28 tiles) or
-// in a per-workgroup slot of the workspace otherwise (L2 / last-level cache
-// resident).  The right-hand side is appended as one extra row (index k_x), so
-// the factorisation performs the forward substitution L y = r on the fly.
-// Right-looking blocked Cholesky, step p:
-//   1. wave 0 factorises the diagonal tile in registers (lane = row, column
-//      broadcast through LDS) and forms L_pp^{-1} (one column per lane);
+// Two blocked Cholesky kernels; the lower triangle of S_i = K + lambda diag(D_i)
+// is cut into 32x32 tiles, and the right-hand side is appended as one extra row
+// (index k_x), so the factorisation performs the forward substitution L y = r
+// on the fly.
+//
+// k_x < 128, rowsolve_tiles_kernel: one 512-thread workgroup per row system,
+// every tile in LDS (at most 40 KB, two systems per CU).  Right-looking, step p:
+//   1. wave 0 factorises the diagonal tile in registers (lane = row, entries of
+//      other rows by readlane) and forms L_pp^{-1} (one column per lane);
 //   2. panel tiles: L_Ip = S_Ip L_pp^{-T}, a 32x32x32 product on the float32
 //      matrix cores, one tile per wave;
 //   3. trailing tiles: S_IJ -= L_Ip L_Jp^T on the matrix cores, one tile per
 //      wave at a time.
 // The back substitution L^T c = y then runs block column by block column.
-// With stored factors (reverse mode) the tiles hold L and only the appended
-// row is carried through steps 2-3.
+//
+// 128 <= k_x <= 319, rowsolve_ll_kernel: left-looking, the active block column
+// in LDS and the finished tiles in the workspace, several systems per CU (see
+// its own description below).
+#include <stdlib.h>
+
+#include <algorithm>
+
 #include "fmap_device.h"
 #include "fmap_launch.h"
 
@@ -46,7 +52,7 @@ enum { RT_FWD = 0, RT_BWD_STORED = 1, RT_BWD_RECOMPUTE = 2 };
 
 // At TMAX = 4 the ten tiles take 40 KB of LDS: capped at 128 VGPRs (4 waves per SIMD, no spills),
 // two workgroups, i.e. two systems, share a CU instead of one.
-template <int TMAX, bool GT, int MODE>
+template <int TMAX, int MODE>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ? 4 : 1))) void rowsolve_tiles_kernel(
     const float *__restrict__ K, const float *__restrict__ Lin, const float *__restrict__ rhs,
     const float *__restrict__ ex, const float *__restrict__ ey, const float *__restrict__ lam, int mask_kind,
@@ -57,7 +63,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
     constexpr int NTL = TMAX * (TMAX + 1) / 2;
     constexpr bool STORED = MODE == RT_BWD_STORED;
     extern __shared__ __align__(16) float smem[];
-    float *aux = GT ? smem : smem + NTL * TSZ;
+    float *aux = smem + NTL * TSZ;
     float *s_minv = aux;
     float *s_dl = s_minv + TSZ;
     float *s_bc = s_dl + 32 * LDD;
@@ -67,7 +73,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
     float *s_part = s_dval + TRM * 32;
     float *s_red = s_part + TRM * 32;
     int *s_fail = reinterpret_cast<int *>(s_red + 8);
-    float *tiles = GT ? tile_ws + (size_t)blockIdx.x * NTL * TSZ : smem;
+    float *tiles = smem;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, half = lane >> 5;
@@ -382,6 +388,381 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
 }
 
 // ---------------------------------------------------------------------------
+// Left-looking variant for 64 < k_x <= 319: several row systems per CU.
+//
+// The right-looking kernel above keeps every tile of a system in LDS (118 KB at
+// k_x = 200), so a CU holds one system and idles while one wave factorises a
+// diagonal tile.  Here a workgroup of 4 waves keeps only the active block
+// column in LDS (7 tiles at k_x = 200, 37 KB in all) and writes each finished
+// tile L_Ip, and the inverse of each diagonal tile, to its own slot of the
+// workspace (32 x 32 row-major tiles in the lower-triangle order of the tile
+// grid; the diagonal positions hold the inverses).  Three or four systems then
+// share a CU and hide each other's serial diagonal steps.  Step p:
+//   1. block column p of S = K + lambda diag(D_i), with the right-hand side as
+//      the appended row, is loaded into LDS;
+//   2. left-looking update S_Ip -= sum_{q < p} L_Iq L_pq^T on the float32
+//      matrix cores, the L tiles read from the slot (L2) straight into the
+//      operand registers: lane (m, h) supplies row m, columns 16 h .. 16 h + 15,
+//      with the K order of the matrix-core steps permuted alike for both operands;
+//   3. wave 0 factorises the diagonal tile and forms its inverse (as above);
+//   4. the panel L_Ip = S_Ip L_pp^{-T} on the matrix cores, stored to the slot.
+// The appended row carries the forward substitution, so its tile row yields
+// y.  The back substitution runs block by block from the last: the finished
+// blocks' contribution L_Ip^T c_I as matrix-vector products over the slot's
+// tiles, then c_p = L_pp^{-T} v as one product with the stored inverse.
+// ---------------------------------------------------------------------------
+constexpr int LLW = 4;          // waves per workgroup
+constexpr int LTS = 32 * 32;    // floats per tile in the workspace slot
+
+constexpr int ll_lds_floats(int TRM) { return TRM * TSZ + TSZ + 3 * TRM * 32 + LLW * 32 + LLW + 4; }
+
+__device__ __forceinline__ f32x4 ldg4(const float *p) { return *reinterpret_cast<const f32x4 *>(p); }
+
+// STORE: the factor is written to Lout (forward mode with stored factors).
+template <int TMAX, int MODE, bool STORE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 ? 2 : 3))) void rowsolve_ll_kernel(
+    const float *__restrict__ K, const float *__restrict__ rhs, const float *__restrict__ ex,
+    const float *__restrict__ ey, const float *__restrict__ lam, int mask_kind, float gamma, int kx, int ky, int nsys,
+    float *out, float *__restrict__ Lout, int *__restrict__ info, const float *__restrict__ Cfwd,
+    float *__restrict__ dlam_part, float *__restrict__ Lws, int cus)
+{
+    constexpr int TRM = TMAX;
+    constexpr int NTL = TMAX * (TMAX + 1) / 2;
+    extern __shared__ __align__(16) float smem[];
+    float *bc = smem;                    // tile j: rows 32 (p + j) .. 32 (p + j) + 31 of block column p
+    float *s_minv = bc + TRM * TSZ;      // inverse of the diagonal tile, Minv[q][c] at q * TLD + c
+    float *s_dval = s_minv + TSZ;
+    float *s_shift = s_dval + TRM * 32;
+    float *s_vec = s_shift + TRM * 32;   // y, then c
+    float *s_part = s_vec + TRM * 32;    // [LLW][32]
+    float *s_red = s_part + LLW * 32;    // [LLW]
+    int *s_fail = reinterpret_cast<int *>(s_red + LLW);
+    float *Ls = Lws + (size_t)blockIdx.x * NTL * LTS;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l32 = lane & 31, half = lane >> 5;
+    // the wave that runs the serial diagonal steps: different for the workgroups that share a CU (ids one grid
+    // round of CUs apart), so that their diagonal chains do not all land on the same SIMD
+    const int dwave = (blockIdx.x / cus) % LLW;
+    const int T = (kx + 31) >> 5;   // column tiles
+    const int TR = (kx + 32) >> 5;  // tile rows (row kx is the right-hand side)
+    const int AR = kx >> 5, ar = kx & 31;
+
+    for (int sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
+        const int p = sys / ky, i = sys % ky;
+        // ---- lambda, mask row, normaliser -----------------------------------------------
+        const float lamv = lam[p];
+        int fail0 = (!(lamv >= 0.f) || !isfinite(lamv)) ? -1 : 0;
+        MaskParams mp;
+        mp.kind = mask_kind;
+        mp.gamma = gamma;
+        mp.inv_scale = 1.f;
+        if (mask_kind == 1) {
+            float mx = -INFINITY;
+            for (int q = tid; q < kx; q += 256) mx = fmaxf(mx, ex[(size_t)p * kx + q]);
+            for (int q = tid; q < ky; q += 256) mx = fmaxf(mx, ey[(size_t)p * ky + q]);
+            mx = wave_max(mx);
+            if (lane == 0) s_red[wave] = mx;
+            __syncthreads();
+            mx = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+            if ((!(mx > 0.f) || !isfinite(mx)) && fail0 == 0) fail0 = -2;
+            mp.inv_scale = 1.f / mx;
+        }
+        const float muy = ey[(size_t)p * ky + i];
+        for (int q = tid; q < TRM * 32; q += 256) {
+            const float dv = (q < kx && fail0 != -2) ? mask_entry(muy, ex[(size_t)p * kx + q], mp) : 0.f;
+            s_dval[q] = dv;
+            s_shift[q] = fail0 == 0 ? lamv * dv : 0.f;
+            s_vec[q] = 0.f;
+        }
+        if (tid == 0) *s_fail = fail0;
+        __syncthreads();
+
+        const float *Kp = K + (size_t)p * kx * kx;
+        const float *rp = rhs + ((size_t)p * ky + i) * kx;
+        for (int ps = 0; ps < T; ++ps) {
+            if (__builtin_amdgcn_readfirstlane(*s_fail) != 0) break;
+            // the lane index, made opaque per step: lane-dependent masks (the identity column of the inverse,
+            // the appended row's accumulator slot) are then formed where they are used, not hoisted out of
+            // every loop into registers
+            int lane = threadIdx.x & 63;
+            asm volatile("" : "+v"(lane));
+            const int l32 = lane & 31, half = lane >> 5;
+            const int nt = TR - ps;                 // tiles of the block column
+            const int kxl = min(32, kx - 32 * ps);  // columns of this block
+            // ---- 1. block column ps ---------------------------------------------------------------
+            if ((kx & 3) == 0) {
+                // 16-byte pieces (rows of K and the right-hand side start 16-byte aligned), a thread's pieces
+                // in groups of four in flight together
+                constexpr int G = 4;
+                for (int e0 = tid; e0 < nt * 256; e0 += G * 256) {
+                f32x4 v[G];
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    const int e = min(e0 + 256 * u, nt * 256 - 1);  // piece: tile e >> 8, row (e >> 3) & 31, 4 columns
+                    const int row = min(32 * (ps + (e >> 8)) + ((e >> 3) & 31), kx);
+                    const int col = min(32 * ps + 4 * (e & 7), kx - 4);
+                    v[u] = ldg4(row == kx ? rp + col : Kp + (size_t)row * kx + col);
+                }
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    const int e = e0 + 256 * u;
+                    if (e < nt * 256) {
+                        const int j = e >> 8, r = (e >> 3) & 31, c0 = 4 * (e & 7);
+                        const int row = 32 * (ps + j) + r;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int col = 32 * ps + c0 + t;
+                            float x = 0.f;
+                            if (row < kx && col < kx) x = v[u][t] + (row == col ? s_shift[row] : 0.f);
+                            else if (row == kx && col < kx) x = v[u][t];
+                            bc[j * TSZ + r * TLD + c0 + t] = x;
+                        }
+                    }
+                }
+                }
+            } else {
+                // groups of 8 unconditional loads from clamped addresses
+                for (int e0 = tid; e0 < nt * 1024; e0 += 8 * 256) {
+                    float v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = min(e0 + 256 * u, nt * 1024 - 1);
+                        const int j = e >> 10, r = (e >> 5) & 31, c = e & 31;
+                        const int row = min(32 * (ps + j) + r, kx), col = min(32 * ps + c, kx - 1);
+                        v[u] = row == kx ? rp[col] : Kp[(size_t)row * kx + col];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + 256 * u;
+                        if (e < nt * 1024) {
+                            const int j = e >> 10, r = (e >> 5) & 31, c = e & 31;
+                            const int row = 32 * (ps + j) + r, col = 32 * ps + c;
+                            float x = 0.f;
+                            if (row < kx && col < kx) x = v[u] + (row == col ? s_shift[row] : 0.f);
+                            else if (row == kx && col < kx) x = v[u];
+                            bc[j * TSZ + r * TLD + c] = x;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // ---- 2. S_Ip -= sum_{q < ps} L_Iq L_pq^T -------------------------------------------
+            if (ps > 0) {
+                for (int j = wave; j < nt; j += LLW) {
+                    float *X = bc + j * TSZ;
+                    f32x16 acc;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[r] = X[acc32_row(r, lane) * TLD + l32];
+                    const int I = ps + j;
+                    const int off = l32 * 32 + 16 * half;
+                    // whole tile pairs (16 floats of each operand per lane), the next pair in flight while one is
+                    // multiplied
+                    f32x4 a0[4], b0[4];
+                    {
+                        const float *ap = Ls + (size_t)tile_index(I, 0, TR) * LTS + off;
+                        const float *bp = Ls + (size_t)tile_index(ps, 0, TR) * LTS + off;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            a0[u] = ldg4(ap + 4 * u);
+                            b0[u] = ldg4(bp + 4 * u);
+                        }
+                    }
+                    for (int q = 0; q < ps; ++q) {
+                        const int qn = min(q + 1, ps - 1);
+                        const float *ap = Ls + (size_t)tile_index(I, qn, TR) * LTS + off;
+                        const float *bp = Ls + (size_t)tile_index(ps, qn, TR) * LTS + off;
+                        f32x4 a1[4], b1[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            a1[u] = ldg4(ap + 4 * u);
+                            b1[u] = ldg4(bp + 4 * u);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) acc = mfma32x32x2(-a0[u][e], b0[u][e], acc);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            a0[u] = a1[u];
+                            b0[u] = b1[u];
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) X[acc32_row(r, lane) * TLD + l32] = acc[r];
+                }
+                __syncthreads();
+            }
+            // ---- 3. diagonal tile and its inverse (one wave) ----------------------------------
+            if (wave == dwave) {
+                float *Dt = bc;
+                float sr[32];
+#pragma unroll
+                for (int q = 0; q < 32; ++q) sr[q] = (lane < 32) ? Dt[l32 * TLD + q] : 0.f;
+                int fail = 0;
+#pragma unroll
+                for (int c = 0; c < 32; ++c) {
+                    if (c < kxl && fail == 0) {
+                        const float piv = uniform_f(readlane(sr[c], c));
+                        if (!(piv > 0.f) || !isfinite(piv)) {
+                            fail = 32 * ps + c + 1;
+                        } else {
+                            const float l = sr[c] * __builtin_amdgcn_rsqf(piv);
+                            sr[c] = l;
+#pragma unroll
+                            for (int q = c + 1; q < 32; ++q) sr[q] -= l * readlane(l, q);
+                        }
+                    }
+                }
+                if (lane == 0 && fail != 0) *s_fail = fail;
+                if (fail == 0) {
+                    if (lane < 32) {  // the factored rows (and the appended row's y) back to LDS
+#pragma unroll
+                        for (int q = 0; q < 32; ++q) Dt[l32 * TLD + q] = sr[q];
+                    }
+                    float m[32];
+#pragma unroll
+                    for (int q = 0; q < 32; ++q) {
+                        float t = (q == lane) ? 1.f : 0.f;
+#pragma unroll
+                        for (int tt = 0; tt < q; ++tt) t -= readlane(sr[tt], q) * m[tt];
+                        m[q] = (q < kxl) ? t * __builtin_amdgcn_rcpf(readlane(sr[q], q)) : 0.f;
+                    }
+                    if (lane < 32) {
+                        float *Mi = Ls + (size_t)tile_index(ps, ps, TR) * LTS;
+#pragma unroll
+                        for (int q = 0; q < 32; ++q) {
+                            s_minv[q * TLD + l32] = m[q];  // Minv[q][lane]
+                            Mi[q * 32 + l32] = m[q];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (__builtin_amdgcn_readfirstlane(*s_fail) != 0) break;
+            if (AR == ps && tid < 32) s_vec[32 * ps + tid] = tid < kxl ? bc[ar * TLD + tid] : 0.f;  // y of this block
+            if (STORE) {
+                // L_pp into the packed factor, consecutive threads on consecutive rows of a column
+                float *Lo = Lout + ((size_t)p * ky + i) * (size_t)(kx * (kx + 1) / 2);
+                for (int e = tid; e < 1024; e += 256) {
+                    const int c = e >> 5, r = e & 31;
+                    if (r >= c && r < kxl) Lo[packed_col_t(32 * ps + c, kx) + (r - c)] = bc[r * TLD + c];
+                }
+            }
+            // ---- 4. panel L_Ip = S_Ip Minv^T (I > ps) -----------------------------------------------
+            for (int j = 1 + wave; j < nt; j += LLW) {
+                const int I = ps + j;
+                const float *X = bc + j * TSZ;
+                f32x16 nv = zero16();
+#pragma unroll
+                for (int t = 0; t < 16; ++t)
+                    nv = mfma32x32x2(X[l32 * TLD + 2 * t + half], s_minv[l32 * TLD + 2 * t + half], nv);
+                float *Lt = Ls + (size_t)tile_index(I, ps, TR) * LTS;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) Lt[acc32_row(r, lane) * 32 + l32] = nv[r];
+                if (STORE) {
+                    // the tile of L also back into LDS (over S_Ip, which this wave alone reads) for the packed output
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) bc[j * TSZ + acc32_row(r, lane) * TLD + l32] = nv[r];
+                }
+                if (I == AR) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        if (acc32_row(r, lane) == ar) s_vec[32 * ps + l32] = l32 < kxl ? nv[r] : 0.f;
+                }
+            }
+            __syncthreads();
+            if (STORE) {
+                // the block column's tiles of L below the diagonal into the packed factor, consecutive threads on
+                // consecutive rows of one column
+                float *Lo = Lout + ((size_t)p * ky + i) * (size_t)(kx * (kx + 1) / 2);
+                for (int e = tid; e < (nt - 1) * 1024; e += 256) {
+                    const int j = 1 + (e >> 10), c = (e >> 5) & 31, r = e & 31;
+                    const int R = 32 * (ps + j) + r, Cc = 32 * ps + c;
+                    if (R < kx && Cc < kx) Lo[packed_col_t(Cc, kx) + R - Cc] = bc[j * TSZ + r * TLD + c];
+                }
+                __syncthreads();
+            }
+        }
+        const int fail = __builtin_amdgcn_readfirstlane(*s_fail);
+
+        // ---- back substitution L^T c = y, column-oriented, from the last block ---------------------------
+        // The inverses of the diagonal tiles go to the block-column buffer (free now, T <= TRM tiles).  Step p:
+        // c_p = L_pp^{-T} y_p from LDS, then y_q -= L_pq^T c_p for every q < p, wave w taking q = w, w + 4, ...
+        // with the tiles' loads issued before c_p is formed.
+        if (fail == 0) {
+            for (int e0 = tid; e0 < T * 1024; e0 += 8 * 256) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = min(e0 + 256 * u, T * 1024 - 1);
+                    v[u] = Ls[(size_t)tile_index(e >> 10, e >> 10, TR) * LTS + (e & 1023)];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + 256 * u;
+                    if (e < T * 1024) bc[(e >> 10) * TSZ + ((e >> 5) & 31) * TLD + (e & 31)] = v[u];
+                }
+            }
+            __syncthreads();
+            for (int ps = T - 1; ps >= 0; --ps) {
+                const int kxl = min(32, kx - 32 * ps);
+                // this wave's first tile (ps, q = wave): rows h, h + 2, ... of column l32, in flight while c_ps is
+                // formed
+                float lv[16];
+                {
+                    const float *Lt = Ls + (size_t)tile_index(ps, min(wave, max(ps - 1, 0)), TR) * LTS;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) lv[u] = Lt[(2 * u + half) * 32 + l32];
+                }
+                if (wave == dwave && lane < 32) {
+                    // c_j = sum_q Minv[q][j] y_q
+                    const float *Mi = bc + ps * TSZ;
+                    float c = 0.f;
+#pragma unroll
+                    for (int q = 0; q < 32; ++q) c += Mi[q * TLD + l32] * s_vec[32 * ps + q];
+                    s_vec[32 * ps + l32] = l32 < kxl ? c : 0.f;
+                }
+                __syncthreads();
+                if (wave < ps) {
+                    float z = 0.f;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) z += lv[u] * s_vec[32 * ps + 2 * u + half];
+                    z += __shfl_xor(z, 32, 64);
+                    if (half == 0) s_vec[32 * wave + l32] -= z;
+                }
+                for (int q = wave + LLW; q < ps; q += LLW) {  // further earlier blocks (k_x > 128)
+                    const float *Lt = Ls + (size_t)tile_index(ps, q, TR) * LTS;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) lv[u] = Lt[(2 * u + half) * 32 + l32];
+                    float z = 0.f;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) z += lv[u] * s_vec[32 * ps + 2 * u + half];
+                    z += __shfl_xor(z, 32, 64);
+                    if (half == 0) s_vec[32 * q + l32] -= z;
+                }
+                __syncthreads();
+            }
+        }
+
+        // ---- outputs ----------------------------------------------------------------------
+        for (int q = tid; q < kx; q += 256) out[((size_t)p * ky + i) * kx + q] = fail == 0 ? s_vec[q] : NAN;
+        if (info && tid == 0) info[(size_t)p * ky + i] = fail;
+        if (MODE != RT_FWD && dlam_part) {
+            float term = 0.f;
+            for (int q = tid; q < kx; q += 256)
+                term += (fail == 0 ? s_vec[q] : NAN) * s_dval[q] * Cfwd[((size_t)p * ky + i) * kx + q];
+            term = wave_sum(term);
+            if (lane == 0) s_red[wave] = term;
+            __syncthreads();
+            if (tid == 0) dlam_part[(size_t)p * ky + i] = -((s_red[0] + s_red[1]) + (s_red[2] + s_red[3]));
+        }
+        __syncthreads();  // LDS and the slot are reused by the next system
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Batched products for the adjoint at any k (operands streamed from global
 // memory / L2).  Out[p] (M x N, row-major) = sum over two K-segments s of
 // sign_s * X_s Y_s, where X_s is M x K_s read as stored ("N") or as the
@@ -472,72 +853,102 @@ static int cu_count()
     return c;
 }
 
-// Workgroups of a launch whose tiles live in the workspace (one tile slot each).
-static int64_t tiled_global_slots(int64_t nsys)
+// Workgroups (and workspace slots) of the left-looking launch: up to four per CU.
+static int64_t ll_slots(int64_t nsys)
 {
-    const int64_t cap = 2 * (int64_t)cu_count();
+    const int64_t cap = 4 * (int64_t)cu_count();
     return nsys < cap ? nsys : cap;
 }
 
+// Tile rows of the left-looking instance (k_x >= 128; below, the right-looking kernel with every tile in LDS
+// runs two systems per CU and is as fast).
+static int ll_tmax(int64_t kx) { return kx < 224 ? 7 : 10; }
+
 size_t tiled_workspace_bytes(int64_t P, int64_t kx, int64_t ky)
 {
-    if (kx < 224) return 0;
-    const int64_t ntl = 10 * 11 / 2;
-    return (size_t)tiled_global_slots(P * ky) * ntl * TSZ * sizeof(float);
+    if (kx < 128) return 0;
+    const int64_t tm = ll_tmax(kx);
+    return (size_t)ll_slots(P * ky) * (tm * (tm + 1) / 2) * LTS * sizeof(float);
 }
 
-template <int TMAX, bool GT, int MODE>
+template <int TMAX, int MODE>
 static void launch_tiles(const float *K, const float *Lin, const float *rhs, const float *ex, const float *ey,
                          const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out,
                          float *Lout, int *info, const float *Cfwd, float *dlam_part, float *tws, hipStream_t st,
                          const float *addend)
 {
     constexpr int NTL = TMAX * (TMAX + 1) / 2;
-    const size_t lds = ((GT ? 0 : (size_t)NTL * TSZ) + aux_floats(TMAX)) * sizeof(float);
+    const size_t lds = ((size_t)NTL * TSZ + aux_floats(TMAX)) * sizeof(float);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)rowsolve_tiles_kernel<TMAX, GT, MODE>,
+        (void)hipFuncSetAttribute((const void *)rowsolve_tiles_kernel<TMAX, MODE>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr = true;
     }
-    const int64_t nsys = P * ky;
-    const int64_t grid = GT ? tiled_global_slots(nsys) : nsys;
-    hipLaunchKernelGGL((rowsolve_tiles_kernel<TMAX, GT, MODE>), dim3((unsigned)grid), dim3(512), lds, st, K, Lin, rhs,
+    const int64_t nsys = P * ky, grid = nsys;
+    hipLaunchKernelGGL((rowsolve_tiles_kernel<TMAX, MODE>), dim3((unsigned)grid), dim3(512), lds, st, K, Lin, rhs,
                        ex, ey, lam, mask_kind, gamma, (int)kx, (int)ky, (int)nsys, out, Lout, info, Cfwd, dlam_part,
                        tws, addend);
 }
 
-template <int MODE>
-static void launch_tiled_mode(const float *K, const float *Lin, const float *rhs, const float *ex, const float *ey,
-                              const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky,
-                              float *out, float *Lout, int *info, const float *Cfwd, float *dlam_part, float *tws,
-                              hipStream_t st, const float *addend)
+template <int TMAX, int MODE, bool STORE>
+static void launch_ll(const float *K, const float *rhs, const float *ex, const float *ey, const float *lam,
+                      int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, float *Lout, int *info,
+                      const float *Cfwd, float *dlam_part, float *ws, hipStream_t st)
 {
-    if (kx < 128)
-        launch_tiles<4, false, MODE>(K, Lin, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info, Cfwd,
-                                     dlam_part, tws, st, addend);
-    else if (kx < 224)
-        launch_tiles<7, false, MODE>(K, Lin, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info, Cfwd,
-                                     dlam_part, tws, st, addend);
-    else
-        launch_tiles<10, true, MODE>(K, Lin, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info, Cfwd,
-                                     dlam_part, tws, st, addend);
+    const size_t lds = (size_t)ll_lds_floats(TMAX) * sizeof(float);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)rowsolve_ll_kernel<TMAX, MODE, STORE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr = true;
+    }
+    // one round of resident workgroups (the runtime's occupancy for this instance, at most the four per CU the
+    // workspace holds slots for): a persistent grid larger than what fits would leave the surplus workgroups
+    // waiting for whole early workgroups, which loop over several systems each
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)rowsolve_ll_kernel<TMAX, MODE, STORE>, 256, lds) !=
+                hipSuccess ||
+            n < 1)
+            n = 1;
+        per_cu = n < 4 ? n : 4;
+    }
+    const int64_t nsys = P * ky;
+    const int64_t grid = std::min<int64_t>(nsys, (int64_t)per_cu * cu_count());
+    hipLaunchKernelGGL((rowsolve_ll_kernel<TMAX, MODE, STORE>), dim3((unsigned)grid), dim3(256), lds, st, K, rhs, ex, ey, lam,
+                       mask_kind, gamma, (int)kx, (int)ky, (int)nsys, out, Lout, info, Cfwd, dlam_part, ws, cu_count());
 }
 
-void launch_rowsolve_tiled(int mode, const float *K, const float *Lin, const float *rhs, const float *ex,
-                           const float *ey, const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx,
-                           int64_t ky, float *out, float *Lout, int *info, const float *Cfwd, float *dlam_part,
-                           float *tws, hipStream_t st, const float *addend)
+void launch_rowsolve_tiled(int mode, const float *K, const float *rhs, const float *ex, const float *ey,
+                           const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out,
+                           float *Lout, int *info, const float *Cfwd, float *dlam_part, float *tws, hipStream_t st)
 {
-    if (mode == RT_FWD)
-        launch_tiled_mode<RT_FWD>(K, Lin, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info, Cfwd,
-                                  dlam_part, tws, st, addend);
-    else if (mode == RT_BWD_STORED)
-        launch_tiled_mode<RT_BWD_STORED>(K, Lin, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info, Cfwd,
-                                         dlam_part, tws, st, addend);
-    else
-        launch_tiled_mode<RT_BWD_RECOMPUTE>(K, Lin, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info,
-                                            Cfwd, dlam_part, tws, st, addend);
+    if (kx < 128) {
+        // every tile in LDS, two systems per CU
+        if (mode == RT_FWD)
+            launch_tiles<4, RT_FWD>(K, nullptr, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info,
+                                           Cfwd, dlam_part, tws, st, nullptr);
+        else
+            launch_tiles<4, RT_BWD_RECOMPUTE>(K, nullptr, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out,
+                                                     Lout, info, Cfwd, dlam_part, tws, st, nullptr);
+        return;
+    }
+    const int tm = ll_tmax(kx);
+#define FMAP_LL(TM, MD, SF) launch_ll<TM, MD, SF>(K, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info, \
+                                                  Cfwd, dlam_part, tws, st)
+    if (mode == RT_FWD && Lout) {
+        if (tm == 7) FMAP_LL(7, RT_FWD, true);
+        else FMAP_LL(10, RT_FWD, true);
+    } else if (mode == RT_FWD) {
+        if (tm == 7) FMAP_LL(7, RT_FWD, false);
+        else FMAP_LL(10, RT_FWD, false);
+    } else {
+        if (tm == 7) FMAP_LL(7, RT_BWD_RECOMPUTE, false);
+        else FMAP_LL(10, RT_BWD_RECOMPUTE, false);
+    }
+#undef FMAP_LL
 }
 
 static void gemm(const GemmSeg &s0, const GemmSeg *s1, int64_t P, int M, int N, float *Out, long long strideO,
