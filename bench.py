@@ -52,6 +52,14 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-pair float32 leg")
     ap.add_argument("--oracle-one-pair", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cache-dir", default=None, help="keep generated workloads here (.npy) and reuse them")
+    ap.add_argument("--pmc-summary", nargs="+", default=None, metavar="DIR",
+                    help="only summarise rocprofv3 counter-collection output (mean per dispatch, per kernel)")
+    ap.add_argument("--stats-summary", nargs="+", default=None, metavar="DIR",
+                    help="only summarise rocprofv3 --stats kernel output")
+    ap.add_argument("--trace-summary", nargs="+", default=None, metavar="DIR",
+                    help="only summarise rocprofv3 --kernel-trace output per kernel and launch grid")
+    ap.add_argument("--traffic-summary", nargs=4, default=None, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="only summarise FETCH_SIZE / WRITE_SIZE runs, calibrated by the --copy-probe runs")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many eager steps (for rocprofv3), no JSON")
     ap.add_argument("--copy-probe", action="store_true",
@@ -199,7 +207,8 @@ def roofline_entry(flops, nbytes, seconds, mfma_peak_tflops):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "headline_hbm_traffic.txt")
-KERNEL_OF_PHASE = {"project": "proj_fwd_x3r_kernel<false>", "project_backward": "proj_bwd_mc_kernel<float, 3, 3, 2>"}
+KERNEL_OF_PHASE = {"project": "fmap::proj_fwd_x3r_kernel<false>",
+                   "project_backward": "fmap::proj_bwd_mc_kernel<float, 3, 3, 2>"}
 
 
 def measured_traffic(phase: str, workload: str, pairs_per_launch: int):
@@ -717,6 +726,12 @@ def bench_multires(args, F, dev):
     for i in range(3):
         run(i)
     torch.cuda.synchronize()
+    if args.profile_steps:
+        for i in range(args.profile_steps):
+            run(i)
+        torch.cuda.synchronize()
+        print(f"profiled {args.profile_steps} eager multi-resolution steps", flush=True)
+        return
     graphs = []
     for i in range(3):
         g = torch.cuda.CUDAGraph()
@@ -778,8 +793,142 @@ def SimpleNamespace_(**kw):
     return SimpleNamespace(**kw)
 
 
+def short_kernel_name(name: str) -> str:
+    """A kernel's name without its argument list (template arguments kept)."""
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0 and i > 0:
+            return name[:i].strip()
+    return name.strip()
+
+
+def csv_files(paths, suffix):
+    import glob
+    out = []
+    for pth in paths:
+        out += sorted(glob.glob(os.path.join(pth, "**", "*" + suffix), recursive=True)) if os.path.isdir(pth) \
+            else [pth]
+    return out
+
+
+def counter_means(paths):
+    """{(kernel, counter): mean value per dispatch} from rocprofv3 counter-collection CSVs."""
+    import csv
+    acc = {}
+    for f in csv_files(paths, "counter_collection.csv"):
+        for row in csv.DictReader(open(f)):
+            kn = short_kernel_name(row["Kernel_Name"])
+            per = acc.setdefault((kn, row["Counter_Name"]), {})
+            d = row["Dispatch_Id"]
+            per[d] = per.get(d, 0.0) + float(row["Counter_Value"])  # summed over the dimensions of one dispatch
+            if "Start_Timestamp" in row and "End_Timestamp" in row:
+                acc.setdefault((kn, "duration_us"), {})[d] = \
+                    (float(row["End_Timestamp"]) - float(row["Start_Timestamp"])) / 1e3
+    return {k: (sum(v.values()) / len(v), len(v)) for k, v in acc.items()}
+
+
+def pmc_summary(paths):
+    """Mean value per dispatch of every counter, per kernel; with the matrix-core and LDS counters, the
+    derived utilisation figures."""
+    m = counter_means(paths)
+    kernels = sorted({k for k, _ in m}, key=lambda k: -max(v[0] for (kk, _), v in m.items() if kk == k))
+    counters = sorted({c for _, c in m})
+    print("kernel".ljust(56) + "disp" + "".join(c.rjust(30) for c in counters))
+    for kn in kernels:
+        nd = max(m[(kn, c)][1] for c in counters if (kn, c) in m)
+        vals = [f"{m[(kn, c)][0]:.4g}" if (kn, c) in m else "-" for c in counters]
+        print(kn[:55].ljust(56) + str(nd).rjust(4) + "".join(v.rjust(30) for v in vals))
+    if any(c == "SQ_VALU_MFMA_BUSY_CYCLES" for _, c in m) and any(c == "GRBM_GUI_ACTIVE" for _, c in m):
+        print("\nderived (per dispatch): GRBM_GUI_ACTIVE is summed over the 8 XCDs (active_per_clk = GRBM_GUI_ACTIVE /\n"
+              " (dispatch duration x 2.4 GHz) reads about 8, a little less when the clock runs below 2.4 GHz), so\n"
+              " mfma_util = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 * 1024 SIMDs);\n"
+              " flops = 512 * SQ_INSTS_VALU_MFMA_MOPS_<type>, TFLOP/s over the dispatch duration;\n"
+              " lds_conflict = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE")
+        print("kernel".ljust(56) + "mfma_util".rjust(12) + "f32_TFLOPs".rjust(12) + "bf16_TFLOPs".rjust(12) +
+              "lds_conflict".rjust(14) + "active_per_clk".rjust(16))
+        for kn in kernels:
+            g = lambda c: m.get((kn, c), (None,))[0]
+            busy, act = g("SQ_VALU_MFMA_BUSY_CYCLES"), g("GRBM_GUI_ACTIVE")
+            util = f"{busy / (act / 8 * 1024):.4f}" if busy is not None and act else "-"
+            f32 = g("SQ_INSTS_VALU_MFMA_MOPS_F32")
+            bf = g("SQ_INSTS_VALU_MFMA_MOPS_BF16")
+            conf, idx = g("SQ_LDS_BANK_CONFLICT"), g("SQ_LDS_IDX_ACTIVE")
+            dur = g("duration_us")
+            clk = f"{act / (dur * 1e-6 * 2.4e9):.2f}" if act and dur else "-"
+            rate = lambda mops: "-" if mops is None or not dur else f"{512 * mops / (dur * 1e-6) / 1e12:.1f}"
+            print(kn[:55].ljust(56) + util.rjust(12) + rate(f32).rjust(12) + rate(bf).rjust(12) +
+                  (f"{conf / idx:.4f}" if conf is not None and idx else "-").rjust(14) + clk.rjust(16))
+
+
+def stats_summary(paths):
+    """rocprofv3 --stats kernel table: calls, mean/min/max duration (us), share of kernel time."""
+    import csv
+    rows = []
+    for f in csv_files(paths, "kernel_stats.csv"):
+        rows += list(csv.DictReader(open(f)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    print("kernel".ljust(64) + "calls".rjust(7) + "avg_us".rjust(10) + "min_us".rjust(10) + "max_us".rjust(10) +
+          "pct".rjust(7))
+    for r in rows:
+        print(short_kernel_name(r["Name"])[:63].ljust(64) + r["Calls"].rjust(7) +
+              f"{float(r['AverageNs']) / 1e3:.2f}".rjust(10) + f"{float(r['MinNs']) / 1e3:.2f}".rjust(10) +
+              f"{float(r['MaxNs']) / 1e3:.2f}".rjust(10) + f"{float(r['Percentage']):.2f}".rjust(7))
+
+
+def trace_summary(paths):
+    """rocprofv3 --kernel-trace table per kernel and launch grid (the same kernel at different batch sizes,
+    e.g. the batched step and the plain per-pair leg, gets one line each): calls, mean/min/max duration
+    (us), share of kernel time."""
+    import csv
+    acc = {}
+    for f in csv_files(paths, "kernel_trace.csv"):
+        for r in csv.DictReader(open(f)):
+            g = "x".join(r[c] for c in ("Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z"))
+            acc.setdefault((short_kernel_name(r["Kernel_Name"]), g), []).append(
+                (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in acc.values())
+    print("kernel".ljust(58) + "grid".rjust(14) + "calls".rjust(7) + "avg_us".rjust(10) + "min_us".rjust(10) +
+          "max_us".rjust(10) + "pct".rjust(7))
+    for (kn, g), v in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+        print(kn[:57].ljust(58) + g.rjust(14) + str(len(v)).rjust(7) + f"{sum(v) / len(v):.2f}".rjust(10) +
+              f"{min(v):.2f}".rjust(10) + f"{max(v):.2f}".rjust(10) + f"{100 * sum(v) / total:.2f}".rjust(7))
+
+
+def traffic_summary(fetch, write, copy_fetch, copy_write, copy_kib=262144.0):
+    """HBM bytes per dispatch from FETCH_SIZE and WRITE_SIZE runs, each scaled by what the same counter
+    reads for the plain copy of copy_kib KiB (the largest kernel of the copy runs)."""
+    f, w = counter_means([fetch]), counter_means([write])
+    cf, cw = counter_means([copy_fetch]), counter_means([copy_write])
+    cfk = max(v[0] for (k, c), v in cf.items() if c == "FETCH_SIZE")
+    cwk = max(v[0] for (k, c), v in cw.items() if c == "WRITE_SIZE")
+    ff, fw = copy_kib / cfk, copy_kib / cwk
+    print(f"calibration: copy of {copy_kib:.0f} KiB reads FETCH_SIZE {cfk:.1f} KiB -> fetch factor {ff:.3f}; "
+          f"WRITE_SIZE {cwk:.1f} KiB -> write factor {fw:.3f}")
+    print()
+    kernels = sorted({k for k, _ in f} | {k for k, _ in w},
+                     key=lambda k: -(f.get((k, "FETCH_SIZE"), (0,))[0] + w.get((k, "WRITE_SIZE"), (0,))[0]))
+    print("kernel".ljust(52) + "FETCH_KiB".rjust(13) + "WRITE_KiB".rjust(13) + "read_MB".rjust(10) + "write_MB".rjust(10))
+    for k in kernels:
+        fk = f.get((k, "FETCH_SIZE"), (0.0,))[0]
+        wk = w.get((k, "WRITE_SIZE"), (0.0,))[0]
+        print(k[:51].ljust(52) + f"{fk:.1f}".rjust(13) + f"{wk:.1f}".rjust(13) +
+              f"{fk * ff * 1024 / 1e6:.2f}".rjust(10) + f"{wk * fw * 1024 / 1e6:.2f}".rjust(10))
+
+
 def main():
     args = parse()
+    if args.pmc_summary:
+        return pmc_summary(args.pmc_summary)
+    if args.stats_summary:
+        return stats_summary(args.stats_summary)
+    if args.trace_summary:
+        return trace_summary(args.trace_summary)
+    if args.traffic_summary:
+        return traffic_summary(*args.traffic_summary)
     if args.cache_dir:
         os.environ["FMAP_BENCH_CACHE"] = args.cache_dir
     if args.oracle_one_pair:

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256, KW == 4 ? 2 : 1) void proj_fwd_bf16_kernel(con
 {
     using C = Bf16Fwd<KW>;
     extern __shared__ __align__(16) float smem[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int ks = wave % KW, dsl = wave / KW;
     const int m16 = lane & 15, g4 = lane >> 4;
 
@@ -164,27 +164,31 @@ __global__ __launch_bounds__(256, KW == 4 ? 2 : 1) void proj_fwd_bf16_kernel(con
 #pragma unroll
         for (int i = 0; i < 8; ++i) mv[i] = (8 * g4 + i < vrem) ? mv[i] : 0.f;
 
-        // feature operands: tile h*4+tt holds columns dsl*128 + h*64 + 4*m16 + tt of vertices 8*g4..+7
+        // feature operands: tile tt holds columns dsl*128 + 8*m16 + tt of vertices 8*g4..+7 (one 16-byte
+        // LDS read per vertex row)
         u32x4_t B[8];
+        {
+            const int cb = dsl * 128 + 8 * m16;
+            u32x4_t y[8];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int cb = dsl * 128 + h * 64 + 4 * m16;
-            uint2 y[8];
+            for (int i = 0; i < 8; ++i) y[i] = *reinterpret_cast<const u32x4_t *>(Fs + (8 * g4 + i) * C::DWG + cb);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) y[i] = *reinterpret_cast<const uint2 *>(Fs + (8 * g4 + i) * C::DWG + cb);
+            for (int tt = 0; tt < 8; ++tt)
 #pragma unroll
-            for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const uint32_t lo = (tt < 2) ? y[2 * jj].x : y[2 * jj].y;
-                    const uint32_t hi = (tt < 2) ? y[2 * jj + 1].x : y[2 * jj + 1].y;
-                    B[h * 4 + tt][jj] = __builtin_amdgcn_perm(hi, lo, (tt & 1) ? 0x07060302u : 0x05040100u);
-                }
+                for (int jj = 0; jj < 4; ++jj)
+                    B[tt][jj] = __builtin_amdgcn_perm(y[2 * jj + 1][tt >> 1], y[2 * jj][tt >> 1],
+                                                      (tt & 1) ? 0x07060302u : 0x05040100u);
         }
-        // basis operands: rows r4..r4+3 x vertices 8*g4..8*g4+7, scaled by mass, as hi + lo
+        // basis operands: rows r4..r4+3 x vertices 8*g4..8*g4+7, scaled by mass, as hi + lo.  Read as
+        // 32-bit pairs: an 8-byte LDS read here (like the earlier 8-byte feature reads) made the compiler
+        // wait for every outstanding global->LDS load, the prefetch two stages ahead included.
         uint2 x[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) x[i] = *reinterpret_cast<const uint2 *>(Ps + (8 * g4 + i) * k + r4);
+        for (int i = 0; i < 8; ++i) {
+            const uint32_t *pp = reinterpret_cast<const uint32_t *>(Ps + (8 * g4 + i) * k + r4);
+            x[i].x = pp[0];
+            x[i].y = pp[1];
+        }
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             u32x4_t Ah, Al;
@@ -204,8 +208,8 @@ __global__ __launch_bounds__(256, KW == 4 ? 2 : 1) void proj_fwd_bf16_kernel(con
     }
 
     // D layout: lane (m16, g4), register r -> matrix-core row 4*g4 + r, column m16.
-    // Row R of tile a is basis row ks*64 + 4R + a; column N of tile (h, tt) is
-    // feature column dbase + dsl*128 + h*64 + 4N + tt.
+    // Row R of tile a is basis row ks*64 + 4R + a; column N of tile tt is
+    // feature column dbase + dsl*128 + 8N + tt.
     float *O = out + (size_t)j * k * d;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -214,12 +218,10 @@ __global__ __launch_bounds__(256, KW == 4 ? 2 : 1) void proj_fwd_bf16_kernel(con
             const int row = ks * 64 + 4 * (4 * g4 + r) + a;
             if (row >= k) continue;
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int tt = 0; tt < 4; ++tt) {
-                    const int col = dbase + dsl * 128 + h * 64 + 4 * m16 + tt;
-                    if (col < d) O[(size_t)row * d + col] = acc[a][h * 4 + tt][r];
-                }
+            for (int tt = 0; tt < 8; ++tt) {
+                const int col = dbase + dsl * 128 + 8 * m16 + tt;
+                if (col < d) O[(size_t)row * d + col] = acc[a][tt][r];
+            }
         }
 }
 

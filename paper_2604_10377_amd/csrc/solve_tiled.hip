@@ -388,7 +388,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
 }
 
 // ---------------------------------------------------------------------------
-// Left-looking variant for 64 < k_x <= 319: several row systems per CU.
+// Left-looking variant for 128 <= k_x <= 319: several row systems per CU.
 //
 // The right-looking kernel above keeps every tile of a system in LDS (118 KB at
 // k_x = 200), so a CU holds one system and idles while one wave factorises a
