@@ -548,8 +548,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
             }
             __syncthreads();
             // ---- 2. S_Ip -= sum_{q < ps} L_Iq L_pq^T -------------------------------------------
+            // The diagonal-tile wave updates the diagonal tile alone and goes straight on to factorise it
+            // (step 3, its own LDS writes, no barrier), while the other waves update the tiles below it.
             if (ps > 0) {
-                for (int j = wave; j < nt; j += LLW) {
+                const int j0 = wave == dwave ? 0 : 1 + (wave - dwave + LLW - 1) % LLW;
+                const int jstep = wave == dwave ? nt : LLW - 1;
+                for (int j = j0; j < nt; j += jstep) {
                     float *X = bc + j * TSZ;
                     f32x16 acc;
 #pragma unroll
@@ -591,7 +595,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
 #pragma unroll
                     for (int r = 0; r < 16; ++r) X[acc32_row(r, lane) * TLD + l32] = acc[r];
                 }
-                __syncthreads();
             }
             // ---- 3. diagonal tile and its inverse (one wave) ----------------------------------
             if (wave == dwave) {
