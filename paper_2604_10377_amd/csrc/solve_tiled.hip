@@ -43,31 +43,155 @@ __device__ __forceinline__ float uniform_f(float v)
 // index of tile (I, J), I >= J, in column-major order of the lower triangle with TR tile rows
 __device__ __forceinline__ int tile_index(int I, int J, int TR) { return J * TR - (J * (J - 1)) / 2 + (I - J); }
 
+// LDS scratch of the diagonal-tile routine below (floats, 16-byte aligned): rows of L, block broadcast
+constexpr int DIAG_LR = 32 * LDD;
+constexpr int DIAG_BC = 256;
+
 // LDS besides the tiles (floats)
-constexpr int aux_floats(int TRM) { return TSZ /*minv*/ + 32 * LDD /*dl*/ + 32 /*bc*/ + 4 * TRM * 32 + 16; }
+constexpr int aux_floats(int TRM) { return TSZ /*minv*/ + DIAG_LR + DIAG_BC + 4 * TRM * 32 + 16; }
+
+// One wave (64 lanes): Cholesky factor of the 32 x 32 diagonal tile Dt (rows at stride TLD, lower part, the
+// first kxl columns; rows past kxl, e.g. the appended right-hand side row, are eliminated with them), and the
+// inverse of the factor, Minv[q][c] at q * TLD + c (rows and columns past kxl zero).  Returns 0, or 1 + the
+// first column whose pivot is not positive and finite (then Dt and Minv hold garbage).
+//   * factor: lane r holds row r; columns in blocks of 8, each block's columns in the lanes' registers with
+//     the entries L_qc taken by readlane, then the block's rank-8 update of the later columns from one LDS
+//     broadcast of the block (rows of the block column, 16-byte reads).  Every step is branch-free (a
+//     column past kxl or after a failure multiplies by 0): branches per column made the compiler copy the
+//     row registers at every join;
+//   * inverse: the two 16 x 16 diagonal blocks of L^{-1}, one per half of lanes 0..31 (lane = column), from
+//     the rows of L in LDS (16-byte reads, each half at its own address), then the lower-left block
+//     M21 = -M22 L21 M11 as two 16 x 16 x 16 products on the float32 matrix cores.
+// Lr ([32][LDD]) and Bc ([256]) are scratch, 16-byte aligned.
+__device__ __forceinline__ int diag_factor_inverse(float *Dt, float *Lr, float *Bc, float *Minv, int kxl, int lane)
+{
+    // the lane index made opaque, so its masks are formed where used, not hoisted into registers
+    asm volatile("" : "+v"(lane));
+    const int l32 = lane & 31;
+    float sr[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) sr[q] = (lane < 32) ? Dt[l32 * TLD + q] : 0.f;
+    int fail = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int c = 8 * b; c < 8 * b + 8; ++c) {
+            const float pv = uniform_f(readlane(sr[c], c));
+            const bool act = c < kxl && fail == 0;
+            const bool bad = !(pv > 0.f) || !isfinite(pv);
+            fail = (act && bad) ? c + 1 : fail;
+            const bool go = act && !bad;
+            const float l0 = sr[c] * __builtin_amdgcn_rsqf(go ? pv : 1.f);
+            sr[c] = go ? l0 : sr[c];
+            const float l = go ? l0 : 0.f;
+#pragma unroll
+            for (int q = c + 1; q < 8 * b + 8; ++q) sr[q] -= l * readlane(l, q);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // columns past kxl take no part (zeroed: nothing reads them afterwards)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sr[8 * b + u] = (8 * b + u < kxl) ? sr[8 * b + u] : 0.f;
+        if (b < 3) {
+            if (lane < 32) {
+                *reinterpret_cast<f32x4 *>(&Bc[8 * l32]) = f32x4{sr[8 * b], sr[8 * b + 1], sr[8 * b + 2], sr[8 * b + 3]};
+                *reinterpret_cast<f32x4 *>(&Bc[8 * l32 + 4]) =
+                    f32x4{sr[8 * b + 4], sr[8 * b + 5], sr[8 * b + 6], sr[8 * b + 7]};
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int q = 8 * b + 8; q < 32; ++q) {
+                const f32x4 x0 = *reinterpret_cast<const f32x4 *>(&Bc[8 * q]);
+                const f32x4 x1 = *reinterpret_cast<const f32x4 *>(&Bc[8 * q + 4]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sr[q] -= sr[8 * b + u] * x0[u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sr[q] -= sr[8 * b + 4 + u] * x1[u];
+                // finished here: left free, the compiler defers later columns' updates past the next block
+                // and keeps all their loaded rows live at once
+                asm volatile("" : "+v"(sr[q]));
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    fail = __builtin_amdgcn_readfirstlane(fail);
+    if (fail != 0) return fail;
+    if (lane < 32) {
+#pragma unroll
+        for (int q = 0; q < 32; ++q) Dt[l32 * TLD + q] = sr[q];
+#pragma unroll
+        for (int q = 0; q < 32; q += 4)
+            *reinterpret_cast<f32x4 *>(&Lr[l32 * LDD + q]) = f32x4{sr[q], sr[q + 1], sr[q + 2], sr[q + 3]};
+    }
+    __builtin_amdgcn_wave_barrier();
+    {
+        const int hb = (lane >> 4) & 1, jj = lane & 15;
+        const float *Lb = Lr + 16 * hb * LDD + 16 * hb;
+        float mb[16];
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq) {
+            float t = (qq == jj) ? 1.f : 0.f;
+            f32x4 row[4];
+#pragma unroll
+            for (int g = 0; g <= qq / 4; ++g) row[g] = *reinterpret_cast<const f32x4 *>(&Lb[qq * LDD + 4 * g]);
+#pragma unroll
+            for (int tt = 0; tt < qq; ++tt) t -= row[tt / 4][tt % 4] * mb[tt];
+            mb[qq] = (16 * hb + qq < kxl) ? t * __builtin_amdgcn_rcpf(row[qq / 4][qq % 4]) : 0.f;
+            asm volatile("" : "+v"(mb[qq]));
+        }
+        if (lane < 32) {
+#pragma unroll
+            for (int qq = 0; qq < 16; ++qq) {
+                Minv[(16 * hb + qq) * TLD + 16 * hb + jj] = mb[qq];
+                Minv[(16 * hb + qq) * TLD + 16 * (1 - hb) + jj] = 0.f;  // upper block; the lower one follows
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    {
+        // 16 x 16 x 4 float32 matrix-core steps: lane (i, k) = (lane % 16, lane / 16) supplies A[i][k] and
+        // B[k][i]; the result row 4 (lane / 16) + r, column lane % 16 is register r
+        const int i16 = lane & 15, k4 = lane >> 4;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < 4; ++st)  // T = L21 M11
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Lr[(16 + i16) * LDD + 4 * st + k4],
+                                                       Minv[(4 * st + k4) * TLD + i16], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Bc[(4 * k4 + r) * 16 + i16] = acc[r];
+        __builtin_amdgcn_wave_barrier();
+        f32x4 acc2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < 4; ++st)  // M21 = -M22 T
+            acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Minv[(16 + i16) * TLD + 16 + 4 * st + k4],
+                                                        Bc[(4 * st + k4) * 16 + i16], acc2, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Minv[(16 + 4 * k4 + r) * TLD + i16] = -acc2[r];
+    }
+    __builtin_amdgcn_wave_barrier();
+    return 0;
+}
 
 }  // namespace
 
-enum { RT_FWD = 0, RT_BWD_STORED = 1, RT_BWD_RECOMPUTE = 2 };
+enum { RT_FWD = 0, RT_BWD_RECOMPUTE = 2 };
 
 // At TMAX = 4 the ten tiles take 40 KB of LDS: capped at 128 VGPRs (4 waves per SIMD, no spills),
 // two workgroups, i.e. two systems, share a CU instead of one.
 template <int TMAX, int MODE>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ? 4 : 1))) void rowsolve_tiles_kernel(
-    const float *__restrict__ K, const float *__restrict__ Lin, const float *__restrict__ rhs,
-    const float *__restrict__ ex, const float *__restrict__ ey, const float *__restrict__ lam, int mask_kind,
-    float gamma, int kx, int ky, int nsys, float *out, float *__restrict__ Lout, int *__restrict__ info,
-    const float *__restrict__ Cfwd, float *__restrict__ dlam_part, float *__restrict__ tile_ws, const float *addend)
+    const float *__restrict__ K, const float *__restrict__ rhs, const float *__restrict__ ex,
+    const float *__restrict__ ey, const float *__restrict__ lam, int mask_kind, float gamma, int kx, int ky, int nsys,
+    float *out, float *__restrict__ Lout, int *__restrict__ info, const float *__restrict__ Cfwd,
+    float *__restrict__ dlam_part)
 {
     constexpr int TRM = TMAX;                        // k_x + 1 rows fit in TMAX tile rows
     constexpr int NTL = TMAX * (TMAX + 1) / 2;
-    constexpr bool STORED = MODE == RT_BWD_STORED;
     extern __shared__ __align__(16) float smem[];
     float *aux = smem + NTL * TSZ;
     float *s_minv = aux;
-    float *s_dl = s_minv + TSZ;
-    float *s_bc = s_dl + 32 * LDD;
-    float *s_vec = s_bc + 32;
+    float *s_lr = s_minv + TSZ;     // scratch of the diagonal-tile routine
+    float *s_bt = s_lr + DIAG_LR;
+    float *s_vec = s_bt + DIAG_BC;
     float *s_shift = s_vec + TRM * 32;
     float *s_dval = s_shift + TRM * 32;
     float *s_part = s_dval + TRM * 32;
@@ -113,9 +237,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
         if (tid == 0) *s_fail = fail0;
         __syncthreads();
 
-        // ---- tiles: S (lower, shifted diagonal) or L; appended row = right-hand side ----
-        const float *Kp = STORED ? nullptr : K + (size_t)p * kx * kx;
-        const float *Lp = STORED ? Lin + ((size_t)p * ky + i) * (size_t)(kx * (kx + 1) / 2) : nullptr;
+        // ---- tiles: S (lower, shifted diagonal); appended row = right-hand side ----
+        const float *Kp = K + (size_t)p * kx * kx;
         const float *rp = rhs + ((size_t)p * ky + i) * kx;
         // tiles in column-major order of the lower triangle, two entries per thread per tile, TG tiles
         // at a time: their loads are unconditional (addresses clamped into the arrays, the right-hand
@@ -140,14 +263,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
                     for (int h = 0; h < 2; ++h) {
                         const int rc = tid + 512 * h, r = rc >> 5, c = rc & 31;
                         const int row = min(32 * Iu[u] + r, kx), col = min(32 * Ju[u] + c, kx - 1);
-                        const float *src;
-                        if (STORED) {
-                            const int cc = min(col, min(row, kx - 1));
-                            src = row == kx ? rp + col : Lp + packed_col_t(cc, kx) + min(row, kx - 1) - cc;
-                        } else {
-                            src = row == kx ? rp + col : Kp + (size_t)row * kx + col;
-                        }
-                        v[u][h] = *src;
+                        v[u][h] = row == kx ? rp[col] : Kp[(size_t)row * kx + col];
                     }
                 }
 #pragma unroll
@@ -158,7 +274,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
                         const int rc = tid + 512 * h, r = rc >> 5, c = rc & 31;
                         const int row = 32 * Iu[u] + r, col = 32 * Ju[u] + c;
                         float x = 0.f;
-                        if (row < kx && col <= row) x = STORED ? v[u][h] : v[u][h] + (row == col ? s_shift[row] : 0.f);
+                        if (row < kx && col <= row) x = v[u][h] + (row == col ? s_shift[row] : 0.f);
                         else if (row == kx && col < kx) x = v[u][h];
                         tiles[(tau0 + u) * TSZ + r * TLD + c] = x;
                     }
@@ -173,48 +289,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
             float *Dt = tiles + tile_index(pstep, pstep, TR) * TSZ;
             // 1. diagonal tile and L_pp^{-1} (wave 0)
             if (wave == 0) {
-                float sr[32];
-#pragma unroll
-                for (int q = 0; q < 32; ++q) sr[q] = (lane < 32) ? Dt[l32 * TLD + q] : 0.f;
-                int fail = 0;
-                // column c of L: the pivot and the entries L_qc come from the lanes that hold rows c and q
-                // (readlane, no LDS round trip); lane j updates its row; entries above the diagonal are
-                // updated too but never read again
-#pragma unroll
-                for (int c = 0; c < 32; ++c) {
-                    if (c < kxl && fail == 0) {
-                        const float piv = uniform_f(readlane(sr[c], c));
-                        if (!(piv > 0.f) || !isfinite(piv)) {
-                            fail = 32 * pstep + c + 1;
-                        } else if (!STORED) {
-                            const float l = sr[c] * __builtin_amdgcn_rsqf(piv);
-                            sr[c] = l;
-#pragma unroll
-                            for (int q = c + 1; q < 32; ++q) sr[q] -= l * readlane(l, q);
-                        }
-                    }
-                }
-                if (fail == 0 && lane < 32 && !STORED) {
-#pragma unroll
-                    for (int q = 0; q < 32; ++q) Dt[l32 * TLD + q] = sr[q];
-                }
-                if (lane == 0 && fail != 0) *s_fail = fail;
-                if (fail == 0) {
-                    // column `lane` of L_pp^{-1}: m_q = (delta_{q,lane} - sum_{t<q} L_qt m_t) / L_qq, the
-                    // entries of L read from the lanes holding them
-                    float m[32];
-#pragma unroll
-                    for (int q = 0; q < 32; ++q) {
-                        float t = (q == lane) ? 1.f : 0.f;
-#pragma unroll
-                        for (int tt = 0; tt < q; ++tt) t -= readlane(sr[tt], q) * m[tt];
-                        m[q] = (q < kxl) ? t * __builtin_amdgcn_rcpf(readlane(sr[q], q)) : 0.f;
-                    }
-                    if (lane < 32) {
-#pragma unroll
-                        for (int q = 0; q < 32; ++q) s_minv[q * TLD + l32] = m[q];  // Minv[q][lane]
-                    }
-                }
+                const int f = diag_factor_inverse(Dt, s_lr, s_bt, s_minv, kxl, lane);
+                if (f != 0 && lane == 0) *s_fail = 32 * pstep + f;
             }
             __syncthreads();
             if (__builtin_amdgcn_readfirstlane(*s_fail) != 0) break;
@@ -222,29 +298,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
             // 2. panel tiles (I, pstep), I > pstep: L_Ip = S_Ip Minv^T
             {
                 const int first = pstep + 1;
-                const int npan = STORED ? (AR > pstep ? 1 : 0) : TR - first;
+                const int npan = TR - first;
                 for (int q = wave; q < npan; q += TW) {
-                    const int I = STORED ? AR : first + q;
+                    const int I = first + q;
                     float *X = tiles + tile_index(I, pstep, TR) * TSZ;
                     f32x16 nv = zero16();
 #pragma unroll
                     for (int t = 0; t < 16; ++t)
                         nv = mfma32x32x2(X[l32 * TLD + 2 * t + half], s_minv[l32 * TLD + 2 * t + half], nv);
                     __builtin_amdgcn_wave_barrier();
-                    // with stored factors the tile's other rows are final L rows: only the appended row moves
 #pragma unroll
-                    for (int r = 0; r < 16; ++r)
-                        if (!STORED || acc32_row(r, lane) == ar) X[acc32_row(r, lane) * TLD + l32] = nv[r];
-                }
-                if (STORED && AR == pstep && wave == 0) {
-                    // appended row inside the diagonal tile: y_c = sum_t Minv[c][t] s_t
-                    float y = 0.f;
-                    if (lane < kxl) {
-#pragma unroll
-                        for (int t = 0; t < 32; ++t) y += s_minv[l32 * TLD + t] * Dt[ar * TLD + t];
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    if (lane < 32) Dt[ar * TLD + l32] = (lane < kxl) ? y : 0.f;
+                    for (int r = 0; r < 16; ++r) X[acc32_row(r, lane) * TLD + l32] = nv[r];
                 }
             }
             __syncthreads();
@@ -252,21 +316,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
             // 3. trailing tiles (I, J), pstep < J <= I < TR: S_IJ -= L_Ip L_Jp^T
             {
                 const int nt = TR - pstep - 1;  // block columns pstep+1 .. TR-1 of the trailing part
-                const int ntrail = STORED ? (AR > pstep ? AR - pstep : 0) : nt * (nt + 1) / 2;
+                const int ntrail = nt * (nt + 1) / 2;
                 for (int q = wave; q < ntrail; q += TW) {
-                    int I, J;
-                    if (STORED) {
-                        I = AR;
-                        J = pstep + 1 + q;
-                    } else {
-                        int jj = 0, t2 = q;
-                        while (t2 >= nt - jj) {
-                            t2 -= nt - jj;
-                            ++jj;
-                        }
-                        J = pstep + 1 + jj;
-                        I = J + t2;
+                    int jj = 0, t2 = q;
+                    while (t2 >= nt - jj) {
+                        t2 -= nt - jj;
+                        ++jj;
                     }
+                    const int J = pstep + 1 + jj;
+                    const int I = J + t2;
                     if (J >= T) continue;  // the appended row's block beyond the last column
                     float *X = tiles + tile_index(I, J, TR) * TSZ;
                     const float *LI = tiles + tile_index(I, pstep, TR) * TSZ;
@@ -278,8 +336,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
                     for (int t = 0; t < 16; ++t)
                         acc = mfma32x32x2(-LI[l32 * TLD + 2 * t + half], LJ[l32 * TLD + 2 * t + half], acc);
 #pragma unroll
-                    for (int r = 0; r < 16; ++r)
-                        if (!STORED || acc32_row(r, lane) == ar) X[acc32_row(r, lane) * TLD + l32] = acc[r];
+                    for (int r = 0; r < 16; ++r) X[acc32_row(r, lane) * TLD + l32] = acc[r];
                 }
             }
             // y of this block column (the appended row) is final
@@ -365,8 +422,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
         // ---- outputs ----------------------------------------------------------------------
         for (int q = tid; q < kx; q += 512) {
             const size_t o = ((size_t)p * ky + i) * kx + q;
-            const float v = fail == 0 ? s_vec[q] : NAN;
-            out[o] = addend ? addend[o] + v : v;  // addend: refinement correction c += delta (in place)
+            out[o] = fail == 0 ? s_vec[q] : NAN;
         }
         if (info && tid == 0) info[(size_t)p * ky + i] = fail;
         if (MODE != RT_FWD && dlam_part) {
@@ -414,7 +470,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
 constexpr int LLW = 4;          // waves per workgroup
 constexpr int LTS = 32 * 32;    // floats per tile in the workspace slot
 
-constexpr int ll_lds_floats(int TRM) { return TRM * TSZ + TSZ + 3 * TRM * 32 + LLW * 32 + LLW + 4; }
+constexpr int ll_lds_floats(int TRM) { return TRM * TSZ + TSZ + DIAG_LR + DIAG_BC + 3 * TRM * 32 + LLW * 32 + LLW + 4; }
 
 __device__ __forceinline__ f32x4 ldg4(const float *p) { return *reinterpret_cast<const f32x4 *>(p); }
 
@@ -431,7 +487,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
     extern __shared__ __align__(16) float smem[];
     float *bc = smem;                    // tile j: rows 32 (p + j) .. 32 (p + j) + 31 of block column p
     float *s_minv = bc + TRM * TSZ;      // inverse of the diagonal tile, Minv[q][c] at q * TLD + c
-    float *s_dval = s_minv + TSZ;
+    float *s_lr = s_minv + TSZ;          // scratch of the diagonal-tile routine
+    float *s_bt = s_lr + DIAG_LR;
+    float *s_dval = s_bt + DIAG_BC;
     float *s_shift = s_dval + TRM * 32;
     float *s_vec = s_shift + TRM * 32;   // y, then c
     float *s_part = s_vec + TRM * 32;    // [LLW][32]
@@ -482,11 +540,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
         const float *rp = rhs + ((size_t)p * ky + i) * kx;
         for (int ps = 0; ps < T; ++ps) {
             if (__builtin_amdgcn_readfirstlane(*s_fail) != 0) break;
-            // the lane index, made opaque per step: lane-dependent masks (the identity column of the inverse,
-            // the appended row's accumulator slot) are then formed where they are used, not hoisted out of
-            // every loop into registers
-            int lane = threadIdx.x & 63;
-            asm volatile("" : "+v"(lane));
+            // the thread index, made opaque per step: lane-dependent masks and addresses (the identity column
+            // of the inverse, the appended row's accumulator slot, the tile offsets of the loads) are then
+            // formed where they are used, not hoisted out of every loop into registers (they had taken some 40
+            // to 80 registers for the whole kernel)
+            int tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            const int lane = tid & 63;
             const int l32 = lane & 31, half = lane >> 5;
             const int nt = TR - ps;                 // tiles of the block column
             const int kxl = min(32, kx - 32 * ps);  // columns of this block
@@ -598,47 +658,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
             }
             // ---- 3. diagonal tile and its inverse (one wave) ----------------------------------
             if (wave == dwave) {
-                float *Dt = bc;
-                float sr[32];
+                const int f = diag_factor_inverse(bc, s_lr, s_bt, s_minv, kxl, lane);
+                if (f != 0) {
+                    if (lane == 0) *s_fail = 32 * ps + f;
+                } else {
+                    // the inverse also into the slot's diagonal position (rows 2 u + half)
+                    float *Mi = Ls + (size_t)tile_index(ps, ps, TR) * LTS;
 #pragma unroll
-                for (int q = 0; q < 32; ++q) sr[q] = (lane < 32) ? Dt[l32 * TLD + q] : 0.f;
-                int fail = 0;
-#pragma unroll
-                for (int c = 0; c < 32; ++c) {
-                    if (c < kxl && fail == 0) {
-                        const float piv = uniform_f(readlane(sr[c], c));
-                        if (!(piv > 0.f) || !isfinite(piv)) {
-                            fail = 32 * ps + c + 1;
-                        } else {
-                            const float l = sr[c] * __builtin_amdgcn_rsqf(piv);
-                            sr[c] = l;
-#pragma unroll
-                            for (int q = c + 1; q < 32; ++q) sr[q] -= l * readlane(l, q);
-                        }
-                    }
-                }
-                if (lane == 0 && fail != 0) *s_fail = fail;
-                if (fail == 0) {
-                    if (lane < 32) {  // the factored rows (and the appended row's y) back to LDS
-#pragma unroll
-                        for (int q = 0; q < 32; ++q) Dt[l32 * TLD + q] = sr[q];
-                    }
-                    float m[32];
-#pragma unroll
-                    for (int q = 0; q < 32; ++q) {
-                        float t = (q == lane) ? 1.f : 0.f;
-#pragma unroll
-                        for (int tt = 0; tt < q; ++tt) t -= readlane(sr[tt], q) * m[tt];
-                        m[q] = (q < kxl) ? t * __builtin_amdgcn_rcpf(readlane(sr[q], q)) : 0.f;
-                    }
-                    if (lane < 32) {
-                        float *Mi = Ls + (size_t)tile_index(ps, ps, TR) * LTS;
-#pragma unroll
-                        for (int q = 0; q < 32; ++q) {
-                            s_minv[q * TLD + l32] = m[q];  // Minv[q][lane]
-                            Mi[q * 32 + l32] = m[q];
-                        }
-                    }
+                    for (int u = 0; u < 16; ++u) Mi[(2 * u + half) * 32 + l32] = s_minv[(2 * u + half) * TLD + l32];
                 }
             }
             __syncthreads();
@@ -875,10 +902,9 @@ size_t tiled_workspace_bytes(int64_t P, int64_t kx, int64_t ky)
 }
 
 template <int TMAX, int MODE>
-static void launch_tiles(const float *K, const float *Lin, const float *rhs, const float *ex, const float *ey,
-                         const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out,
-                         float *Lout, int *info, const float *Cfwd, float *dlam_part, float *tws, hipStream_t st,
-                         const float *addend)
+static void launch_tiles(const float *K, const float *rhs, const float *ex, const float *ey, const float *lam,
+                         int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, float *Lout,
+                         int *info, const float *Cfwd, float *dlam_part, hipStream_t st)
 {
     constexpr int NTL = TMAX * (TMAX + 1) / 2;
     const size_t lds = ((size_t)NTL * TSZ + aux_floats(TMAX)) * sizeof(float);
@@ -889,9 +915,8 @@ static void launch_tiles(const float *K, const float *Lin, const float *rhs, con
         attr = true;
     }
     const int64_t nsys = P * ky, grid = nsys;
-    hipLaunchKernelGGL((rowsolve_tiles_kernel<TMAX, MODE>), dim3((unsigned)grid), dim3(512), lds, st, K, Lin, rhs,
-                       ex, ey, lam, mask_kind, gamma, (int)kx, (int)ky, (int)nsys, out, Lout, info, Cfwd, dlam_part,
-                       tws, addend);
+    hipLaunchKernelGGL((rowsolve_tiles_kernel<TMAX, MODE>), dim3((unsigned)grid), dim3(512), lds, st, K, rhs, ex,
+                       ey, lam, mask_kind, gamma, (int)kx, (int)ky, (int)nsys, out, Lout, info, Cfwd, dlam_part);
 }
 
 template <int TMAX, int MODE, bool STORE>
@@ -931,11 +956,11 @@ void launch_rowsolve_tiled(int mode, const float *K, const float *rhs, const flo
     if (kx < 128) {
         // every tile in LDS, two systems per CU
         if (mode == RT_FWD)
-            launch_tiles<4, RT_FWD>(K, nullptr, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info,
-                                           Cfwd, dlam_part, tws, st, nullptr);
+            launch_tiles<4, RT_FWD>(K, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info, Cfwd,
+                                    dlam_part, st);
         else
-            launch_tiles<4, RT_BWD_RECOMPUTE>(K, nullptr, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out,
-                                                     Lout, info, Cfwd, dlam_part, tws, st, nullptr);
+            launch_tiles<4, RT_BWD_RECOMPUTE>(K, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info,
+                                              Cfwd, dlam_part, st);
         return;
     }
     const int tm = ll_tmax(kx);
