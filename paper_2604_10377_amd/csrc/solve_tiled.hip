@@ -1,25 +1,12 @@
 // Row systems of order 64 < k_x <= 319 (Eqs. (5)-(7) at large spectral
 // resolution), and the adjoint products for any k.
 //
-// Two blocked Cholesky kernels; the lower triangle of S_i = K + lambda diag(D_i)
+// A blocked left-looking Cholesky: the lower triangle of S_i = K + lambda diag(D_i)
 // is cut into 32x32 tiles, and the right-hand side is appended as one extra row
 // (index k_x), so the factorisation performs the forward substitution L y = r
-// on the fly.
-//
-// k_x < 128, rowsolve_tiles_kernel: one 512-thread workgroup per row system,
-// every tile in LDS (at most 40 KB, two systems per CU).  Right-looking, step p:
-//   1. wave 0 factorises the diagonal tile in registers (lane = row, entries of
-//      other rows by readlane) and forms L_pp^{-1} (one column per lane);
-//   2. panel tiles: L_Ip = S_Ip L_pp^{-T}, a 32x32x32 product on the float32
-//      matrix cores, one tile per wave;
-//   3. trailing tiles: S_IJ -= L_Ip L_Jp^T on the matrix cores, one tile per
-//      wave at a time.
-// The back substitution L^T c = y then runs block column by block column.
-//
-// 128 <= k_x <= 319, rowsolve_ll_kernel: left-looking, the active block column
-// in LDS and the finished tiles in the workspace, several systems per CU (see
-// its own description below).
-#include <stdlib.h>
+// on the fly.  A 4-wave workgroup keeps the active block column in LDS and the
+// finished tiles in its slot of the workspace, and several systems share a CU
+// (rowsolve_ll_kernel, described below).
 
 #include <algorithm>
 
@@ -32,8 +19,7 @@ namespace {
 
 constexpr int TLD = 33;                 // row stride of a stored tile (odd: conflict-free columns)
 constexpr int TSZ = 32 * TLD;           // floats per tile
-constexpr int LDD = 36;                 // row stride of the factorised diagonal tile (aligned rows)
-constexpr int TW = 8;                   // waves per workgroup
+constexpr int LDD = 36;                 // row stride of the aligned copy of the diagonal tile
 
 __device__ __forceinline__ int packed_col_t(int c, int m) { return c * m - (c * (c - 1)) / 2; }
 __device__ __forceinline__ float uniform_f(float v)
@@ -43,12 +29,8 @@ __device__ __forceinline__ float uniform_f(float v)
 // index of tile (I, J), I >= J, in column-major order of the lower triangle with TR tile rows
 __device__ __forceinline__ int tile_index(int I, int J, int TR) { return J * TR - (J * (J - 1)) / 2 + (I - J); }
 
-// LDS scratch of the diagonal-tile routine below (floats, 16-byte aligned): rows of L, block broadcast
+// LDS scratch of the diagonal-tile routine below (floats, 16-byte aligned)
 constexpr int DIAG_LR = 32 * LDD;
-constexpr int DIAG_BC = 256;
-
-// LDS besides the tiles (floats)
-constexpr int aux_floats(int TRM) { return TSZ /*minv*/ + DIAG_LR + DIAG_BC + 4 * TRM * 32 + 16; }
 
 // One wave (64 lanes): Cholesky factor of the 32 x 32 diagonal tile Dt (rows at stride TLD, lower part, the
 // first kxl columns; rows past kxl, e.g. the appended right-hand side row, are eliminated with them), and the
@@ -62,8 +44,9 @@ constexpr int aux_floats(int TRM) { return TSZ /*minv*/ + DIAG_LR + DIAG_BC + 4 
 //   * inverse: the two 16 x 16 diagonal blocks of L^{-1}, one per half of lanes 0..31 (lane = column), from
 //     the rows of L in LDS (16-byte reads, each half at its own address), then the lower-left block
 //     M21 = -M22 L21 M11 as two 16 x 16 x 16 products on the float32 matrix cores.
-// Lr ([32][LDD]) and Bc ([256]) are scratch, 16-byte aligned.
-__device__ __forceinline__ int diag_factor_inverse(float *Dt, float *Lr, float *Bc, float *Minv, int kxl, int lane)
+// Lr ([32][LDD], 16-byte aligned) is scratch: the block broadcasts of the factor, then the rows of L, then
+// (over rows 0..7, free by then) the product L21 M11.
+__device__ __forceinline__ int diag_factor_inverse(float *Dt, float *Lr, float *Minv, int kxl, int lane)
 {
     // the lane index made opaque, so its masks are formed where used, not hoisted into registers
     asm volatile("" : "+v"(lane));
@@ -93,15 +76,15 @@ __device__ __forceinline__ int diag_factor_inverse(float *Dt, float *Lr, float *
         for (int u = 0; u < 8; ++u) sr[8 * b + u] = (8 * b + u < kxl) ? sr[8 * b + u] : 0.f;
         if (b < 3) {
             if (lane < 32) {
-                *reinterpret_cast<f32x4 *>(&Bc[8 * l32]) = f32x4{sr[8 * b], sr[8 * b + 1], sr[8 * b + 2], sr[8 * b + 3]};
-                *reinterpret_cast<f32x4 *>(&Bc[8 * l32 + 4]) =
+                *reinterpret_cast<f32x4 *>(&Lr[8 * l32]) = f32x4{sr[8 * b], sr[8 * b + 1], sr[8 * b + 2], sr[8 * b + 3]};
+                *reinterpret_cast<f32x4 *>(&Lr[8 * l32 + 4]) =
                     f32x4{sr[8 * b + 4], sr[8 * b + 5], sr[8 * b + 6], sr[8 * b + 7]};
             }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int q = 8 * b + 8; q < 32; ++q) {
-                const f32x4 x0 = *reinterpret_cast<const f32x4 *>(&Bc[8 * q]);
-                const f32x4 x1 = *reinterpret_cast<const f32x4 *>(&Bc[8 * q + 4]);
+                const f32x4 x0 = *reinterpret_cast<const f32x4 *>(&Lr[8 * q]);
+                const f32x4 x1 = *reinterpret_cast<const f32x4 *>(&Lr[8 * q + 4]);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) sr[q] -= sr[8 * b + u] * x0[u];
 #pragma unroll
@@ -157,13 +140,13 @@ __device__ __forceinline__ int diag_factor_inverse(float *Dt, float *Lr, float *
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Lr[(16 + i16) * LDD + 4 * st + k4],
                                                        Minv[(4 * st + k4) * TLD + i16], acc, 0, 0, 0);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Bc[(4 * k4 + r) * 16 + i16] = acc[r];
+        for (int r = 0; r < 4; ++r) Lr[(4 * k4 + r) * 16 + i16] = acc[r];
         __builtin_amdgcn_wave_barrier();
         f32x4 acc2 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int st = 0; st < 4; ++st)  // M21 = -M22 T
             acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(Minv[(16 + i16) * TLD + 16 + 4 * st + k4],
-                                                        Bc[(4 * st + k4) * 16 + i16], acc2, 0, 0, 0);
+                                                        Lr[(4 * st + k4) * 16 + i16], acc2, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) Minv[(16 + 4 * k4 + r) * TLD + i16] = -acc2[r];
     }
@@ -175,292 +158,27 @@ __device__ __forceinline__ int diag_factor_inverse(float *Dt, float *Lr, float *
 
 enum { RT_FWD = 0, RT_BWD_RECOMPUTE = 2 };
 
-// At TMAX = 4 the ten tiles take 40 KB of LDS: capped at 128 VGPRs (4 waves per SIMD, no spills),
-// two workgroups, i.e. two systems, share a CU instead of one.
-template <int TMAX, int MODE>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ? 4 : 1))) void rowsolve_tiles_kernel(
-    const float *__restrict__ K, const float *__restrict__ rhs, const float *__restrict__ ex,
-    const float *__restrict__ ey, const float *__restrict__ lam, int mask_kind, float gamma, int kx, int ky, int nsys,
-    float *out, float *__restrict__ Lout, int *__restrict__ info, const float *__restrict__ Cfwd,
-    float *__restrict__ dlam_part)
-{
-    constexpr int TRM = TMAX;                        // k_x + 1 rows fit in TMAX tile rows
-    constexpr int NTL = TMAX * (TMAX + 1) / 2;
-    extern __shared__ __align__(16) float smem[];
-    float *aux = smem + NTL * TSZ;
-    float *s_minv = aux;
-    float *s_lr = s_minv + TSZ;     // scratch of the diagonal-tile routine
-    float *s_bt = s_lr + DIAG_LR;
-    float *s_vec = s_bt + DIAG_BC;
-    float *s_shift = s_vec + TRM * 32;
-    float *s_dval = s_shift + TRM * 32;
-    float *s_part = s_dval + TRM * 32;
-    float *s_red = s_part + TRM * 32;
-    int *s_fail = reinterpret_cast<int *>(s_red + 8);
-    float *tiles = smem;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l32 = lane & 31, half = lane >> 5;
-    const int T = (kx + 31) >> 5;   // column tiles
-    const int TR = (kx + 32) >> 5;  // tile rows (row kx is the right-hand side)
-    const int AR = kx >> 5, ar = kx & 31;
-
-    for (int sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
-        const int p = sys / ky, i = sys % ky;
-        // ---- lambda, mask row, normaliser ---------------------------------------------
-        const float lamv = lam[p];
-        int fail0 = (!(lamv >= 0.f) || !isfinite(lamv)) ? -1 : 0;
-        MaskParams mp;
-        mp.kind = mask_kind;
-        mp.gamma = gamma;
-        mp.inv_scale = 1.f;
-        if (mask_kind == 1) {
-            float mx = -INFINITY;
-            for (int q = tid; q < kx; q += 512) mx = fmaxf(mx, ex[(size_t)p * kx + q]);
-            for (int q = tid; q < ky; q += 512) mx = fmaxf(mx, ey[(size_t)p * ky + q]);
-            mx = wave_max(mx);
-            if (lane == 0) s_red[wave] = mx;
-            __syncthreads();
-            mx = s_red[0];
-#pragma unroll
-            for (int w = 1; w < TW; ++w) mx = fmaxf(mx, s_red[w]);
-            if ((!(mx > 0.f) || !isfinite(mx)) && fail0 == 0) fail0 = -2;
-            mp.inv_scale = 1.f / mx;
-        }
-        const float muy = ey[(size_t)p * ky + i];
-        for (int q = tid; q < TRM * 32; q += 512) {
-            const float dv = (q < kx && fail0 != -2) ? mask_entry(muy, ex[(size_t)p * kx + q], mp) : 0.f;
-            s_dval[q] = dv;
-            s_shift[q] = fail0 == 0 ? lamv * dv : 0.f;
-            s_vec[q] = 0.f;
-        }
-        if (tid == 0) *s_fail = fail0;
-        __syncthreads();
-
-        // ---- tiles: S (lower, shifted diagonal); appended row = right-hand side ----
-        const float *Kp = K + (size_t)p * kx * kx;
-        const float *rp = rhs + ((size_t)p * ky + i) * kx;
-        // tiles in column-major order of the lower triangle, two entries per thread per tile, TG tiles
-        // at a time: their loads are unconditional (addresses clamped into the arrays, the right-hand
-        // side row selected by address) so all of a group's loads are in flight together, and the
-        // values are masked when written
-        {
-            constexpr int TG = 4;
-            const int ntile = T * TR - (T * (T - 1)) / 2;
-            int I = 0, J = 0;  // tile cursor, uniform
-            for (int tau0 = 0; tau0 < ntile; tau0 += TG) {
-                float v[TG][2];
-                int Iu[TG], Ju[TG];
-#pragma unroll
-                for (int u = 0; u < TG; ++u) {
-                    Iu[u] = I;
-                    Ju[u] = J;
-                    if (++I >= TR) {  // next column of tiles
-                        ++J;
-                        I = J;
-                    }
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int rc = tid + 512 * h, r = rc >> 5, c = rc & 31;
-                        const int row = min(32 * Iu[u] + r, kx), col = min(32 * Ju[u] + c, kx - 1);
-                        v[u][h] = row == kx ? rp[col] : Kp[(size_t)row * kx + col];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < TG; ++u) {
-                    if (tau0 + u >= ntile) break;
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int rc = tid + 512 * h, r = rc >> 5, c = rc & 31;
-                        const int row = 32 * Iu[u] + r, col = 32 * Ju[u] + c;
-                        float x = 0.f;
-                        if (row < kx && col <= row) x = v[u][h] + (row == col ? s_shift[row] : 0.f);
-                        else if (row == kx && col < kx) x = v[u][h];
-                        tiles[(tau0 + u) * TSZ + r * TLD + c] = x;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-
-        for (int pstep = 0; pstep < T; ++pstep) {
-            if (__builtin_amdgcn_readfirstlane(*s_fail) != 0) break;
-            const int kxl = min(32, kx - 32 * pstep);
-            float *Dt = tiles + tile_index(pstep, pstep, TR) * TSZ;
-            // 1. diagonal tile and L_pp^{-1} (wave 0)
-            if (wave == 0) {
-                const int f = diag_factor_inverse(Dt, s_lr, s_bt, s_minv, kxl, lane);
-                if (f != 0 && lane == 0) *s_fail = 32 * pstep + f;
-            }
-            __syncthreads();
-            if (__builtin_amdgcn_readfirstlane(*s_fail) != 0) break;
-
-            // 2. panel tiles (I, pstep), I > pstep: L_Ip = S_Ip Minv^T
-            {
-                const int first = pstep + 1;
-                const int npan = TR - first;
-                for (int q = wave; q < npan; q += TW) {
-                    const int I = first + q;
-                    float *X = tiles + tile_index(I, pstep, TR) * TSZ;
-                    f32x16 nv = zero16();
-#pragma unroll
-                    for (int t = 0; t < 16; ++t)
-                        nv = mfma32x32x2(X[l32 * TLD + 2 * t + half], s_minv[l32 * TLD + 2 * t + half], nv);
-                    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) X[acc32_row(r, lane) * TLD + l32] = nv[r];
-                }
-            }
-            __syncthreads();
-
-            // 3. trailing tiles (I, J), pstep < J <= I < TR: S_IJ -= L_Ip L_Jp^T
-            {
-                const int nt = TR - pstep - 1;  // block columns pstep+1 .. TR-1 of the trailing part
-                const int ntrail = nt * (nt + 1) / 2;
-                for (int q = wave; q < ntrail; q += TW) {
-                    int jj = 0, t2 = q;
-                    while (t2 >= nt - jj) {
-                        t2 -= nt - jj;
-                        ++jj;
-                    }
-                    const int J = pstep + 1 + jj;
-                    const int I = J + t2;
-                    if (J >= T) continue;  // the appended row's block beyond the last column
-                    float *X = tiles + tile_index(I, J, TR) * TSZ;
-                    const float *LI = tiles + tile_index(I, pstep, TR) * TSZ;
-                    const float *LJ = tiles + tile_index(J, pstep, TR) * TSZ;
-                    f32x16 acc;
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) acc[r] = X[acc32_row(r, lane) * TLD + l32];
-#pragma unroll
-                    for (int t = 0; t < 16; ++t)
-                        acc = mfma32x32x2(-LI[l32 * TLD + 2 * t + half], LJ[l32 * TLD + 2 * t + half], acc);
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) X[acc32_row(r, lane) * TLD + l32] = acc[r];
-                }
-            }
-            // y of this block column (the appended row) is final
-            if (wave == TW - 1 && lane < 32) {
-                const float *src = tiles + tile_index(AR, pstep, TR) * TSZ;
-                s_vec[32 * pstep + l32] = (l32 < kxl) ? src[ar * TLD + l32] : 0.f;
-            }
-            __syncthreads();
-        }
-        const int fail = __builtin_amdgcn_readfirstlane(*s_fail);
-
-        // ---- factors out (forward mode) ----------------------------------------------------
-        if (MODE == RT_FWD && Lout && fail == 0) {
-            // in packed (column-major) order, so consecutive threads store consecutive floats.  Entry e
-            // lies in the column q with packed_col(q) <= e < packed_col(q + 1), found from the quadratic
-            // for packed_col (hardware square root) and corrected by one step either way; every index
-            // product fits in 24 bits
-            float *Lo = Lout + ((size_t)p * ky + i) * (size_t)(kx * (kx + 1) / 2);
-            const int total = kx * (kx + 1) / 2;
-            const unsigned ku = (unsigned)kx;
-            auto pcol = [&](unsigned q) { return __umul24(q, ku) - (__umul24(q, q - 1u) >> 1); };
-            const float bq = 2.f * kx + 1.f;
-            // 8 entries per batch: their LDS reads are issued together, then the stores
-            for (int e0 = tid; e0 < total; e0 += 8 * 512) {
-                int src[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const unsigned e = (unsigned)min(e0 + 512 * u, total - 1);
-                    unsigned q = (unsigned)max(
-                        (int)((bq - __builtin_amdgcn_sqrtf(fmaxf(bq * bq - 8.f * (float)e, 0.f))) * 0.5f), 0);
-                    q = min(q, ku - 1u);
-                    q += (unsigned)((q + 1u < ku) & (pcol(q + 1u) <= e));
-                    q -= (unsigned)((q > 0u) & (pcol(q) > e));
-                    const int col = (int)q, row = (int)min(q + e - pcol(q), ku - 1u);
-                    src[u] = tile_index(row >> 5, col >> 5, TR) * TSZ + (row & 31) * TLD + (col & 31);
-                }
-                float v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = tiles[src[u]];
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (e0 + 512 * u < total) Lo[e0 + 512 * u] = v[u];
-            }
-        }
-
-        // ---- back substitution L^T c = y ----------------------------------------------------
-        if (fail == 0) {
-            for (int pstep = T - 1; pstep >= 0; --pstep) {
-                const int kxl = min(32, kx - 32 * pstep);
-                // z_I = L_Ip^T c_I for pstep < I < T: lanes 0..31 and 32..63 take two tiles
-                const int nz = T - pstep - 1;
-                for (int q = 2 * wave + half; q < nz; q += 2 * TW) {
-                    const int I = pstep + 1 + q;
-                    const float *X = tiles + tile_index(I, pstep, TR) * TSZ;
-                    float z = 0.f;
-#pragma unroll
-                    for (int r = 0; r < 32; ++r) z += X[r * TLD + l32] * s_vec[32 * I + r];
-                    s_part[32 * I + l32] = z;
-                }
-                __syncthreads();
-                if (wave == 0) {
-                    const float *Dt = tiles + tile_index(pstep, pstep, TR) * TSZ;
-                    float v = 0.f;
-                    if (lane < 32) {
-                        v = s_vec[32 * pstep + l32];
-                        for (int I = pstep + 1; I < T; ++I) v -= s_part[32 * I + l32];
-                    }
-                    float cv = 0.f;
-#pragma unroll
-                    for (int c = 31; c >= 0; --c) {
-                        if (c < kxl) {
-                            const float cc = readlane(v, c) * __builtin_amdgcn_rcpf(Dt[c * TLD + c]);
-                            if (lane == c) cv = cc;
-                            if (lane < c) v -= Dt[c * TLD + l32] * cc;
-                        }
-                    }
-                    if (lane < 32) s_vec[32 * pstep + l32] = (l32 < kxl) ? cv : 0.f;
-                }
-                __syncthreads();
-            }
-        }
-
-        // ---- outputs ----------------------------------------------------------------------
-        for (int q = tid; q < kx; q += 512) {
-            const size_t o = ((size_t)p * ky + i) * kx + q;
-            out[o] = fail == 0 ? s_vec[q] : NAN;
-        }
-        if (info && tid == 0) info[(size_t)p * ky + i] = fail;
-        if (MODE != RT_FWD && dlam_part) {
-            float term = 0.f;
-            for (int q = tid; q < kx; q += 512)
-                term += (fail == 0 ? s_vec[q] : NAN) * s_dval[q] * Cfwd[((size_t)p * ky + i) * kx + q];
-            term = wave_sum(term);
-            if (lane == 0) s_red[wave] = term;
-            __syncthreads();
-            if (tid == 0) {
-                float sm = 0.f;
-#pragma unroll
-                for (int w = 0; w < TW; ++w) sm += s_red[w];
-                dlam_part[(size_t)p * ky + i] = -sm;
-            }
-        }
-        __syncthreads();  // LDS and the tile slot are reused by the next system
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Left-looking variant for 128 <= k_x <= 319: several row systems per CU.
+// The left-looking kernel, 64 < k_x <= 319: several row systems per CU.
 //
-// The right-looking kernel above keeps every tile of a system in LDS (118 KB at
-// k_x = 200), so a CU holds one system and idles while one wave factorises a
-// diagonal tile.  Here a workgroup of 4 waves keeps only the active block
-// column in LDS (7 tiles at k_x = 200, 37 KB in all) and writes each finished
-// tile L_Ip, and the inverse of each diagonal tile, to its own slot of the
-// workspace (32 x 32 row-major tiles in the lower-triangle order of the tile
-// grid; the diagonal positions hold the inverses).  Three or four systems then
-// share a CU and hide each other's serial diagonal steps.  Step p:
+// Keeping every tile of a system in LDS (118 KB at k_x = 200) would hold a CU
+// to one system, idle while one wave factorises a diagonal tile.  Here a
+// workgroup of 4 waves keeps only the active block column in LDS (40 KB in all
+// at k_x = 200) and writes each finished tile L_Ip, and the inverse of each
+// diagonal tile, to its own slot of the workspace (32 x 32 row-major tiles in
+// the lower-triangle order of the tile grid; the diagonal positions hold the
+// inverses).  Two to four systems then share a CU and hide each other's serial
+// diagonal steps.  Step p:
 //   1. block column p of S = K + lambda diag(D_i), with the right-hand side as
 //      the appended row, is loaded into LDS;
 //   2. left-looking update S_Ip -= sum_{q < p} L_Iq L_pq^T on the float32
-//      matrix cores, the L tiles read from the slot (L2) straight into the
-//      operand registers: lane (m, h) supplies row m, columns 16 h .. 16 h + 15,
-//      with the K order of the matrix-core steps permuted alike for both operands;
-//   3. wave 0 factorises the diagonal tile and forms its inverse (as above);
+//      matrix cores, the L tiles read from the slot straight into the operand
+//      registers: lane (m, h) supplies row m, columns 16 h .. 16 h + 15, with
+//      the K order of the matrix-core steps permuted alike for both operands.
+//      One wave updates the diagonal tile and goes on to step 3 at once, while
+//      the others update the tiles below it;
+//   3. that wave factorises the diagonal tile and forms its inverse
+//      (diag_factor_inverse);
 //   4. the panel L_Ip = S_Ip L_pp^{-T} on the matrix cores, stored to the slot.
 // The appended row carries the forward substitution, so its tile row yields
 // y.  The back substitution runs block by block from the last: the finished
@@ -470,13 +188,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TMAX <= 4 ?
 constexpr int LLW = 4;          // waves per workgroup
 constexpr int LTS = 32 * 32;    // floats per tile in the workspace slot
 
-constexpr int ll_lds_floats(int TRM) { return TRM * TSZ + TSZ + DIAG_LR + DIAG_BC + 3 * TRM * 32 + LLW * 32 + LLW + 4; }
+constexpr int ll_lds_floats(int TRM) { return TRM * TSZ + TSZ + DIAG_LR + 2 * TRM * 32 + LLW * 32 + LLW + 4; }
 
 __device__ __forceinline__ f32x4 ldg4(const float *p) { return *reinterpret_cast<const f32x4 *>(p); }
 
 // STORE: the factor is written to Lout (forward mode with stored factors).
 template <int TMAX, int MODE, bool STORE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 ? 2 : 3))) void rowsolve_ll_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 ? 2 : 4))) void rowsolve_ll_kernel(
     const float *__restrict__ K, const float *__restrict__ rhs, const float *__restrict__ ex,
     const float *__restrict__ ey, const float *__restrict__ lam, int mask_kind, float gamma, int kx, int ky, int nsys,
     float *out, float *__restrict__ Lout, int *__restrict__ info, const float *__restrict__ Cfwd,
@@ -488,10 +206,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
     float *bc = smem;                    // tile j: rows 32 (p + j) .. 32 (p + j) + 31 of block column p
     float *s_minv = bc + TRM * TSZ;      // inverse of the diagonal tile, Minv[q][c] at q * TLD + c
     float *s_lr = s_minv + TSZ;          // scratch of the diagonal-tile routine
-    float *s_bt = s_lr + DIAG_LR;
-    float *s_dval = s_bt + DIAG_BC;
-    float *s_shift = s_dval + TRM * 32;
-    float *s_vec = s_shift + TRM * 32;   // y, then c
+    float *s_dval = s_lr + DIAG_LR;      // mask row D_i
+    float *s_vec = s_dval + TRM * 32;    // y, then c
     float *s_part = s_vec + TRM * 32;    // [LLW][32]
     float *s_red = s_part + LLW * 32;    // [LLW]
     int *s_fail = reinterpret_cast<int *>(s_red + LLW);
@@ -508,6 +224,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
 
     for (int sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
         const int p = sys / ky, i = sys % ky;
+        int tid = threadIdx.x;  // opaque per system, as in the steps below
+        asm volatile("" : "+v"(tid));
+        const int lane = tid & 63;
         // ---- lambda, mask row, normaliser -----------------------------------------------
         const float lamv = lam[p];
         int fail0 = (!(lamv >= 0.f) || !isfinite(lamv)) ? -1 : 0;
@@ -530,10 +249,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
         for (int q = tid; q < TRM * 32; q += 256) {
             const float dv = (q < kx && fail0 != -2) ? mask_entry(muy, ex[(size_t)p * kx + q], mp) : 0.f;
             s_dval[q] = dv;
-            s_shift[q] = fail0 == 0 ? lamv * dv : 0.f;
             s_vec[q] = 0.f;
         }
         if (tid == 0) *s_fail = fail0;
+        const float lsh = fail0 == 0 ? lamv : 0.f;  // the diagonal shift is lsh * D_iq
         __syncthreads();
 
         const float *Kp = K + (size_t)p * kx * kx;
@@ -574,7 +293,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
                         for (int t = 0; t < 4; ++t) {
                             const int col = 32 * ps + c0 + t;
                             float x = 0.f;
-                            if (row < kx && col < kx) x = v[u][t] + (row == col ? s_shift[row] : 0.f);
+                            if (row < kx && col < kx) x = v[u][t] + (row == col ? lsh * s_dval[row] : 0.f);
                             else if (row == kx && col < kx) x = v[u][t];
                             bc[j * TSZ + r * TLD + c0 + t] = x;
                         }
@@ -599,7 +318,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
                             const int j = e >> 10, r = (e >> 5) & 31, c = e & 31;
                             const int row = 32 * (ps + j) + r, col = 32 * ps + c;
                             float x = 0.f;
-                            if (row < kx && col < kx) x = v[u] + (row == col ? s_shift[row] : 0.f);
+                            if (row < kx && col < kx) x = v[u] + (row == col ? lsh * s_dval[row] : 0.f);
                             else if (row == kx && col < kx) x = v[u];
                             bc[j * TSZ + r * TLD + c] = x;
                         }
@@ -658,7 +377,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
             }
             // ---- 3. diagonal tile and its inverse (one wave) ----------------------------------
             if (wave == dwave) {
-                const int f = diag_factor_inverse(bc, s_lr, s_bt, s_minv, kxl, lane);
+                const int f = diag_factor_inverse(bc, s_lr, s_minv, kxl, lane);
                 if (f != 0) {
                     if (lane == 0) *s_fail = 32 * ps + f;
                 } else {
@@ -890,33 +609,13 @@ static int64_t ll_slots(int64_t nsys)
     return nsys < cap ? nsys : cap;
 }
 
-// Tile rows of the left-looking instance (k_x >= 128; below, the right-looking kernel with every tile in LDS
-// runs two systems per CU and is as fast).
-static int ll_tmax(int64_t kx) { return kx < 224 ? 7 : 10; }
+// Tile rows of the instance for k_x (k_x + 1 rows, with the appended right-hand side)
+static int ll_tmax(int64_t kx) { return kx < 128 ? 4 : (kx < 224 ? 7 : 10); }
 
 size_t tiled_workspace_bytes(int64_t P, int64_t kx, int64_t ky)
 {
-    if (kx < 128) return 0;
     const int64_t tm = ll_tmax(kx);
     return (size_t)ll_slots(P * ky) * (tm * (tm + 1) / 2) * LTS * sizeof(float);
-}
-
-template <int TMAX, int MODE>
-static void launch_tiles(const float *K, const float *rhs, const float *ex, const float *ey, const float *lam,
-                         int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, float *Lout,
-                         int *info, const float *Cfwd, float *dlam_part, hipStream_t st)
-{
-    constexpr int NTL = TMAX * (TMAX + 1) / 2;
-    const size_t lds = ((size_t)NTL * TSZ + aux_floats(TMAX)) * sizeof(float);
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void *)rowsolve_tiles_kernel<TMAX, MODE>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
-    }
-    const int64_t nsys = P * ky, grid = nsys;
-    hipLaunchKernelGGL((rowsolve_tiles_kernel<TMAX, MODE>), dim3((unsigned)grid), dim3(512), lds, st, K, rhs, ex,
-                       ey, lam, mask_kind, gamma, (int)kx, (int)ky, (int)nsys, out, Lout, info, Cfwd, dlam_part);
 }
 
 template <int TMAX, int MODE, bool STORE>
@@ -933,7 +632,8 @@ static void launch_ll(const float *K, const float *rhs, const float *ex, const f
     }
     // one round of resident workgroups (the runtime's occupancy for this instance, at most the four per CU the
     // workspace holds slots for): a persistent grid larger than what fits would leave the surplus workgroups
-    // waiting for whole early workgroups, which loop over several systems each
+    // waiting for whole early workgroups, which loop over several systems each.  At TMAX = 10 three would fit
+    // but measured slower than two (k = 300: 1.23 against 1.05 ms per forward solve).
     static int per_cu = 0;
     if (per_cu == 0) {
         int n = 0;
@@ -941,7 +641,8 @@ static void launch_ll(const float *K, const float *rhs, const float *ex, const f
                 hipSuccess ||
             n < 1)
             n = 1;
-        per_cu = n < 4 ? n : 4;
+        const int cap = TMAX == 10 ? 2 : 4;
+        per_cu = n < cap ? n : cap;
     }
     const int64_t nsys = P * ky;
     const int64_t grid = std::min<int64_t>(nsys, (int64_t)per_cu * cu_count());
@@ -953,27 +654,20 @@ void launch_rowsolve_tiled(int mode, const float *K, const float *rhs, const flo
                            const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out,
                            float *Lout, int *info, const float *Cfwd, float *dlam_part, float *tws, hipStream_t st)
 {
-    if (kx < 128) {
-        // every tile in LDS, two systems per CU
-        if (mode == RT_FWD)
-            launch_tiles<4, RT_FWD>(K, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info, Cfwd,
-                                    dlam_part, st);
-        else
-            launch_tiles<4, RT_BWD_RECOMPUTE>(K, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info,
-                                              Cfwd, dlam_part, st);
-        return;
-    }
     const int tm = ll_tmax(kx);
 #define FMAP_LL(TM, MD, SF) launch_ll<TM, MD, SF>(K, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info, \
                                                   Cfwd, dlam_part, tws, st)
     if (mode == RT_FWD && Lout) {
-        if (tm == 7) FMAP_LL(7, RT_FWD, true);
+        if (tm == 4) FMAP_LL(4, RT_FWD, true);
+        else if (tm == 7) FMAP_LL(7, RT_FWD, true);
         else FMAP_LL(10, RT_FWD, true);
     } else if (mode == RT_FWD) {
-        if (tm == 7) FMAP_LL(7, RT_FWD, false);
+        if (tm == 4) FMAP_LL(4, RT_FWD, false);
+        else if (tm == 7) FMAP_LL(7, RT_FWD, false);
         else FMAP_LL(10, RT_FWD, false);
     } else {
-        if (tm == 7) FMAP_LL(7, RT_BWD_RECOMPUTE, false);
+        if (tm == 4) FMAP_LL(4, RT_BWD_RECOMPUTE, false);
+        else if (tm == 7) FMAP_LL(7, RT_BWD_RECOMPUTE, false);
         else FMAP_LL(10, RT_BWD_RECOMPUTE, false);
     }
 #undef FMAP_LL
