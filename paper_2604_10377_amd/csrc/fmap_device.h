@@ -99,6 +99,14 @@ __device__ __forceinline__ float readlane(float v, int lane)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// v_writelane: lane `lane` of `old` takes the wave-uniform `src`, the other lanes keep theirs (the LLVM
+// intrinsic, which this compiler exposes under no builtin name)
+__device__ int amdgcn_writelane_i32(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+__device__ __forceinline__ float writelane(float src, int lane, float old)
+{
+    return __int_as_float(amdgcn_writelane_i32(__float_as_int(src), lane, __float_as_int(old)));
+}
+
 // bfloat16 bit pattern -> float (exact).
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 

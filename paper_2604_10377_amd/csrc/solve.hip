@@ -206,7 +206,7 @@ __device__ __forceinline__ float uniform(float v) { return __int_as_float(__buil
 // ---------------------------------------------------------------------------
 template <int KMAX> struct RowsolveLds {
     static constexpr int KP = KMAX + 4;                    // staged factor row stride (floats)
-    static constexpr int PER_WAVE = 4 * KMAX + KMAX * KP + 3 * KMAX;  // block broadcast, staged factor, scalars
+    static constexpr int PER_WAVE = 4 * KMAX + KMAX * KP;  // block broadcast, staged factor
 };
 
 template <int KMAX, int MODE>
@@ -223,9 +223,8 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
     const int W = blockDim.x >> 6;
     float *s_bcw = s_rs + w * RowsolveLds<KMAX>::PER_WAVE;  // [KMAX][4]: the block's columns, row by row
     float *s_Lw = s_bcw + 4 * KMAX;                          // [KMAX][KP]: rows of L
-    // per-column scalars (1 / L_cc, y_c, c_c): lane 0 records them as the serial steps produce them,
-    // and each lane reads its own entry afterwards (no per-column lane masks)
-    float *s_inv = s_Lw + KMAX * KP, *s_y = s_inv + KMAX, *s_c = s_y + KMAX;
+    // per-column scalars (1 / L_cc, y_c, c_c) are written into lane c of a register as the serial steps
+    // produce them (v_writelane: no lane mask, no LDS), and each lane uses its own entry afterwards
     const int rgroups = (ky + W - 1) / W;
     const int p = blockIdx.x / rgroups;
     const int i = (blockIdx.x % rgroups) * W + w;
@@ -275,6 +274,7 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
         sr[q] = (q == j) ? (jok ? v + shift : 1.f) : v;
     }
     float r = jok ? rin : 0.f;
+    float vinv = 0.f, vy = 0.f;
 
     // Lanes j < c take garbage in column c (and in their entries above the diagonal); none of it is
     // read: a lane's later use of column c is for rows below c, and y_j was recorded at step j.
@@ -292,10 +292,8 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
                     const float l = sr[c] * inv;  // lane c: sqrt(pivot)
                     sr[c] = l;
                     const float yc = uniform(readlane(r, c) * inv);  // forward substitution, step c
-                    if (j == 0) {
-                        s_inv[c] = inv;
-                        s_y[c] = yc;
-                    }
+                    vinv = writelane(inv, c, vinv);
+                    vy = writelane(yc, c, vy);
                     r -= l * yc;
 #pragma unroll
                     for (int t2 = t + 1; t2 < 4; ++t2) sr[c0 + t2] -= l * readlane(l, c0 + t2);
@@ -357,19 +355,18 @@ __global__ __launch_bounds__(256) void rowsolve_kernel(
         const int jr = min(j, KMAX - 1);
 #pragma unroll
         for (int c = 0; c < KMAX; ++c) sr[c] = (c > j) ? s_Lw[c * KP + jr] : 0.f;
-        const int jr2 = min(j, KMAX - 1);
-        float y = s_y[jr2];
-        const float myinv = s_inv[jr2];
+        float y = vy;
+        const float myinv = vinv;
+        float vc = 0.f;
 #pragma unroll
         for (int c = KMAX - 1; c >= 0; --c) {
             // columns of blocks past k_x were never factorised (their scalars were never recorded):
             // their solution entries are 0, taken by a select so that no stale value enters
             const float cc = (c < kx) ? uniform(readlane(y, c) * readlane(myinv, c)) : 0.f;
-            if (j == 0) s_c[c] = cc;
+            vc = writelane(cc, c, vc);
             y -= sr[c] * cc;
         }
-        __builtin_amdgcn_wave_barrier();
-        cv = s_c[jr2];
+        cv = vc;
     }
 
     if (jok) {
@@ -589,6 +586,7 @@ static void launch_rowsolve(const float *K, const float *rhs, const float *ex, c
     else if (kx <= 32) FMAP_RS(32);
     else if (kx <= 40) FMAP_RS(40);
     else if (kx <= 48) FMAP_RS(48);
+    else if (kx <= 52) FMAP_RS(52);
     else if (kx <= 56) FMAP_RS(56);
     else FMAP_RS(64);
 #undef FMAP_RS

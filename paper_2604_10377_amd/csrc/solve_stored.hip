@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void trisolve_small_kernel(const float *__rest
                                                             int *__restrict__ info, const float *__restrict__ Cfwd,
                                                             float *__restrict__ dlam_part, const float *addend)
 {
-    static_assert(KMAX % 8 == 0 && KMAX <= 64, "register row length");
+    static_assert(KMAX % 4 == 0 && KMAX <= 64, "register row length");
     const int j = threadIdx.x & 63;
     // the system index in a scalar register, so the buffer descriptor below is one per wave
     const int sys = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
@@ -355,16 +355,15 @@ void launch_trisolve_small(const float *Lin, const float *rhs, const float *ex, 
         hipLaunchKernelGGL((trisolve_small_kernel<KM>), grid, block, lds_, st, Lin, rhs, ex, ey, lam, mask_kind,  \
                            gamma, (int)kx, (int)ky, nsys, out, info, Cfwd, dlam_part, addend);                    \
     } while (0)
-    switch ((kx + 7) / 8) {
-    case 1: FMAP_TSS(8); break;
-    case 2: FMAP_TSS(16); break;
-    case 3: FMAP_TSS(24); break;
-    case 4: FMAP_TSS(32); break;
-    case 5: FMAP_TSS(40); break;
-    case 6: FMAP_TSS(48); break;
-    case 7: FMAP_TSS(56); break;
-    default: FMAP_TSS(64); break;
-    }
+    if (kx <= 8) FMAP_TSS(8);
+    else if (kx <= 16) FMAP_TSS(16);
+    else if (kx <= 24) FMAP_TSS(24);
+    else if (kx <= 32) FMAP_TSS(32);
+    else if (kx <= 40) FMAP_TSS(40);
+    else if (kx <= 48) FMAP_TSS(48);
+    else if (kx <= 52) FMAP_TSS(52);
+    else if (kx <= 56) FMAP_TSS(56);
+    else FMAP_TSS(64);
 #undef FMAP_TSS
 }
 

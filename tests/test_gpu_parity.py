@@ -173,8 +173,9 @@ def _unpack_lower_colmajor(packed, m):
     return L
 
 
+# k_x picks the register row length (the next multiple of 8, or 52 for 49..52): both sides of each boundary
 SOLVE_CASES = [(3, 1, 1, 4), (5, 5, 5, 16), (4, 30, 30, 128), (3, 50, 50, 256), (2, 64, 64, 256),
-               (3, 17, 33, 80), (2, 40, 23, 96), (7, 32, 32, 64)]
+               (3, 17, 33, 80), (2, 40, 23, 96), (7, 32, 32, 64), (2, 52, 52, 128), (2, 53, 41, 128)]
 
 
 @pytest.mark.parametrize("mask", [0, 1])
