@@ -86,7 +86,7 @@ hipError_t launch_project_backward(const void *phi, const float *mass, int32_t d
 // rs_waves: row systems per workgroup of the register row solve (k_x <= kSmallK): 1, 2 or 4.
 // Workspace carve-up of the solver (byte offsets, 256-aligned).
 struct SolveWs {
-    size_t K, R, V, W, tiles, K64, R64, dlam, total;
+    size_t K, R, V, W, tiles, K64, R64, dlam, flag, total;
 };
 SolveWs solve_workspace_layout(int64_t pairs, int64_t kx, int64_t ky, int64_t d);
 
@@ -102,16 +102,19 @@ hipError_t launch_solve_backward(const float *dC, const float *A, const float *B
 // Row solves with stored factors (reverse mode, refinement correction) by streaming triangular solves.
 void launch_trisolve_stored(const float *Lin, const float *rhs, const float *ex, const float *ey, const float *lam,
                             int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, int *info,
-                            const float *Cfwd, float *dlam_part, const float *addend, hipStream_t st);
+                            const float *Cfwd, float *dlam_part, const float *addend, hipStream_t st,
+                            const int *only = nullptr);
 // The same for k_x <= 64: one wave per system, both substitutions in registers.
 void launch_trisolve_small(const float *Lin, const float *rhs, const float *ex, const float *ey, const float *lam,
                            int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, int *info,
                            const float *Cfwd, float *dlam_part, const float *addend, hipStream_t st);
 // Row systems for 64 < k_x <= kMaxK: mode 0 forward (factors to Lout if non-NULL), mode 2 reverse mode with
 // refactorisation (V rows, per-row dlambda terms).  tile_ws: tiled_workspace_bytes(P, k_x, k_y) bytes.
+// only: if non-NULL, the systems of pairs p with only[p] == 0 are skipped (their outputs left as they are).
 void launch_rowsolve_tiled(int mode, const float *K, const float *rhs, const float *ex, const float *ey,
                            const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out,
-                           float *Lout, int *info, const float *Cfwd, float *dlam_part, float *tile_ws, hipStream_t st);
+                           float *Lout, int *info, const float *Cfwd, float *dlam_part, float *tile_ws, hipStream_t st,
+                           const int *only = nullptr);
 size_t tiled_workspace_bytes(int64_t P, int64_t kx, int64_t ky);
 void launch_adjoint_general(const float *V, const float *C, const float *A, const float *B, int64_t P, int64_t kx,
                             int64_t ky, int64_t d, float *Wbuf, const float *dlam_part, float *dlam, float *dA,
@@ -121,9 +124,10 @@ void launch_gram64(const float *A, const float *B, int64_t P, int64_t kx, int64_
                    double *R64, hipStream_t st);
 void launch_residual64(const float *C, const double *K64, const double *R64, const float *ex, const float *ey,
                        const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *rho,
-                       hipStream_t st);
+                       hipStream_t st, const int *only = nullptr);
+// flag: if non-NULL, flag[p] = 1 where the pair's products were replaced (estimate above threshold), else 0.
 void launch_cond(const float *K, int64_t P, int64_t kx, int64_t ky, float threshold, const double *K64,
-                 const double *R64, float *Kout, float *Rout, float *cond_est, hipStream_t st);
+                 const double *R64, float *Kout, float *Rout, float *cond_est, hipStream_t st, int *flag = nullptr);
 // Largest k_x for the condition estimate (its float32 factor lives in LDS).
 constexpr int kMaxCondK = 256;
 

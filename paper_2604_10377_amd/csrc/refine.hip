@@ -107,12 +107,13 @@ __global__ __launch_bounds__(256) void residual64_kernel(const float *__restrict
                                                          const double *__restrict__ R64, const float *__restrict__ ex,
                                                          const float *__restrict__ ey, const float *__restrict__ lam,
                                                          int mask_kind, float gamma, int kx, int ky,
-                                                         float *__restrict__ rho)
+                                                         float *__restrict__ rho, const int *__restrict__ only)
 {
     extern __shared__ double sC[];  // [16][kx]
     __shared__ double s_red[4];
     const int rb = (ky + 15) / 16;
     const int p = blockIdx.x / rb, i0 = (blockIdx.x % rb) * 16;
+    if (only && only[p] == 0) return;  // whole workgroup, before any barrier
     const int tid = threadIdx.x;
     const int nr = min(16, ky - i0);
     batched_for<8>(
@@ -294,7 +295,7 @@ __device__ __forceinline__ void chol_solve_regs(const float *L, const float *Din
 __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, int kx, float threshold,
                                                    const double *__restrict__ K64, const double *__restrict__ R64,
                                                    float *__restrict__ Kout, float *__restrict__ Rout, int ky,
-                                                   float *__restrict__ cond_est)
+                                                   float *__restrict__ cond_est, int *__restrict__ flag)
 {
     extern __shared__ __align__(16) float sm[];
     float *L = sm;                     // packed lower, kx(kx+1)/2
@@ -463,7 +464,9 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
     }
     if (tid == 0 && cond_est) cond_est[p] = est;
     // ill-conditioned pair: use the float64-formed products (rounded) for the row factorisations
-    if (threshold > 0.f && !(est <= threshold) && K64) {
+    const bool replace = threshold > 0.f && !(est <= threshold) && K64;
+    if (tid == 0 && flag) flag[p] = replace ? 1 : 0;
+    if (replace) {
         batched_for<8>(
             tid, kx * kx, 512, [&](int e) { return K64[(size_t)p * kx * kx + e]; },
             [&](int e, double v) { Kout[(size_t)p * kx * kx + e] = (float)v; });
@@ -487,7 +490,7 @@ void launch_gram64(const float *A, const float *B, int64_t P, int64_t kx, int64_
 
 void launch_residual64(const float *C, const double *K64, const double *R64, const float *ex, const float *ey,
                        const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *rho,
-                       hipStream_t st)
+                       hipStream_t st, const int *only)
 {
     const size_t lds = (size_t)16 * kx * sizeof(double);
     static bool attr = false;
@@ -497,11 +500,11 @@ void launch_residual64(const float *C, const double *K64, const double *R64, con
         attr = true;
     }
     hipLaunchKernelGGL(residual64_kernel, dim3((unsigned)(P * ((ky + 15) / 16))), dim3(256), lds, st, C, K64, R64,
-                       ex, ey, lam, mask_kind, gamma, (int)kx, (int)ky, rho);
+                       ex, ey, lam, mask_kind, gamma, (int)kx, (int)ky, rho, only);
 }
 
 void launch_cond(const float *K, int64_t P, int64_t kx, int64_t ky, float threshold, const double *K64,
-                 const double *R64, float *Kout, float *Rout, float *cond_est, hipStream_t st)
+                 const double *R64, float *Kout, float *Rout, float *cond_est, hipStream_t st, int *flag)
 {
     const size_t lds = ((size_t)kx * (kx + 1) / 2 + (1 + CPW) * kx + 4 + CPAD) * sizeof(float);
     static bool attr = false;
@@ -512,7 +515,7 @@ void launch_cond(const float *K, int64_t P, int64_t kx, int64_t ky, float thresh
         attr = true;
     }
     hipLaunchKernelGGL(cond_kernel, dim3((unsigned)P), dim3(512), lds, st, K, (int)kx, threshold, K64, R64, Kout, Rout,
-                       (int)ky, cond_est);
+                       (int)ky, cond_est, flag);
 }
 
 }  // namespace fmap

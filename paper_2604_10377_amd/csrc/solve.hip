@@ -21,6 +21,8 @@
 // is broadcast through LDS and each lane applies the rank-1 update to its row.
 // Work per step is uniform, so the wave never diverges; a non-positive pivot
 // is detected uniformly and stops the factorisation (LAPACK info).
+#include <mutex>
+
 #include "fmap_device.h"
 #include "fmap_launch.h"
 
@@ -542,6 +544,8 @@ SolveWs solve_workspace_layout(int64_t P, int64_t kx, int64_t ky, int64_t d)
     off += align256((size_t)P * ky * kx * sizeof(double));
     w.dlam = off;
     off += align256((size_t)P * ky * sizeof(float));
+    w.flag = off;
+    off += align256((size_t)P * sizeof(int));
     w.total = off;
     return w;
 }
@@ -592,6 +596,42 @@ static void launch_rowsolve(const float *K, const float *rhs, const float *ex, c
 #undef FMAP_RS
 }
 
+// A second stream per device, with a fork and a join event, for work that overlaps the caller's stream
+// within one library call.  Created on first use outside stream capture (creating it during a capture is not
+// allowed); under capture the fork and join become graph edges, so the side work is part of the captured graph.
+// Calls that overlap on one device share it: their side work is serialised, but each waits for its own.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+static SideStream *side_stream(hipStream_t st)
+{
+    static std::mutex mu;
+    static SideStream per_dev[64];
+    static bool made[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!made[dev]) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+        SideStream S;
+        bool ok = hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&S.fork, hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&S.join, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            if (S.join) (void)hipEventDestroy(S.join);
+            if (S.fork) (void)hipEventDestroy(S.fork);
+            if (S.s) (void)hipStreamDestroy(S.s);
+            return nullptr;
+        }
+        per_dev[dev] = S;
+        made[dev] = true;
+    }
+    return &per_dev[dev];
+}
+
 hipError_t launch_solve(const float *A, const float *B, const float *ex, const float *ey, const float *lam,
                         int32_t mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, int64_t d,
                         int32_t refine_steps, float cond_threshold, float *C, float *factors, int32_t *info,
@@ -604,9 +644,45 @@ hipError_t launch_solve(const float *A, const float *B, const float *ex, const f
     float *tiles = (float *)(base + L.tiles);
     launch_gram(A, B, P, kx, ky, d, true, K, R, st);
     if (refine_steps > 0) launch_gram64(A, B, P, kx, ky, d, K64, R64, st);
-    if (cond_threshold > 0.f || cond_est)
-        launch_cond(K, P, kx, ky, refine_steps > 0 ? cond_threshold : 0.f, refine_steps > 0 ? K64 : nullptr,
-                    refine_steps > 0 ? R64 : nullptr, K, R, cond_est, st);
+    const bool want_cond = cond_threshold > 0.f || cond_est;
+    const float thr = refine_steps > 0 ? cond_threshold : 0.f;
+    float *rho = (float *)(base + L.V);
+    SideStream *side = (want_cond && refine_steps > 0 && kx > kSmallK) ? side_stream(st) : nullptr;
+    if (side) {
+        // The condition estimate (one workgroup per pair, latency-bound) runs on a side stream beside the
+        // refinement of every pair, after the row solve on the float32 products.  Nothing on the main stream
+        // reads K or R after that solve, so the estimate may replace them for the pairs above the threshold;
+        // those pairs are then solved and refined again from the rounded float64 products (their first results
+        // are overwritten), which gives every pair the result of the sequential order.
+        int *flag = (int *)(base + L.flag);
+        launch_rowsolve_tiled(RS_FWD, K, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info, nullptr,
+                              nullptr, tiles, st);
+        hipError_t e = hipEventRecord(side->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
+        if (e != hipSuccess) return e;
+        launch_cond(K, P, kx, ky, thr, K64, R64, K, R, cond_est, side->s, flag);
+        e = hipEventRecord(side->join, side->s);
+        for (int it = 0; it < refine_steps; ++it) {
+            launch_residual64(C, K64, R64, ex, ey, lam, mask_kind, gamma, P, kx, ky, rho, st);
+            launch_trisolve_stored(factors, rho, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, nullptr, nullptr,
+                                   nullptr, C, st);
+        }
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
+        if (e != hipSuccess) return e;
+        if (thr > 0.f) {
+            launch_rowsolve_tiled(RS_FWD, K, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info, nullptr,
+                                  nullptr, tiles, st, flag);
+            for (int it = 0; it < refine_steps; ++it) {
+                launch_residual64(C, K64, R64, ex, ey, lam, mask_kind, gamma, P, kx, ky, rho, st, flag);
+                launch_trisolve_stored(factors, rho, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, nullptr, nullptr,
+                                       nullptr, C, st, flag);
+            }
+        }
+        return hipGetLastError();
+    }
+    if (want_cond)
+        launch_cond(K, P, kx, ky, thr, refine_steps > 0 ? K64 : nullptr, refine_steps > 0 ? R64 : nullptr, K, R,
+                    cond_est, st);
     if (kx <= kSmallK)
         launch_rowsolve<RS_FWD>(K, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info, nullptr,
                                 nullptr, st, rs_waves);
@@ -614,7 +690,6 @@ hipError_t launch_solve(const float *A, const float *B, const float *ex, const f
         launch_rowsolve_tiled(RS_FWD, K, R, ex, ey, lam, mask_kind, gamma, P, kx, ky, C, factors, info, nullptr,
                               nullptr, tiles, st);
     // iterative refinement: rho = R64 - C K64 - lambda D o C in float64, C += S^{-1} rho with the float32 factors
-    float *rho = (float *)(base + L.V);
     for (int it = 0; it < refine_steps; ++it) {
         launch_residual64(C, K64, R64, ex, ey, lam, mask_kind, gamma, P, kx, ky, rho, st);
         if (kx <= kSmallK)

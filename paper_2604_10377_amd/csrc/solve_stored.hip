@@ -48,13 +48,15 @@ __global__ __launch_bounds__(256) void trisolve_stored_kernel(const float *__res
                                                              const float *__restrict__ lam, int mask_kind, float gamma,
                                                              int kx, int ky, int nsys, float *out,
                                                              int *__restrict__ info, const float *__restrict__ Cfwd,
-                                                             float *__restrict__ dlam_part, const float *addend)
+                                                             float *__restrict__ dlam_part, const float *addend,
+                                                             const int *__restrict__ only)
 {
     const int j = threadIdx.x & 63;
     // the system index in a scalar register, so the buffer descriptor below is one per wave
     const int sys = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (sys >= nsys) return;  // wave-uniform; no block-level barrier below
     const int p = sys / ky, i = sys - p * ky;
+    if (only && __builtin_amdgcn_readfirstlane(only[p]) == 0) return;  // wave-uniform
     const float *Lp = Lin + (size_t)sys * (kx * (kx + 1) / 2);
     const int ng = (kx + SG - 1) / SG;
 
@@ -194,13 +196,13 @@ __global__ __launch_bounds__(256) void trisolve_stored_kernel(const float *__res
 
 void launch_trisolve_stored(const float *Lin, const float *rhs, const float *ex, const float *ey, const float *lam,
                             int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, int *info,
-                            const float *Cfwd, float *dlam_part, const float *addend, hipStream_t st)
+                            const float *Cfwd, float *dlam_part, const float *addend, hipStream_t st, const int *only)
 {
     const int nsys = (int)(P * ky);
     const dim3 grid((unsigned)((nsys + 3) / 4)), block(256);
 #define FMAP_TS(NS)                                                                                              \
     hipLaunchKernelGGL((trisolve_stored_kernel<NS>), grid, block, 0, st, Lin, rhs, ex, ey, lam, mask_kind, gamma, \
-                       (int)kx, (int)ky, nsys, out, info, Cfwd, dlam_part, addend)
+                       (int)kx, (int)ky, nsys, out, info, Cfwd, dlam_part, addend, only)
     switch ((kx + 63) / 64) {
     case 1: FMAP_TS(1); break;
     case 2: FMAP_TS(2); break;

@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
     const float *__restrict__ K, const float *__restrict__ rhs, const float *__restrict__ ex,
     const float *__restrict__ ey, const float *__restrict__ lam, int mask_kind, float gamma, int kx, int ky, int nsys,
     float *out, float *__restrict__ Lout, int *__restrict__ info, const float *__restrict__ Cfwd,
-    float *__restrict__ dlam_part, float *__restrict__ Lws, int cus)
+    float *__restrict__ dlam_part, float *__restrict__ Lws, int cus, const int *__restrict__ only)
 {
     constexpr int TRM = TMAX;
     constexpr int NTL = TMAX * (TMAX + 1) / 2;
@@ -224,6 +224,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
 
     for (int sys = blockIdx.x; sys < nsys; sys += gridDim.x) {
         const int p = sys / ky, i = sys % ky;
+        if (only && __builtin_amdgcn_readfirstlane(only[p]) == 0) continue;  // uniform: before any barrier
         int tid = threadIdx.x;  // opaque per system, as in the steps below
         asm volatile("" : "+v"(tid));
         const int lane = tid & 63;
@@ -621,7 +622,7 @@ size_t tiled_workspace_bytes(int64_t P, int64_t kx, int64_t ky)
 template <int TMAX, int MODE, bool STORE>
 static void launch_ll(const float *K, const float *rhs, const float *ex, const float *ey, const float *lam,
                       int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out, float *Lout, int *info,
-                      const float *Cfwd, float *dlam_part, float *ws, hipStream_t st)
+                      const float *Cfwd, float *dlam_part, float *ws, hipStream_t st, const int *only)
 {
     const size_t lds = (size_t)ll_lds_floats(TMAX) * sizeof(float);
     static bool attr = false;
@@ -647,16 +648,18 @@ static void launch_ll(const float *K, const float *rhs, const float *ex, const f
     const int64_t nsys = P * ky;
     const int64_t grid = std::min<int64_t>(nsys, (int64_t)per_cu * cu_count());
     hipLaunchKernelGGL((rowsolve_ll_kernel<TMAX, MODE, STORE>), dim3((unsigned)grid), dim3(256), lds, st, K, rhs, ex, ey, lam,
-                       mask_kind, gamma, (int)kx, (int)ky, (int)nsys, out, Lout, info, Cfwd, dlam_part, ws, cu_count());
+                       mask_kind, gamma, (int)kx, (int)ky, (int)nsys, out, Lout, info, Cfwd, dlam_part, ws, cu_count(),
+                       only);
 }
 
 void launch_rowsolve_tiled(int mode, const float *K, const float *rhs, const float *ex, const float *ey,
                            const float *lam, int mask_kind, float gamma, int64_t P, int64_t kx, int64_t ky, float *out,
-                           float *Lout, int *info, const float *Cfwd, float *dlam_part, float *tws, hipStream_t st)
+                           float *Lout, int *info, const float *Cfwd, float *dlam_part, float *tws, hipStream_t st,
+                           const int *only)
 {
     const int tm = ll_tmax(kx);
 #define FMAP_LL(TM, MD, SF) launch_ll<TM, MD, SF>(K, rhs, ex, ey, lam, mask_kind, gamma, P, kx, ky, out, Lout, info, \
-                                                  Cfwd, dlam_part, tws, st)
+                                                  Cfwd, dlam_part, tws, st, only)
     if (mode == RT_FWD && Lout) {
         if (tm == 4) FMAP_LL(4, RT_FWD, true);
         else if (tm == 7) FMAP_LL(7, RT_FWD, true);

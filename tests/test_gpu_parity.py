@@ -508,16 +508,23 @@ def test_refinement_reduces_error(F, dev, k, d, ratio, lam):
         assert e2 <= 1e-5, (p, e0, e1, e2)
 
 
-def test_fp64_normal_matrix_branch(F, dev):
+# k = 40: register row solve, estimate first; k = 150: tiled row solve, the estimate beside it on a second
+# stream and the flagged pairs solved again (pair 1 well conditioned, so only pairs 0 and 2 are redone)
+@pytest.mark.parametrize("k,d", [(40, 96), (150, 320)])
+def test_fp64_normal_matrix_branch(F, dev, k, d):
     """Pairs whose estimate exceeds the threshold factorise the rounded float64 product; the result stays
     within tolerance after refinement and the estimate reports the ill-conditioning."""
-    P, k, d = 2, 40, 96
+    P = 3
     A, B, ex, ey = _conditioned(23, P, k, d, 3000.0)   # cond(A A^T) ~ 9e6
+    A1, B1, _, _ = _conditioned(24, 1, k, d, 3.0)
+    A[1], B[1] = A1[0], B1[0]
     lam = np.full(P, 1e-4, np.float32)
     args = [T(A, dev), T(B, dev), T(ex, dev), T(ey, dev), T(lam, dev), 0, 0.5]
     C, _, info, cond = F.fmap_solve(*args, refine_steps=2, cond_fp64_threshold=1e6, want_cond=True)
     ref = _oracle_solve(A, B, ex, ey, lam, 0, 0.5)
-    assert (N(cond) > 1e6).all()
+    cond = N(cond)
+    assert cond[0] > 1e6 and cond[2] > 1e6 and cond[1] < 1e3, cond
+    assert (N(info) == 0).all()
     for p in range(P):
         assert rel_fro(N(C)[p], ref[p]["C"]) <= 1e-5, (p, rel_fro(N(C)[p], ref[p]["C"]))
 
