@@ -9,9 +9,9 @@
 //
 // The count is one streaming pass (5 bytes per vertex, HBM-bound).  Each wave
 // owns a contiguous run of rows of 256 vertices (four per lane, one 16-byte
-// score load and one 4-byte label load per lane, the next row in flight while
-// the current one is counted) and keeps per-lane counts for the shape it is
-// in; when it leaves a shape it adds the wave's counts to that shape's slot
+// score load and one 4-byte label load per lane, the rows loaded in chunks of
+// four with the next chunk in flight while one is counted) and keeps per-lane
+// counts for the shape it is in; when it leaves a shape it adds the wave's counts to that shape's slot
 // with 64-bit integer atomics, so the totals do not depend on the order in
 // which waves finish.  The shape of a wave's first vertex is found by a
 // 64-way parallel search over the offsets; later shapes by walking forward.
@@ -31,6 +31,7 @@ namespace {
 
 constexpr int OV_THREADS = 256;
 constexpr int OV_ROW = 256;  // vertices per wave row (4 per lane)
+constexpr int OV_DEPTH = 4;  // rows per load chunk (two chunks in flight per wave)
 
 // Largest s in [0, S) with off[s] <= v (off nondecreasing; clamps for any contents), found by the whole
 // wave: each round the 64 lanes test 64 evenly spaced candidates (one load each, all in flight together)
@@ -118,11 +119,10 @@ __global__ __launch_bounds__(OV_THREADS) void overlap_count_kernel(const float *
             c[q] = 0u;
         }
     };
-    float sc[4], sn[4];
-    uint32_t gt, gn;
-    load(row0, sc, gt);
-    for (int64_t row = row0; row < row1; ++row) {
-        if (row + 1 < row1) load(row + 1, sn, gn);  // next row in flight while this one is counted
+    // count one row (vertices base .. base + 255, 4 per lane): whole rows of the current shape on the fast
+    // path; a row that reaches past it vertex by vertex, walking the shapes forward (each lane to the shape
+    // of its vertex), then the current shape moves on
+    auto count_row = [&](int64_t row, const float (&sv)[4], uint32_t g) {
         const int64_t base = row * OV_ROW;
         const int64_t v0 = base + 4 * lane;
         const int64_t last = min(base + OV_ROW, total) - 1;
@@ -130,13 +130,11 @@ __global__ __launch_bounds__(OV_THREADS) void overlap_count_kernel(const float *
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 if (v0 + e <= last) {
-                    const bool pos = sc[e] > thr, t = ((gt >> (8 * e)) & 0xffu) != 0u;
+                    const bool pos = sv[e] > thr, t = ((g >> (8 * e)) & 0xffu) != 0u;
                     c[pos ? (t ? 0 : 1) : (t ? 2 : 3)] += 1u;
                 }
             }
         } else {
-            // the row reaches past the current shape: count it vertex by vertex, walking the shapes forward
-            // from the current one (each lane to the shape of its vertex), then move the current shape on
             flush();
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -145,7 +143,7 @@ __global__ __launch_bounds__(OV_THREADS) void overlap_count_kernel(const float *
                     int s = cur;
                     while (s + 1 < S && off[s + 1] <= v) ++s;
                     if (v >= off[s] && v < off[s + 1]) {
-                        const bool pos = sc[e] > thr, t = ((gt >> (8 * e)) & 0xffu) != 0u;
+                        const bool pos = sv[e] > thr, t = ((g >> (8 * e)) & 0xffu) != 0u;
                         atomicAdd(&counts[4 * (int64_t)s + (pos ? (t ? 0 : 1) : (t ? 2 : 3))], 1ull);
                     }
                 }
@@ -155,9 +153,26 @@ __global__ __launch_bounds__(OV_THREADS) void overlap_count_kernel(const float *
             cur_lo = off[cur];
             cur_hi = off[cur + 1];
         }
+    };
+    // rows in chunks of OV_DEPTH, the next chunk's loads in flight while one is counted (two register
+    // buffers alternating by unrolling; loads past the run re-read its last row and are not counted)
+    float sa[OV_DEPTH][4], sb[OV_DEPTH][4];
+    uint32_t ga[OV_DEPTH], gb[OV_DEPTH];
+    auto load_chunk = [&](int64_t r0, float (&sv)[OV_DEPTH][4], uint32_t (&g)[OV_DEPTH]) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) sc[e] = sn[e];
-        gt = gn;
+        for (int u = 0; u < OV_DEPTH; ++u) load(min(r0 + u, row1 - 1), sv[u], g[u]);
+    };
+    load_chunk(row0, sa, ga);
+    for (int64_t row = row0; row < row1; row += 2 * OV_DEPTH) {
+        load_chunk(row + OV_DEPTH, sb, gb);
+#pragma unroll
+        for (int u = 0; u < OV_DEPTH; ++u)
+            if (row + u < row1) count_row(row + u, sa[u], ga[u]);
+        if (row + OV_DEPTH >= row1) break;
+        load_chunk(row + 2 * OV_DEPTH, sa, ga);
+#pragma unroll
+        for (int u = 0; u < OV_DEPTH; ++u)
+            if (row + OV_DEPTH + u < row1) count_row(row + OV_DEPTH + u, sb[u], gb[u]);
     }
     flush();
 }

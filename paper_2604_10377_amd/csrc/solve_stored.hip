@@ -5,14 +5,16 @@
 //
 // With the factor known, a system is two triangular solves over k_x^2/2
 // stored floats, so the work is streaming the factor, once per substitution.
-// Large k_x: one wave per system; lane j holds rows j, j + 64, ... (NS slots).  The factor
-// is packed lower, column-major, so column c is contiguous: the forward
-// substitution L y = r goes column by column (y_c = r_c / L_cc, then the rows
-// below subtract L_qc y_c), the back substitution L^T x = y is a dot product
-// of column c with the finished x_q (q > c) and a wave reduction.  Columns
-// stream through registers in groups of 8, the next group loaded while the
-// current one is used (two buffers swapped by unrolling, unconditional loads
-// from clamped addresses, masking only where the values are used).
+// Large k_x: one wave per system; lane j holds rows j, j + 64, ... (NS slots).
+// The factor is packed lower, column-major, so column c is contiguous:
+//   * forward L y = r column by column (y_c = r_c / L_cc, then the rows below
+//     subtract L_qc y_c), with the slot and lane of c compile-time, so y_c and
+//     L_cc are single readlanes and each slot takes one fused multiply-add;
+//   * back substitution L^T x = y one slot of 64 columns at a time, lane c
+//     taking column c: the slots already solved contribute the dot product of
+//     the lane's own contiguous column segment with their x, and the 64 x 64
+//     diagonal block is solved column by column from the block's columns in
+//     the lanes' registers, so no step needs a cross-lane reduction.
 #include "fmap_device.h"
 #include "fmap_launch.h"
 
@@ -20,23 +22,11 @@ namespace fmap {
 
 namespace {
 
-constexpr int SG = 8;  // columns per prefetch group
-
 __device__ __forceinline__ int pcol(int c, int k) { return c * k - (c * (c - 1)) / 2; }
 
-// row c's value of a slotted vector (c wave-uniform): every slot is read at lane c % 64 and the
-// scalar results selected, so no register array is ever indexed by a runtime value
-template <int NS>
-__device__ __forceinline__ float row_value(const float (&v)[NS], int c)
+__device__ __forceinline__ float uniform_f(float v)
 {
-    const int l = c & 63, s = c >> 6;
-    float r = readlane(v[0], l);
-#pragma unroll
-    for (int t = 1; t < NS; ++t) {
-        const float x = readlane(v[t], l);
-        r = (s == t) ? x : r;
-    }
-    return r;
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
 }  // namespace
@@ -58,7 +48,6 @@ __global__ __launch_bounds__(256) void trisolve_stored_kernel(const float *__res
     const int p = sys / ky, i = sys - p * ky;
     if (only && __builtin_amdgcn_readfirstlane(only[p]) == 0) return;  // wave-uniform
     const float *Lp = Lin + (size_t)sys * (kx * (kx + 1) / 2);
-    const int ng = (kx + SG - 1) / SG;
 
     // every input load first (unconditional, clamped), then the validity of lambda and of the
     // resolvent normaliser (as in the forward solve)
@@ -93,87 +82,112 @@ __global__ __launch_bounds__(256) void trisolve_stored_kernel(const float *__res
 #pragma unroll
     for (int s = 0; s < NS; ++s) y[s] = j + 64 * s < kx ? y[s] : 0.f;
 
-    float ga[SG][NS], gb[SG][NS];
-    // group g of columns into buf: element (q, c) for the lane's rows.  Through a buffer descriptor the
-    // address is a lane offset of 4 q (fixed per slot) plus a scalar offset per column, with no vector
-    // address arithmetic; rows above the diagonal read other entries of the factor and rows past its
-    // end read 0 (the descriptor's range), and both are masked where the values are used
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void *)Lp, 0, (int)(kx * (kx + 1) / 2 * sizeof(float)), 0x00020000);
-    auto load_group = [&](int g, float (&buf)[SG][NS]) {
-#pragma unroll
-        for (int t = 0; t < SG; ++t) {
-            const int c = min(g * SG + t, kx - 1);
-            const int so = 4 * (pcol(c, kx) - c);
-#pragma unroll
-            for (int s = 0; s < NS; ++s)  // (the builtin returns the bits as an integer: reinterpreted)
-                buf[t][s] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * (j + 64 * s), so, 0));
-        }
+    // element (row, col) of the packed factor (row >= col) is at pcol(col) + row - col.  Through the buffer
+    // descriptor, reads past the factor's end return 0; reads of other entries (rows above the diagonal, rows
+    // past k_x) are finite and meet only zero or masked operands.
+    auto ldf = [&](int voff_floats, int soff_floats) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, 4 * voff_floats, 4 * soff_floats, 0));
     };
 
-    // forward substitution, columns ascending
-    auto fwd_group = [&](int g, const float (&buf)[SG][NS]) {
-#pragma unroll
-        for (int t = 0; t < SG; ++t) {
-            const int c = g * SG + t;
-            if (c < kx && fail == 0) {
-                const float dg = row_value<NS>(buf[t], c);
-                if (!(dg > 0.f) || !isfinite(dg)) {
-                    fail = c + 1;
-                } else {
-                    const float yc = row_value<NS>(y, c) * __builtin_amdgcn_rcpf(dg);
-#pragma unroll
-                    for (int s = 0; s < NS; ++s) {
-                        const int q = j + 64 * s;
-                        y[s] = (q == c) ? yc : ((q > c && q < kx) ? y[s] - buf[t][s] * yc : y[s]);
-                    }
-                }
-            }
-        }
-    };
-    // back substitution, columns descending: x_c = (y_c - sum_{q > c} L_qc x_q) / L_cc (x overwrites y)
-    auto bwd_group = [&](int g, const float (&buf)[SG][NS]) {
-#pragma unroll
-        for (int t = SG - 1; t >= 0; --t) {
-            const int c = g * SG + t;
-            if (c < kx) {
-                float part = 0.f;
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    const int q = j + 64 * s;
-                    part += (q > c && q < kx) ? buf[t][s] * y[s] : 0.f;
-                }
-                const float dot = wave_sum_uniform(part);
-                const float dg = row_value<NS>(buf[t], c);
-                const float xc = (row_value<NS>(y, c) - dot) * __builtin_amdgcn_rcpf(dg);
-#pragma unroll
-                for (int s = 0; s < NS; ++s) y[s] = (j + 64 * s == c) ? xc : y[s];
-            }
-        }
-    };
-
+    // ---- forward substitution L y = r, column by column: slot s and the lane of column c are compile-time, so
+    // y_c and L_cc are single readlanes, and the rows below c take one fused multiply-add per slot (the slot of
+    // c under a lane mask).  Columns come in groups of 8, the next group's loads in flight while one is used;
+    // a group loads only the slots at or below its own (the rows above the diagonal are never needed).
     if (fail == 0) {
-        load_group(0, ga);
-        for (int g = 0; g < ng; g += 2) {
-            load_group(min(g + 1, ng - 1), gb);
-            fwd_group(g, ga);
-            if (g + 1 >= ng) break;
-            load_group(min(g + 2, ng - 1), ga);
-            fwd_group(g + 1, gb);
+        float ba[8][NS], bb[8][NS];
+        auto load_group = [&](int q, float (&buf)[8][NS]) {  // q = 8 s + g, compile-time
+            const int s0 = q / 8;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int c = min(8 * q + t, kx - 1);
+                const int so = pcol(c, kx) - c;
+#pragma unroll
+                for (int sl = 0; sl < NS; ++sl)
+                    if (sl >= s0) buf[t][sl] = ldf(j + 64 * sl, so);
+            }
+        };
+        auto fwd_group = [&](int q, const float (&buf)[8][NS]) {
+            const int s0 = q / 8;
+            int lane = j;
+            asm volatile("" : "+v"(lane));  // masks formed per column, not hoisted into scalar registers
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int c = 8 * q + t, cl = c & 63;
+                const float dg = uniform_f(readlane(buf[t][s0], cl));
+                const bool act = c < kx && fail == 0;
+                const bool bad = !(dg > 0.f) || !isfinite(dg);
+                fail = (act && bad) ? c + 1 : fail;
+                const bool go = act && !bad;
+                const float yc = go ? uniform_f(readlane(y[s0], cl) * __builtin_amdgcn_rcpf(dg)) : 0.f;
+                y[s0] = (lane > cl) ? y[s0] - buf[t][s0] * yc : ((lane == cl && go) ? yc : y[s0]);
+#pragma unroll
+                for (int sl = 0; sl < NS; ++sl)
+                    if (sl > s0) y[sl] -= buf[t][sl] * yc;
+            }
+        };
+        constexpr int NQ = 8 * NS;
+        load_group(0, ba);
+#pragma unroll
+        for (int q = 0; q < NQ; q += 2) {
+            if (8 * q >= kx) break;
+            load_group(q + 1 < NQ ? q + 1 : q, bb);
+            fwd_group(q, ba);
+            if (8 * (q + 1) >= kx || q + 1 >= NQ) break;
+            load_group(q + 2 < NQ ? q + 2 : q + 1, ba);
+            fwd_group(q + 1, bb);
         }
         fail = __builtin_amdgcn_readfirstlane(fail);
     }
+
+    // ---- back substitution L^T x = y, 64 columns (one slot) at a time from the last, lane c taking column
+    // 64 s + c: the finished slots below contribute the dot product of the lane's own column segment (contiguous
+    // in the column-major factor) with their x, and the diagonal block is then solved column by column with the
+    // block's columns in the lanes' registers (L[64 s + r][64 s + c] in register r of lane c), so no step needs a
+    // cross-lane reduction.
+    float x[NS];
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) x[sl] = 0.f;
     if (fail == 0) {
-        const int g0 = ng - 1;
-        load_group(g0, ga);
-        for (int g = g0; g >= 0; g -= 2) {
-            load_group(max(g - 1, 0), gb);
-            bwd_group(g, ga);
-            if (g - 1 < 0) break;
-            load_group(max(g - 2, 0), ga);
-            bwd_group(g - 1, gb);
+#pragma unroll
+        for (int s0 = NS - 1; s0 >= 0; --s0) {
+            if (64 * s0 >= kx) continue;
+            const int col = 64 * s0 + j;
+            const int cb = pcol(min(col, kx - 1), kx) - min(col, kx - 1);  // factor offset of (row 0, this column)
+            const bool colok = col < kx;
+            float v = y[s0];
+#pragma unroll
+            for (int sl = NS - 1; sl > s0; --sl) {
+                if (64 * sl >= kx) continue;
+                // rows 64 sl .. 64 sl + 63 of this lane's column, 16 at a time (loads of a chunk issued first)
+#pragma unroll
+                for (int r0 = 0; r0 < 64; r0 += 16) {
+                    float lv[16];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) lv[r] = ldf(cb + r0 + r, 64 * sl);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) v -= lv[r] * uniform_f(readlane(x[sl], r0 + r));
+                }
+            }
+            float dl[64];
+#pragma unroll
+            for (int r = 0; r < 64; ++r) dl[r] = ldf(cb + r, 64 * s0);
+            int lane = j;
+            asm volatile("" : "+v"(lane));
+            float xs = 0.f;
+#pragma unroll
+            for (int c2 = 63; c2 >= 0; --c2) {
+                const bool act = 64 * s0 + c2 < kx;
+                const float xc = act ? uniform_f(readlane(v, c2) * __builtin_amdgcn_rcpf(readlane(dl[c2], c2))) : 0.f;
+                v = (lane < c2) ? v - dl[c2] * xc : v;
+                xs = (lane == c2) ? xc : xs;
+            }
+            x[s0] = colok ? xs : 0.f;
         }
     }
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) y[sl] = x[sl];
 
     const float muy = ey[(size_t)p * ky + i];
     float term = 0.f;
