@@ -100,6 +100,96 @@ __global__ __launch_bounds__(256) void gram64_kernel(const float *__restrict__ A
 }
 
 // ---------------------------------------------------------------------------
+// The same products on the float64 matrix cores (v_mfma_f64_16x16x4f64), for d % 8 == 0.  One wave per
+// 16 x 16 output tile: the lower-triangle tiles of the symmetric K64 (an off-diagonal tile is also
+// written mirrored) and every tile of R64.  Lane (i, q) feeds row i of its operands with columns
+// kb + 8 q + u to matrix step u of a 32-column batch, so each lane reads two 16-byte pieces per operand
+// and batch; the next batch is loaded while the current one is multiplied.  Workgroup ids are remapped
+// so that consecutive tiles, and so the tiles of one pair, share an XCD (ids in one residue class mod 8).
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void gram64_mfma_kernel(const float *__restrict__ A, const float *__restrict__ B,
+                                                          int kx, int ky, int d, int tkx, int tky, long long ntiles,
+                                                          int per_xcd, double *__restrict__ K64,
+                                                          double *__restrict__ R64)
+{
+    const int wid = blockIdx.x;
+    const long long lwg = (long long)(wid & 7) * per_xcd + (wid >> 3);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long g = lwg * 4 + wave;
+    if (g >= ntiles) return;  // no barriers below
+    const int ktiles = tkx * (tkx + 1) / 2, per_pair = ktiles + tky * tkx;
+    const int p = (int)(g / per_pair);
+    int t = (int)(g % per_pair);
+    int I, J, rowsX;
+    const float *X;
+    double *O;
+    const bool sym = t < ktiles;
+    if (sym) {  // t = I (I + 1) / 2 + J, J <= I
+        I = (int)((sqrtf(8.f * t + 1.f) - 1.f) * 0.5f);
+        while ((I + 1) * (I + 2) / 2 <= t) ++I;
+        while (I * (I + 1) / 2 > t) --I;
+        J = t - I * (I + 1) / 2;
+        X = A + (size_t)p * kx * d;
+        O = K64 + (size_t)p * kx * kx;
+        rowsX = kx;
+    } else {
+        t -= ktiles;
+        I = t / tkx;
+        J = t % tkx;
+        X = B + (size_t)p * ky * d;
+        O = R64 + (size_t)p * ky * kx;
+        rowsX = ky;
+    }
+    const int i16 = lane & 15, q = lane >> 4;
+    // rows past the matrix read a clamped row; they only reach outputs that are not stored
+    const float *xr = X + (size_t)min(I * 16 + i16, rowsX - 1) * d;
+    const float *yr = A + (size_t)p * kx * d + (size_t)min(J * 16 + i16, kx - 1) * d;
+    struct Batch {
+        f32x4 x0, x1, y0, y1;
+    };
+    auto load = [&](int kb) {
+        const int o = min(kb + 8 * q, d - 8);  // a batch past d reads in bounds and is masked
+        Batch b;
+        b.x0 = *reinterpret_cast<const f32x4 *>(xr + o);
+        b.x1 = *reinterpret_cast<const f32x4 *>(xr + o + 4);
+        b.y0 = *reinterpret_cast<const f32x4 *>(yr + o);
+        b.y1 = *reinterpret_cast<const f32x4 *>(yr + o + 4);
+        return b;
+    };
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    auto mma = [&](int kb, const Batch &b) {
+        const bool ok = kb + 8 * q < d;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float xv = u < 4 ? b.x0[u & 3] : b.x1[u & 3];
+            const float yv = u < 4 ? b.y0[u & 3] : b.y1[u & 3];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok ? (double)xv : 0.0, (double)yv, acc, 0, 0, 0);
+        }
+    };
+    const int nb = (((d + 31) / 32) + 1) & ~1;  // batches, rounded up to even for the two-buffer rotation
+    Batch b0 = load(0), b1;
+    for (int j = 0; j < nb; j += 2) {
+        const int kb = 32 * j;
+        b1 = load(kb + 32);
+        mma(kb, b0);
+        b0 = load(kb + 64);
+        mma(kb + 32, b1);
+    }
+    // acc[r] = D[q + 4 r][i16] (the float64 instruction's result layout)
+    const int col = J * 16 + i16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = I * 16 + q + 4 * r;
+        if (row < rowsX && col < kx) {
+            O[(size_t)row * kx + col] = acc[r];
+            if (sym && I != J) O[(size_t)col * kx + row] = acc[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // rho[p][i][j] = R64[i][j] - sum_q C[i][q] K64[q][j] - lambda D_ij C[i][j] for a
 // block of 16 rows of one pair (float64 arithmetic, result rounded to float32).
 // ---------------------------------------------------------------------------
@@ -446,7 +536,11 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
 #pragma unroll
                 for (int s = 0; s < CNS; ++s) x[s] = (lane + 64 * s == bj) ? 1.f : 0.f;
             }
-            // Higham's extra probe: b_i = (-1)^i (1 + i/(n-1)); estimate 2 ||K^{-1} b||_1 / (3n)
+            if (lane == 0) s_red[0] = e1;
+        } else if (wave == 1) {
+            // Higham's extra probe, beside the Hager sweeps: b_i = (-1)^i (1 + i/(n-1)); estimate
+            // 2 ||K^{-1} b||_1 / (3n)
+            float z[CNS];
 #pragma unroll
             for (int s = 0; s < CNS; ++s) {
                 const int r = lane + 64 * s;
@@ -457,10 +551,10 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
 #pragma unroll
             for (int s = 0; s < CNS; ++s) s2 += (lane + 64 * s < kx) ? fabsf(z[s]) : 0.f;
             s2 = wave_sum(s2) * 2.f / (3.f * kx);
-            if (lane == 0) s_red[0] = fmaxf(e1, s2) * knorm;
+            if (lane == 0) s_red[1] = s2;
         }
         __syncthreads();
-        est = s_red[0];
+        est = fmaxf(s_red[0], s_red[1]) * knorm;
     }
     if (tid == 0 && cond_est) cond_est[p] = est;
     // ill-conditioned pair: use the float64-formed products (rounded) for the row factorisations
@@ -483,6 +577,15 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
 void launch_gram64(const float *A, const float *B, int64_t P, int64_t kx, int64_t ky, int64_t d, double *K64,
                    double *R64, hipStream_t st)
 {
+    if (d >= 8 && d % 8 == 0 && ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0) {
+        const int tkx = (int)((kx + 15) / 16), tky = (int)((ky + 15) / 16);
+        const long long ntiles = P * (long long)(tkx * (tkx + 1) / 2 + tky * tkx);
+        const long long wgs = (ntiles + 3) / 4;
+        const int per_xcd = (int)((wgs + 7) / 8);
+        hipLaunchKernelGGL(gram64_mfma_kernel, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, st, A, B, (int)kx, (int)ky,
+                           (int)d, tkx, tky, ntiles, per_xcd, K64, R64);
+        return;
+    }
     const int tkx = (int)((kx + 31) / 32), tky = (int)((ky + 31) / 32);
     hipLaunchKernelGGL(gram64_kernel, dim3((unsigned)(P * (tkx * tkx + tky * tkx))), dim3(256), 0, st, A, B, (int)kx,
                        (int)ky, (int)d, tkx, tky, K64, R64);

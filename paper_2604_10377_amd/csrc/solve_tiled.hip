@@ -517,7 +517,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
 // memory / L2).  Out[p] (M x N, row-major) = sum over two K-segments s of
 // sign_s * X_s Y_s, where X_s is M x K_s read as stored ("N") or as the
 // transpose of a K_s x M row-major array ("T"), and Y_s is K_s x N row-major.
-// One wave per 32x32 output tile; loads are issued in batches of 8 steps.
+// One 4-wave workgroup per 32x32 output tile.  K is cut into batches of 16;
+// wave w takes batches w, w + 4, ... and keeps the next batch's loads in flight
+// while it multiplies the current one.  The four partial tiles are summed
+// through LDS in wave order.
 // ---------------------------------------------------------------------------
 struct GemmSeg {
     const float *X;
@@ -529,55 +532,89 @@ struct GemmSeg {
     float sign;
 };
 
-__global__ __launch_bounds__(256) void batched_gemm_kernel(GemmSeg s0, GemmSeg s1, int nseg, int M, int N,
-                                                           int tilesM, int tilesN, long long nwaves,
-                                                           float *__restrict__ Out, long long strideO)
+// X load modes: 0 every segment's X transposed; 1 one segment, X as stored with 16-byte aligned rows and
+// K % 8 == 0 (two 16-byte loads per lane and batch); 2 any segments and layouts.
+template <int XM>
+__device__ __forceinline__ void gemm_batch_load(const GemmSeg &sg, const float *X, const float *Y, int kb, int mc,
+                                                int nc, int half, float (&a)[8], float (&b)[8])
 {
+    // lane (m, half) supplies k = kb + 8 half + u to matrix step u; every address is clamped into the
+    // operand, and entries past K are masked when the operands are formed
+    if constexpr (XM == 1) {
+        const int k0 = min(kb + 8 * half, sg.K - 8);
+        const f32x4 *px = reinterpret_cast<const f32x4 *>(X + (size_t)mc * sg.ldx + k0);
+        const f32x4 v0 = px[0], v1 = px[1];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = v0[u];
+            a[4 + u] = v1[u];
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int kc = min(kb + 8 * half + u, sg.K - 1);
+            const bool tr = XM == 0 || sg.transX;
+            a[u] = X[tr ? (size_t)kc * sg.ldx + mc : (size_t)mc * sg.ldx + kc];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b[u] = Y[(size_t)min(kb + 8 * half + u, sg.K - 1) * sg.ldy + nc];
+}
+
+template <int XM>
+__global__ __launch_bounds__(256) void batched_gemm_kernel(GemmSeg s0, GemmSeg s1, int nseg, int M, int N,
+                                                           int tilesM, int tilesN, float *__restrict__ Out,
+                                                           long long strideO)
+{
+    __shared__ float red[4][16][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int half = lane >> 5, l32 = lane & 31;
     const int tiles = tilesM * tilesN;
-    const long long gtile = (long long)blockIdx.x * 4 + wave;
-    if (gtile >= nwaves) return;
-    const int p = (int)(gtile / tiles);
-    const int t = (int)(gtile % tiles);
+    const int p = blockIdx.x / tiles;
+    const int t = blockIdx.x % tiles;
     const int I = t / tilesN, Jt = t % tilesN;
     const int m = I * 32 + l32, n = Jt * 32 + l32;
     const bool mok = m < M, nok = n < N;
+    const int mc = min(m, M - 1), nc = min(n, N - 1);
+    auto keep = [](float x, bool ok) { return __uint_as_float(__float_as_uint(x) & (ok ? ~0u : 0u)); };
     f32x16 acc = zero16();
     for (int sgi = 0; sgi < nseg; ++sgi) {
         const GemmSeg &sg = sgi == 0 ? s0 : s1;
         const float *X = sg.X + (long long)p * sg.strideX;
         const float *Y = sg.Y + (long long)p * sg.strideY;
-        // every load unconditional, from addresses clamped into the operands, and masked by a bit mask
-        // afterwards: a load under a condition was compiled as a branch with a wait of its own, and the
-        // batch's loads then went out one at a time
-        const int mc = min(m, M - 1), nc = min(n, N - 1);
-        auto keep = [](float x, bool ok) { return __uint_as_float(__float_as_uint(x) & (ok ? ~0u : 0u)); };
-        for (int k0 = 0; k0 < sg.K; k0 += 16) {
-            float a[8], b[8];
+        const float sign = sg.sign;
+        const int K = sg.K;
+        // this wave's batches j = 0 .. nb - 1 start at k = 16 (wave + 4 j); nb rounded up to even for the
+        // two-buffer rotation (a batch past K is all masked)
+        const int nbat = (K + 15) / 16;
+        const int nb = (((nbat - wave + 3) / 4) + 1) & ~1;
+        auto mma = [&](int kb, const float (&a)[8], const float (&b)[8]) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int kk = k0 + 2 * u + half;
-                const int kc = min(kk, sg.K - 1);
-                const size_t xo = sg.transX ? (size_t)kc * sg.ldx + mc : (size_t)mc * sg.ldx + kc;
-                a[u] = X[xo];
-                b[u] = Y[(size_t)kc * sg.ldy + nc];
+                const bool kok = kb + 8 * half + u < K;
+                acc = mfma32x32x2(keep(sign * a[u], mok && kok), keep(b[u], nok && kok), acc);
             }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const bool kok = k0 + 2 * u + half < sg.K;
-                a[u] = keep(sg.sign * a[u], mok && kok);
-                b[u] = keep(b[u], nok && kok);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc = mfma32x32x2(a[u], b[u], acc);
+        };
+        float a0[8], b0[8], a1[8], b1[8];
+        gemm_batch_load<XM>(sg, X, Y, 16 * wave, mc, nc, half, a0, b0);
+        for (int j = 0; j < nb; j += 2) {
+            const int kb = 16 * (wave + 4 * j);
+            gemm_batch_load<XM>(sg, X, Y, kb + 64, mc, nc, half, a1, b1);
+            mma(kb, a0, b0);
+            gemm_batch_load<XM>(sg, X, Y, kb + 128, mc, nc, half, a0, b0);
+            mma(kb + 64, a1, b1);
         }
     }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[r];
+    __syncthreads();
     float *O = Out + (long long)p * strideO;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int rr = 0; rr < 4; ++rr) {
+        const int r = 4 * wave + rr;
+        const float v = ((red[0][r][lane] + red[1][r][lane]) + red[2][r][lane]) + red[3][r][lane];
         const int row = I * 32 + acc32_row(r, lane);
-        if (row < M && nok) O[(size_t)row * N + n] = acc[r];
+        if (row < M && nok) O[(size_t)row * N + n] = v;
     }
 }
 
@@ -680,12 +717,23 @@ static void gemm(const GemmSeg &s0, const GemmSeg *s1, int64_t P, int M, int N, 
                  hipStream_t st)
 {
     const int tM = (M + 31) / 32, tN = (N + 31) / 32;
-    const long long waves = (long long)P * tM * tN;
-    const unsigned grid = (unsigned)((waves + 3) / 4);
+    const unsigned grid = (unsigned)(P * tM * tN);
     GemmSeg z = s0;
     z.K = 0;
-    hipLaunchKernelGGL(batched_gemm_kernel, dim3(grid), dim3(256), 0, st, s0, s1 ? *s1 : z, s1 ? 2 : 1, M, N, tM, tN,
-                       waves, Out, strideO);
+    const int nseg = s1 ? 2 : 1;
+    const GemmSeg &t1 = s1 ? *s1 : z;
+    auto aligned = [](const GemmSeg &g) {
+        return g.ldx % 4 == 0 && g.strideX % 4 == 0 && g.K >= 8 && g.K % 8 == 0 && ((uintptr_t)g.X & 15) == 0;
+    };
+    if (s0.transX && (!s1 || s1->transX))
+        hipLaunchKernelGGL(batched_gemm_kernel<0>, dim3(grid), dim3(256), 0, st, s0, t1, nseg, M, N, tM, tN, Out,
+                           strideO);
+    else if (!s1 && !s0.transX && aligned(s0))
+        hipLaunchKernelGGL(batched_gemm_kernel<1>, dim3(grid), dim3(256), 0, st, s0, t1, nseg, M, N, tM, tN, Out,
+                           strideO);
+    else
+        hipLaunchKernelGGL(batched_gemm_kernel<2>, dim3(grid), dim3(256), 0, st, s0, t1, nseg, M, N, tM, tN, Out,
+                           strideO);
 }
 
 // W = V^T C + C^T V (into Wbuf), dB = V A, dA = V^T B - W A.
