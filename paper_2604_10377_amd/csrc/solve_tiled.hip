@@ -270,80 +270,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
             const int l32 = lane & 31, half = lane >> 5;
             const int nt = TR - ps;                 // tiles of the block column
             const int kxl = min(32, kx - 32 * ps);  // columns of this block
-            // ---- 1. block column ps ---------------------------------------------------------------
-            if ((kx & 3) == 0) {
-                // 16-byte pieces (rows of K and the right-hand side start 16-byte aligned), a thread's pieces
-                // in groups of four in flight together
-                constexpr int G = 4;
-                for (int e0 = tid; e0 < nt * 256; e0 += G * 256) {
-                f32x4 v[G];
-#pragma unroll
-                for (int u = 0; u < G; ++u) {
-                    const int e = min(e0 + 256 * u, nt * 256 - 1);  // piece: tile e >> 8, row (e >> 3) & 31, 4 columns
-                    const int row = min(32 * (ps + (e >> 8)) + ((e >> 3) & 31), kx);
-                    const int col = min(32 * ps + 4 * (e & 7), kx - 4);
-                    v[u] = ldg4(row == kx ? rp + col : Kp + (size_t)row * kx + col);
-                }
-#pragma unroll
-                for (int u = 0; u < G; ++u) {
-                    const int e = e0 + 256 * u;
-                    if (e < nt * 256) {
-                        const int j = e >> 8, r = (e >> 3) & 31, c0 = 4 * (e & 7);
-                        const int row = 32 * (ps + j) + r;
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            const int col = 32 * ps + c0 + t;
-                            float x = 0.f;
-                            if (row < kx && col < kx) x = v[u][t] + (row == col ? lsh * s_dval[row] : 0.f);
-                            else if (row == kx && col < kx) x = v[u][t];
-                            bc[j * TSZ + r * TLD + c0 + t] = x;
-                        }
-                    }
-                }
-                }
-            } else {
-                // groups of 8 unconditional loads from clamped addresses
-                for (int e0 = tid; e0 < nt * 1024; e0 += 8 * 256) {
-                    float v[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int e = min(e0 + 256 * u, nt * 1024 - 1);
-                        const int j = e >> 10, r = (e >> 5) & 31, c = e & 31;
-                        const int row = min(32 * (ps + j) + r, kx), col = min(32 * ps + c, kx - 1);
-                        v[u] = row == kx ? rp[col] : Kp[(size_t)row * kx + col];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int e = e0 + 256 * u;
-                        if (e < nt * 1024) {
-                            const int j = e >> 10, r = (e >> 5) & 31, c = e & 31;
-                            const int row = 32 * (ps + j) + r, col = 32 * ps + c;
-                            float x = 0.f;
-                            if (row < kx && col < kx) x = v[u] + (row == col ? lsh * s_dval[row] : 0.f);
-                            else if (row == kx && col < kx) x = v[u];
-                            bc[j * TSZ + r * TLD + c] = x;
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            // ---- 2. S_Ip -= sum_{q < ps} L_Iq L_pq^T -------------------------------------------
-            // The diagonal-tile wave updates the diagonal tile alone and goes straight on to factorise it
-            // (step 3, its own LDS writes, no barrier), while the other waves update the tiles below it.
-            if (ps > 0) {
+            // ---- 1. block column ps: S_Ip = K_Ip (+ the shift on the diagonal; row k_x is the right-hand
+            //         side, rows and columns past it are zero), minus sum_{q < ps} L_Iq L_pq^T ------------
+            // Each wave loads its own tiles straight into its accumulators (no barrier between the loads and
+            // the update).  The diagonal-tile wave takes the diagonal tile alone and goes straight on to
+            // factorise it (step 3, its own LDS writes, no barrier), while the other waves take the tiles
+            // below it.
+            {
                 const int j0 = wave == dwave ? 0 : 1 + (wave - dwave + LLW - 1) % LLW;
                 const int jstep = wave == dwave ? nt : LLW - 1;
                 for (int j = j0; j < nt; j += jstep) {
+                    // lane-derived values formed per tile (kept out of the registers held across the update)
+                    int ln = lane;
+                    asm volatile("" : "+v"(ln));
+                    const int l32 = ln & 31, half = ln >> 5;
+                    const int col = 32 * ps + l32;
+                    const int colc = min(col, kx - 1);
                     float *X = bc + j * TSZ;
-                    f32x16 acc;
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) acc[r] = X[acc32_row(r, lane) * TLD + l32];
                     const int I = ps + j;
                     const int off = l32 * 32 + 16 * half;
-                    // whole tile pairs (16 floats of each operand per lane), the next pair in flight while one is
-                    // multiplied
+                    // this tile's entries of K (unconditional loads from clamped addresses) and the first
+                    // tile pair of the update, all in flight together
+                    f32x16 acc;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int rowc = min(32 * I + acc32_row(r, ln), kx);
+                        acc[r] = *(rowc == kx ? rp + colc : Kp + (size_t)rowc * kx + colc);
+                    }
                     f32x4 a0[4], b0[4];
-                    {
+                    if (ps > 0) {
                         const float *ap = Ls + (size_t)tile_index(I, 0, TR) * LTS + off;
                         const float *bp = Ls + (size_t)tile_index(ps, 0, TR) * LTS + off;
 #pragma unroll
@@ -352,6 +307,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
                             b0[u] = ldg4(bp + 4 * u);
                         }
                     }
+                    const float dsh = lsh * s_dval[col];  // the shift of this column's diagonal entry
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int row = 32 * I + acc32_row(r, ln);
+                        const float v = acc[r];
+                        float x = 0.f;
+                        if (row < kx && col < kx) x = v + (row == col ? dsh : 0.f);
+                        else if (row == kx && col < kx) x = v;
+                        acc[r] = x;
+                    }
+                    // whole tile pairs (16 floats of each operand per lane), the next pair in flight while one is
+                    // multiplied
                     for (int q = 0; q < ps; ++q) {
                         const int qn = min(q + 1, ps - 1);
                         const float *ap = Ls + (size_t)tile_index(I, qn, TR) * LTS + off;
@@ -373,7 +340,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
                         }
                     }
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) X[acc32_row(r, lane) * TLD + l32] = acc[r];
+                    for (int r = 0; r < 16; ++r) X[acc32_row(r, ln) * TLD + l32] = acc[r];
                 }
             }
             // ---- 3. diagonal tile and its inverse (one wave) ----------------------------------
@@ -442,6 +409,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
         // c_p = L_pp^{-T} y_p from LDS, then y_q -= L_pq^T c_p for every q < p, wave w taking q = w, w + 4, ...
         // with the tiles' loads issued before c_p is formed.
         if (fail == 0) {
+            // lane values formed here, from an opaque thread index (not held from the kernel's start)
+            int tb = threadIdx.x;
+            asm volatile("" : "+v"(tb));
+            const int tid = tb, lane = tb & 63;
+            const int l32 = lane & 31, half = lane >> 5;
             for (int e0 = tid; e0 < T * 1024; e0 += 8 * 256) {
                 float v[8];
 #pragma unroll
@@ -518,8 +490,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
 // sign_s * X_s Y_s, where X_s is M x K_s read as stored ("N") or as the
 // transpose of a K_s x M row-major array ("T"), and Y_s is K_s x N row-major.
 // One 4-wave workgroup per 32x32 output tile.  K is cut into batches of 16;
-// wave w takes batches w, w + 4, ... and keeps the next batch's loads in flight
-// while it multiplies the current one.  The four partial tiles are summed
+// wave w takes batches w, w + 4, ... of each segment and keeps the loads of the
+// next three batches in flight while it multiplies the current one.  The four partial tiles are summed
 // through LDS in wave order.
 // ---------------------------------------------------------------------------
 struct GemmSeg {
@@ -534,31 +506,37 @@ struct GemmSeg {
 
 // X load modes: 0 every segment's X transposed; 1 one segment, X as stored with 16-byte aligned rows and
 // K % 8 == 0 (two 16-byte loads per lane and batch); 2 any segments and layouts.
+struct GemmBatch {
+    float a[8], b[8];
+};
+
 template <int XM>
-__device__ __forceinline__ void gemm_batch_load(const GemmSeg &sg, const float *X, const float *Y, int kb, int mc,
-                                                int nc, int half, float (&a)[8], float (&b)[8])
+__device__ __forceinline__ GemmBatch gemm_batch_load(const float *X, const float *Y, int K, int ldx, int ldy,
+                                                     bool transX, int kb, int mc, int nc, int half)
 {
     // lane (m, half) supplies k = kb + 8 half + u to matrix step u; every address is clamped into the
     // operand, and entries past K are masked when the operands are formed
+    GemmBatch g;
     if constexpr (XM == 1) {
-        const int k0 = min(kb + 8 * half, sg.K - 8);
-        const f32x4 *px = reinterpret_cast<const f32x4 *>(X + (size_t)mc * sg.ldx + k0);
+        const int k0 = min(kb + 8 * half, K - 8);
+        const f32x4 *px = reinterpret_cast<const f32x4 *>(X + (size_t)mc * ldx + k0);
         const f32x4 v0 = px[0], v1 = px[1];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            a[u] = v0[u];
-            a[4 + u] = v1[u];
+            g.a[u] = v0[u];
+            g.a[4 + u] = v1[u];
         }
     } else {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int kc = min(kb + 8 * half + u, sg.K - 1);
-            const bool tr = XM == 0 || sg.transX;
-            a[u] = X[tr ? (size_t)kc * sg.ldx + mc : (size_t)mc * sg.ldx + kc];
+            const int kc = min(kb + 8 * half + u, K - 1);
+            const bool tr = XM == 0 || transX;
+            g.a[u] = X[tr ? (size_t)kc * ldx + mc : (size_t)mc * ldx + kc];
         }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) b[u] = Y[(size_t)min(kb + 8 * half + u, sg.K - 1) * sg.ldy + nc];
+    for (int u = 0; u < 8; ++u) g.b[u] = Y[(size_t)min(kb + 8 * half + u, K - 1) * ldy + nc];
+    return g;
 }
 
 template <int XM>
@@ -577,33 +555,43 @@ __global__ __launch_bounds__(256) void batched_gemm_kernel(GemmSeg s0, GemmSeg s
     const bool mok = m < M, nok = n < N;
     const int mc = min(m, M - 1), nc = min(n, N - 1);
     auto keep = [](float x, bool ok) { return __uint_as_float(__float_as_uint(x) & (ok ? ~0u : 0u)); };
+    // this wave's steps: the batches of 16 k starting at 16 (wave + 4 j) of segment 0, then those of
+    // segment 1; their count is rounded up to a multiple of 4 for the four-buffer rotation (a step past
+    // the last is masked to zero)
+    const int nb0 = max(0, ((s0.K + 15) / 16 - wave + 3) / 4);
+    const int nb1 = nseg > 1 ? max(0, ((s1.K + 15) / 16 - wave + 3) / 4) : 0;
+    const int nsteps = (nb0 + nb1 + 3) & ~3;
+    const float *X0 = s0.X + (long long)p * s0.strideX, *Y0 = s0.Y + (long long)p * s0.strideY;
+    const float *X1 = s1.X + (long long)p * s1.strideX, *Y1 = s1.Y + (long long)p * s1.strideY;
+    auto load = [&](int st) {
+        const bool first = st < nb0 || nseg == 1;
+        const int kb = 16 * (wave + 4 * (first ? st : st - nb0));
+        return first ? gemm_batch_load<XM>(X0, Y0, s0.K, s0.ldx, s0.ldy, s0.transX, kb, mc, nc, half)
+                     : gemm_batch_load<XM>(X1, Y1, s1.K, s1.ldx, s1.ldy, s1.transX, kb, mc, nc, half);
+    };
     f32x16 acc = zero16();
-    for (int sgi = 0; sgi < nseg; ++sgi) {
-        const GemmSeg &sg = sgi == 0 ? s0 : s1;
-        const float *X = sg.X + (long long)p * sg.strideX;
-        const float *Y = sg.Y + (long long)p * sg.strideY;
-        const float sign = sg.sign;
-        const int K = sg.K;
-        // this wave's batches j = 0 .. nb - 1 start at k = 16 (wave + 4 j); nb rounded up to even for the
-        // two-buffer rotation (a batch past K is all masked)
-        const int nbat = (K + 15) / 16;
-        const int nb = (((nbat - wave + 3) / 4) + 1) & ~1;
-        auto mma = [&](int kb, const float (&a)[8], const float (&b)[8]) {
+    auto mma = [&](int st, const GemmBatch &g) {
+        const bool first = st < nb0 || nseg == 1;
+        const int kb = 16 * (wave + 4 * (first ? st : st - nb0));
+        const int K = first ? s0.K : s1.K;
+        const float sign = first ? s0.sign : s1.sign;
+        const bool live = st < nb0 + nb1;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const bool kok = kb + 8 * half + u < K;
-                acc = mfma32x32x2(keep(sign * a[u], mok && kok), keep(b[u], nok && kok), acc);
-            }
-        };
-        float a0[8], b0[8], a1[8], b1[8];
-        gemm_batch_load<XM>(sg, X, Y, 16 * wave, mc, nc, half, a0, b0);
-        for (int j = 0; j < nb; j += 2) {
-            const int kb = 16 * (wave + 4 * j);
-            gemm_batch_load<XM>(sg, X, Y, kb + 64, mc, nc, half, a1, b1);
-            mma(kb, a0, b0);
-            gemm_batch_load<XM>(sg, X, Y, kb + 128, mc, nc, half, a0, b0);
-            mma(kb + 64, a1, b1);
+        for (int u = 0; u < 8; ++u) {
+            const bool kok = live && kb + 8 * half + u < K;
+            acc = mfma32x32x2(keep(sign * g.a[u], mok && kok), keep(g.b[u], nok && kok), acc);
         }
+    };
+    GemmBatch g0 = load(0), g1 = load(1), g2 = load(2), g3;
+    for (int st = 0; st < nsteps; st += 4) {
+        g3 = load(st + 3);
+        mma(st, g0);
+        g0 = load(st + 4);
+        mma(st + 1, g1);
+        g1 = load(st + 5);
+        mma(st + 2, g2);
+        g2 = load(st + 6);
+        mma(st + 3, g3);
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[r];
