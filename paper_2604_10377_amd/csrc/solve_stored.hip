@@ -156,23 +156,43 @@ __global__ __launch_bounds__(256) void trisolve_stored_kernel(const float *__res
             const int col = 64 * s0 + j;
             const int cb = pcol(min(col, kx - 1), kx) - min(col, kx - 1);  // factor offset of (row 0, this column)
             const bool colok = col < kx;
-            float v = y[s0];
-#pragma unroll
-            for (int sl = NS - 1; sl > s0; --sl) {
-                if (64 * sl >= kx) continue;
-                // rows 64 sl .. 64 sl + 63 of this lane's column, 16 at a time (loads of a chunk issued first)
-#pragma unroll
-                for (int r0 = 0; r0 < 64; r0 += 16) {
-                    float lv[16];
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) lv[r] = ldf(cb + r0 + r, 64 * sl);
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) v -= lv[r] * uniform_f(readlane(x[sl], r0 + r));
-                }
-            }
+            // the finished slots' rows 64 sl .. 64 sl + 63 of this lane's column in chunks of 16, slots from the
+            // last, the next chunk's loads in flight while one is used (every slot below NS holds rows:
+            // NS = ceil(k_x / 64)).  The diagonal block's column segment is loaded after them, except in the
+            // widest instance, where loading it first measured faster (k = 300: 0.350 against 0.376 ms per
+            // reverse-mode call; k = 200: 0.235 against 0.252 ms the other way round).
             float dl[64];
+            if constexpr (NS >= 5) {
 #pragma unroll
-            for (int r = 0; r < 64; ++r) dl[r] = ldf(cb + r, 64 * s0);
+                for (int r = 0; r < 64; ++r) dl[r] = ldf(cb + r, 64 * s0);
+            }
+            float v = y[s0];
+            constexpr int CH = 4;                // chunks of 16 rows per slot
+            const int nch = CH * (NS - 1 - s0);  // compile-time once s0 is unrolled
+            float la[16], lb[16];
+            auto load_chunk = [&](int c, float (&buf)[16]) {
+                const int sl = NS - 1 - c / CH, r0 = 16 * (c % CH);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) buf[r] = ldf(cb + r0 + r, 64 * sl);
+            };
+            auto use_chunk = [&](int c, const float (&buf)[16]) {
+                const int sl = NS - 1 - c / CH, r0 = 16 * (c % CH);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v -= buf[r] * uniform_f(readlane(x[sl], r0 + r));
+            };
+            if (nch > 0) load_chunk(0, la);
+#pragma unroll
+            for (int c = 0; c < nch; c += 2) {
+                if (c + 1 < nch) load_chunk(c + 1, lb);
+                use_chunk(c, la);
+                if (c + 1 >= nch) break;
+                if (c + 2 < nch) load_chunk(c + 2, la);
+                use_chunk(c + 1, lb);
+            }
+            if constexpr (NS < 5) {
+#pragma unroll
+                for (int r = 0; r < 64; ++r) dl[r] = ldf(cb + r, 64 * s0);
+            }
             int lane = j;
             asm volatile("" : "+v"(lane));
             float xs = 0.f;
