@@ -169,14 +169,15 @@ enum { RT_FWD = 0, RT_BWD_RECOMPUTE = 2 };
 // the lower-triangle order of the tile grid; the diagonal positions hold the
 // inverses).  Two to four systems then share a CU and hide each other's serial
 // diagonal steps.  Step p:
-//   1. block column p of S = K + lambda diag(D_i), with the right-hand side as
-//      the appended row, is loaded into LDS;
+//   1. each wave loads its own tiles of block column p of
+//      S = K + lambda diag(D_i) (the right-hand side as the appended row)
+//      straight into its accumulators, with no barrier before step 2;
 //   2. left-looking update S_Ip -= sum_{q < p} L_Iq L_pq^T on the float32
 //      matrix cores, the L tiles read from the slot straight into the operand
 //      registers: lane (m, h) supplies row m, columns 16 h .. 16 h + 15, with
 //      the K order of the matrix-core steps permuted alike for both operands.
 //      One wave updates the diagonal tile and goes on to step 3 at once, while
-//      the others update the tiles below it;
+//      the others update the tiles below it; the updated tiles go to LDS;
 //   3. that wave factorises the diagonal tile and forms its inverse
 //      (diag_factor_inverse);
 //   4. the panel L_Ip = S_Ip L_pp^{-T} on the matrix cores, stored to the slot.
