@@ -31,6 +31,10 @@ Two further oracles, in plain numpy float64, live in submodules:
   oracle.gradfeat    DiffusionNet spatial-gradient features, variants A and B,
                      and their reverse mode (Sec. 3.2); pins in
                      tests/test_oracle_pins_gradfeat.py
+  oracle.vectorized  the vectorized k^2 x k^2 solve with general (non-diagonal)
+                     commutativity operators (Sec. 3.1, the formulation the
+                     conclusion names for non-orthogonal bases); pins in
+                     tests/test_oracle_pins_vectorized.py
 """
 from __future__ import annotations
 
