@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--warmup-seconds", type=float, default=1.5,
                     help="untimed replays for this much wall time before the counted warm-up")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "plain", "mixed", "large", "ragged", "overlap", "gradfeat", "multires"])
+                    choices=["headline", "plain", "mixed", "large", "ragged", "overlap", "gradfeat", "multires",
+                             "vectorized"])
     ap.add_argument("--variant", default="A", choices=["A", "B"], help="gradient-feature variant (gradfeat)")
     ap.add_argument("--bwd", default=None, choices=["stored", "recompute"],
                     help="backward mode (default: recompute for the large workload, stored otherwise)")
@@ -702,6 +703,67 @@ def bench_gradfeat(args, F, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_vectorized(args, F, dev):
+    """The vectorized solve with general commutativity operators: 256 pairs, kx = ky = 16 (normal equations of
+    order n = 256 per pair), d = 256, lambda = 0.1, non-symmetric operators; one library call per step."""
+    import torch
+    from oracle import vectorized as vz
+    from paper_2604_10377_amd import synth
+    A, B, D1, D2, lam = synth.workload_vectorized()
+    P, kx, d = A.shape
+    ky = B.shape[1]
+    n = kx * ky
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    tA, tB, tD1, tD2, tl = t(A), t(B), t(D1), t(D2), t(lam)
+    ws = torch.empty(max(F.fmap_solve_vectorized_workspace_bytes(P, kx, ky, d), 256), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = [None]
+
+    def call():
+        out[0] = F.fmap_solve_vectorized(tA, tB, tD1, tD2, tl, workspace=ws)
+
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            call()
+        torch.cuda.synchronize()
+        print(f"profiled {args.profile_steps} vectorized-solve calls", flush=True)
+        return
+    ms, stats = timed_calls(call, args, stream)
+    # algorithmic work per pair: Cholesky n^3/3 and the two substitutions 2 n^2 (multiply-adds x 2), the
+    # products A A^T and B A^T 2 (kx^2 + ky kx) d; bytes: A, B, the operators, H written and read, C
+    flops = P * (2.0 * (n ** 3 / 3.0 + 2.0 * n * n) + 2.0 * (kx * kx + ky * kx) * d)
+    nbytes = P * 4.0 * ((kx + ky) * d + kx * kx + ky * ky + 2.0 * n * n + 2.0 * n)
+    roof = roofline_entry(flops, nbytes, ms * 1e-3, FP32_PEAK_TFLOPS)
+    roof["kernel"] = "whole call: normal products, vec_form_kernel, rowsolve_ll_kernel<10> (one system per pair)"
+    roof["traffic"] = None
+    call()
+    torch.cuda.synchronize()
+    C, info = out[0][0].cpu().numpy(), out[0][1].cpu().numpy()
+    assert (info == 0).all(), info
+    errs = [float(np.linalg.norm(C[p] - vz.solve(A[p], B[p], D1[p], D2[p], float(lam[p])))
+                  / np.linalg.norm(vz.solve(A[p], B[p], D1[p], D2[p], float(lam[p])))) for p in (0, P - 1)]
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0, done = time.perf_counter(), 0
+        while time.perf_counter() - t0 < min(args.cpu_seconds, 5.0):
+            vz.solve(A[done % P], B[done % P], D1[done % P], D2[done % P], float(lam[done % P]))
+            done += 1
+        el = time.perf_counter() - t0
+        cpu = {"value": round(done / el, 2), "unit": "solves/s", "cores": int(os.environ.get("OMP_NUM_THREADS", 0))
+               or len(os.sched_getaffinity(0)), "kind": "oracle",
+               "sample": f"{done} pairs of the same batch in {el:.1f} s, numpy float64 (Kronecker system + LU)",
+               "cpu_model": cpu_model()}
+    res = {"metric": f"vectorized-operator solves/sec (kx=ky={kx}, n={n}, d={d}, batch {P})",
+           "value": round(P / (ms * 1e-3), 1), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 5), "step_ms": stats, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"vectorized-k{kx}-d{d}", "pairs": P, "kx": kx, "ky": ky, "d": d,
+                      "lambda": float(lam[0]), "operators": "Q diag(mu) Q^-1, Q = I + 0.1 N"},
+           "roofline": roof, "cpu_baseline": cpu,
+           "accuracy_vs_oracle": {"C": float(f"{max(errs):.3e}"), "pairs": [0, P - 1]}}
+    print(json.dumps(res), flush=True)
+
+
 def bench_multires(args, F, dev):
     """One projection at k = 120 and maps at resolutions 30, 50, 80 and 120 (32 pairs, n = 5000, d = 256,
     Laplacian mask): the two library calls captured as one graph per input set, three sets rotated."""
@@ -956,6 +1018,8 @@ def main():
         return bench_overlap(args, F, dev)
     if args.workload == "gradfeat":
         return bench_gradfeat(args, F, dev)
+    if args.workload == "vectorized":
+        return bench_vectorized(args, F, dev)
     if args.workload == "multires":
         return bench_multires(args, F, dev)
     if args.bwd is None:

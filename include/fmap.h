@@ -191,6 +191,31 @@ fmap_status fmap_solve_resolutions(const float *A, const float *B, const float *
                                    void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Vectorized solve with general commutativity operators (Sec. 3.1: the        */
+/* k^2 x k^2 least-squares formulation that the row-wise solve avoids; the     */
+/* conclusion names it for non-orthogonal bases, where the operators are not   */
+/* diagonal).  Per pair p:                                                     */
+/*     C_p = argmin ||C A_p - B_p||_F^2 + lambda[p] ||C X_p - Y_p C||_F^2       */
+/* A [pairs][kx][d], B [pairs][ky][d], op_x = X [pairs][kx][kx] (source        */
+/* operator), op_y = Y [pairs][ky][ky] (target operator), lambda [pairs], all  */
+/* float32 row-major on the device; C [pairs][ky][kx] float32 out.  With       */
+/* c = vec(C) (c[i kx + j] = C[i][j]) it solves the normal equations H c = g   */
+/* of order n = kx ky by one float32 Cholesky factorisation per pair (H is     */
+/* formed in float32 from A A^T, B A^T and the operators).  With diagonal      */
+/* operators X = diag(evals_x), Y = diag(evals_y) the result is fmap_solve's   */
+/* with the Laplacian mask.  Supported: kx ky <= fmap_max_k() (the k^2 x k^2   */
+/* system is for small k), else FMAP_ERR_UNSUPPORTED.  info [pairs] int32 out: */
+/* 0; c + 1 if the pivot of vectorized index c = i kx + j is not positive     */
+/* (that pair's C is NaN); -1 for a negative or non-finite lambda.  workspace: */
+/* fmap_solve_vectorized_workspace_bytes(...) bytes (0 for invalid sizes).     */
+/* Forward only.                                                               */
+/* ------------------------------------------------------------------------ */
+size_t fmap_solve_vectorized_workspace_bytes(int64_t pairs, int64_t kx, int64_t ky, int64_t d);
+fmap_status fmap_solve_vectorized(const float *A, const float *B, const float *op_x, const float *op_y,
+                                  const float *lambda, int64_t pairs, int64_t kx, int64_t ky, int64_t d, float *C,
+                                  int32_t *info, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* DiffusionNet spatial-gradient features (Sec. 3.2), the step upstream of the  */
 /* projection.  Per vertex the D channels hold complex gradients z = x + i y,   */
 /* interleaved: z [vertices][channels][2] float (x_j, y_j).  With A_re, A_im    */

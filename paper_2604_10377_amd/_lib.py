@@ -38,6 +38,8 @@ SIGNATURES = {
     "fmap_project_pinv": (_i32, [_vp, _vp, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _sz, _vp]),
     "fmap_project_pinv_backward": (_i32, [_vp, _i32, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _sz, _vp]),
     "fmap_solve_resolutions_workspace_bytes": (_sz, [_i64, _i64, _i64, _i64, _i32, _vp, _vp]),
+    "fmap_solve_vectorized_workspace_bytes": (_sz, [_i64, _i64, _i64, _i64]),
+    "fmap_solve_vectorized": (_i32, [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _sz, _vp]),
     "fmap_solve_resolutions": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _f32, _i64, _i64, _i64, _i64, _i32, _vp, _vp,
                                       _vp, _vp, _vp, _sz, _vp]),
     "fmap_gradient_features": (_i32, [_vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp]),

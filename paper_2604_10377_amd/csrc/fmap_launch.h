@@ -120,6 +120,20 @@ void launch_adjoint_general(const float *V, const float *C, const float *A, cons
                             int64_t ky, int64_t d, float *Wbuf, const float *dlam_part, float *dlam, float *dA,
                             float *dB, hipStream_t st);
 
+// K = A A^T [P][kx][kx] and, with with_R, R = B A^T [P][ky][kx] in float32.
+void launch_gram(const float *A, const float *B, int64_t P, int64_t kx, int64_t ky, int64_t d, bool with_R,
+                 float *K, float *R, hipStream_t st);
+// One system per pair with a given symmetric matrix: S [P][n][n] (n <= kMaxK), right-hand side g [P][n],
+// solution out [P][n], info [P]; ex_zero [P][n] and ey_zero [P] must hold zeros (no mask shift is added) and
+// lam [P] only flags an invalid value.  tiles: tiled_workspace_bytes(P, n, 1) bytes when n > kSmallK.
+void launch_rowsolve_dense(const float *S, const float *g, const float *ex_zero, const float *ey_zero, const float *lam,
+                           int64_t P, int64_t n, float *out, int *info, float *tiles, hipStream_t st);
+// The vectorized solve with general commutativity operators (kx ky <= kMaxK).
+size_t vectorized_workspace_bytes(int64_t P, int64_t kx, int64_t ky);
+hipError_t launch_solve_vectorized(const float *A, const float *B, const float *D1, const float *D2, const float *lam,
+                                   int64_t P, int64_t kx, int64_t ky, int64_t d, float *C, int32_t *info, void *ws,
+                                   hipStream_t st);
+
 void launch_gram64(const float *A, const float *B, int64_t P, int64_t kx, int64_t ky, int64_t d, double *K64,
                    double *R64, hipStream_t st);
 void launch_residual64(const float *C, const double *K64, const double *R64, const float *ex, const float *ey,

@@ -550,7 +550,7 @@ SolveWs solve_workspace_layout(int64_t P, int64_t kx, int64_t ky, int64_t d)
     return w;
 }
 
-static void launch_gram(const float *A, const float *B, int64_t P, int64_t kx, int64_t ky, int64_t d, bool with_R,
+void launch_gram(const float *A, const float *B, int64_t P, int64_t kx, int64_t ky, int64_t d, bool with_R,
                         float *K, float *R, hipStream_t st)
 {
     const int tkx = (int)((kx + 31) / 32), tky = (int)((ky + 31) / 32);
@@ -630,6 +630,18 @@ static SideStream *side_stream(hipStream_t st)
         made[dev] = true;
     }
     return &per_dev[dev];
+}
+
+void launch_rowsolve_dense(const float *S, const float *g, const float *ex_zero, const float *ey_zero, const float *lam,
+                           int64_t P, int64_t n, float *out, int *info, float *tiles, hipStream_t st)
+{
+    // one system per pair (k_y = 1): the zero mask rows add no diagonal shift, lambda only gates validity
+    if (n <= kSmallK)
+        launch_rowsolve<RS_FWD>(S, g, ex_zero, ey_zero, lam, 0, 0.5f, P, n, 1, out, nullptr, info, nullptr, nullptr, st,
+                                1);
+    else
+        launch_rowsolve_tiled(RS_FWD, S, g, ex_zero, ey_zero, lam, 0, 0.5f, P, n, 1, out, nullptr, info, nullptr,
+                              nullptr, tiles, st);
 }
 
 hipError_t launch_solve(const float *A, const float *B, const float *ex, const float *ey, const float *lam,

@@ -81,6 +81,10 @@ def fmap_solve_workspace_bytes(pairs: int, kx: int, ky: int, d: int) -> int:
     return int(_lib.lib().fmap_solve_workspace_bytes(pairs, kx, ky, d))
 
 
+def fmap_solve_vectorized_workspace_bytes(pairs: int, kx: int, ky: int, d: int) -> int:
+    return int(_lib.lib().fmap_solve_vectorized_workspace_bytes(pairs, kx, ky, d))
+
+
 def fmap_factor_floats(kx: int, ky: int) -> int:
     return int(_lib.lib().fmap_factor_floats(kx, ky))
 
@@ -263,6 +267,29 @@ def fmap_solve_resolutions(A: torch.Tensor, B: torch.Tensor, evals_x: torch.Tens
         _ptr(A), _ptr(B), _ptr(evals_x), _ptr(evals_y), _ptr(lam), int(mask_kind), float(gamma), P, kx, ky, d, nres,
         kxs, kys, cptr, iptr, _ptr(workspace), _wsbytes(workspace), _stream(dev)))
     return list(zip(Cs, infos))
+
+
+def fmap_solve_vectorized(A: torch.Tensor, B: torch.Tensor, op_x: torch.Tensor, op_y: torch.Tensor,
+                          lam: torch.Tensor, *, workspace: Optional[torch.Tensor] = None):
+    """Vectorized solve with general commutativity operators (op_x [P, kx, kx], op_y [P, ky, ky]):
+    C = argmin ||C A - B||^2 + lam ||C op_x - op_y C||^2 per pair, kx * ky <= fmap_max_k().  Returns
+    (C [P, ky, kx], info [P])."""
+    dev = A.device
+    P, kx, d = A.shape
+    ky = B.shape[1]
+    _need(A, "A", torch.float32, (P, kx, d), dev)
+    _need(B, "B", torch.float32, (P, ky, d), dev)
+    _need(op_x, "op_x", torch.float32, (P, kx, kx), dev)
+    _need(op_y, "op_y", torch.float32, (P, ky, ky), dev)
+    _need(lam, "lam", torch.float32, (P,), dev)
+    C = torch.empty((P, ky, kx), dtype=torch.float32, device=dev)
+    info = torch.empty((P,), dtype=torch.int32, device=dev)
+    nbytes = fmap_solve_vectorized_workspace_bytes(P, kx, ky, d)
+    workspace = _workspace(nbytes, dev, workspace)
+    _lib.check("fmap_solve_vectorized", _lib.lib().fmap_solve_vectorized(
+        _ptr(A), _ptr(B), _ptr(op_x), _ptr(op_y), _ptr(lam), P, kx, ky, d, _ptr(C), _ptr(info), _ptr(workspace),
+        _wsbytes(workspace), _stream(dev)))
+    return C, info
 
 
 # ---------------------------------------------------------------------------- gradient features

@@ -335,3 +335,34 @@ def workload_gradfeat(vertices: int = 160_000, channels: int = 128, tag: int = 7
     A_re = rng.uniform(-s, s, (channels, channels)).astype(np.float32)
     A_im = rng.uniform(-s, s, (channels, channels)).astype(np.float32)
     return z, A_re, A_im
+
+
+def operator_nonorthogonal(rng: np.random.Generator, k: int, skew: float = 0.1) -> np.ndarray:
+    """A Laplacian-like operator expressed in a non-orthogonal basis: Q diag(mu) Q^{-1} with mu the sorted
+    eigenvalue draw of `eigenvalues_linear` and Q = I + skew N (N ~ N(0, 1/k)), i.e. real positive spectrum,
+    non-symmetric matrix, nearly diagonal for small skew."""
+    mu = eigenvalues_linear(rng, k)
+    Q = np.eye(k) + skew * rng.standard_normal((k, k)) / np.sqrt(k)
+    return (Q * mu) @ np.linalg.inv(Q)
+
+
+def workload_vectorized(pairs: int = 256, k: int = 16, d: int = 256, *, ky: Optional[int] = None, lam: float = 0.1,
+                        skew: float = 0.1, tag: int = 8):
+    """Inputs of the vectorized solve with general operators: A [P, kx, d] ~ N(0, 1/d) and B = C0 A + 0.05 E
+    with C0 ~ N(0, 1/kx) (a synthesized map plus noise), operators from `operator_nonorthogonal` for both sides,
+    lambda [P] = lam.  Float32, rounded once."""
+    kx = k
+    ky = k if ky is None else ky
+    A = np.empty((pairs, kx, d), np.float32)
+    B = np.empty((pairs, ky, d), np.float32)
+    D1 = np.empty((pairs, kx, kx), np.float32)
+    D2 = np.empty((pairs, ky, ky), np.float32)
+    for p in range(pairs):
+        rng = rng_for(tag, pairs, kx, ky, d, p)
+        a = rng.standard_normal((kx, d)) / np.sqrt(d)
+        c0 = rng.standard_normal((ky, kx)) / np.sqrt(kx)
+        A[p] = a
+        B[p] = c0 @ a + 0.05 * rng.standard_normal((ky, d)) / np.sqrt(d)
+        D1[p] = operator_nonorthogonal(rng, kx, skew)
+        D2[p] = operator_nonorthogonal(rng, ky, skew)
+    return A, B, D1, D2, np.full(pairs, lam, np.float32)
