@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void residual64_kernel(const float *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// Condition estimate of K = A A^T per pair (one 512-thread workgroup).
+// Condition estimate of K = A A^T per pair (one workgroup of 16 waves).
 //
 // ||K||_1 is the largest row sum of |K| (K is symmetric), summed along rows so
 // that the loads are coalesced.  The Cholesky factor of K is formed in LDS
@@ -282,6 +282,7 @@ constexpr int CPW = 8;                 // Cholesky panel width
 constexpr int CPAD = 32;
 
 constexpr int CG = 8;  // columns per group of the triangular solves
+constexpr int CWV = 16, CTH = 64 * CWV;  // waves and threads of the estimate's workgroup
 
 // x if ok, else +0, by a bit mask: the read that produced x stays unconditional (a select would let the
 // compiler put the read under a branch of its own)
@@ -382,7 +383,7 @@ __device__ __forceinline__ void chol_solve_regs(const float *L, const float *Din
     for (int s = 0; s < CNS; ++s) v[s] *= dinv[s];  // x
 }
 
-__global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, int kx, float threshold,
+__global__ __launch_bounds__(CTH) void cond_kernel(const float *__restrict__ K, int kx, float threshold,
                                                    const double *__restrict__ K64, const double *__restrict__ R64,
                                                    float *__restrict__ Kout, float *__restrict__ Rout, int ky,
                                                    float *__restrict__ cond_est, int *__restrict__ flag)
@@ -391,12 +392,12 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
     float *L = sm;                     // packed lower, kx(kx+1)/2
     float *Dinv = L + kx * (kx + 1) / 2;  // reciprocal pivots, kx
     float *Pn = sm + ((kx * (kx + 1) / 2 + kx + 3) & ~3);  // the current panel, row by row: [kx][8] (16-byte rows)
-    __shared__ float s_red[8];
+    __shared__ float s_red[CWV];
     __shared__ int s_fail;
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float *Kp = K + (size_t)p * kx * kx;
     batched_for<8>(
-        tid, kx * kx, 512, [&](int e) { return Kp[e]; },
+        tid, kx * kx, CTH, [&](int e) { return Kp[e]; },
         [&](int e, float v) {
             const int r = e / kx, c = e - r * kx;
             if (c <= r) L[pk(r, c)] = v;
@@ -404,13 +405,13 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
     if (tid == 0) s_fail = 0;
     {  // the alignment gap after Dinv and the padding after Pn are read (never used) by the solves' last groups
         const int gap0 = kx * (kx + 1) / 2 + kx, gap1 = (gap0 + 3) & ~3, pad0 = gap1 + CPW * kx;
-        for (int e = gap0 + tid; e < gap1; e += 512) sm[e] = 0.f;
-        for (int e = pad0 + tid; e < pad0 + CPAD; e += 512) sm[e] = 0.f;
+        for (int e = gap0 + tid; e < gap1; e += CTH) sm[e] = 0.f;
+        for (int e = pad0 + tid; e < pad0 + CPAD; e += CTH) sm[e] = 0.f;
     }
     __syncthreads();
     // ||K||_1 = max row sum of |K| (symmetric: the strict upper part of row r is column r of L), one wave per row
     float rmax = 0.f;
-    for (int r = wave; r < kx; r += 8) {
+    for (int r = wave; r < kx; r += CWV) {
         float s = 0.f;
         for (int c = lane; c < kx; c += 64) s += fabsf(c <= r ? L[pk(r, c)] : L[pk(c, r)]);
         rmax = fmaxf(rmax, wave_sum(s));
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
     if (lane == 0) s_red[wave] = rmax;
     __syncthreads();
     float knorm = s_red[0];
-    for (int w = 1; w < 8; ++w) knorm = fmaxf(knorm, s_red[w]);
+    for (int w = 1; w < CWV; ++w) knorm = fmaxf(knorm, s_red[w]);
     // Blocked right-looking Cholesky in LDS, panels of CPW columns.  Wave 0 factorises the panel in
     // registers (lane l holds rows c0 + l + 64 s of the panel's columns; the pivots and the panel's own
     // rows come by readlane) and writes it back, also row by row to Pn.  Then every wave updates the
@@ -474,7 +475,7 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
         __syncthreads();
         if (s_fail) break;  // uniform
         const int m0 = c0 + CPW;  // panel columns past k_x are zero (clamped rows, masked below)
-        for (int r = m0 + wave; r < kx; r += 8) {
+        for (int r = m0 + wave; r < kx; r += CWV) {
             const f32x4 pa = *reinterpret_cast<const f32x4 *>(&Pn[r * CPW]);
             const f32x4 pb = *reinterpret_cast<const f32x4 *>(&Pn[r * CPW + 4]);
             float *Lr = L + r * (r + 1) / 2;  // row r
@@ -492,7 +493,7 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
         __syncthreads();
     }
     __syncthreads();
-    for (int c = tid; c < kx; c += 512) Dinv[c] = 1.f / L[pk(c, c)];
+    for (int c = tid; c < kx; c += CTH) Dinv[c] = 1.f / L[pk(c, c)];
     __syncthreads();
     float est = INFINITY;
     if (s_fail == 0) {
@@ -562,10 +563,10 @@ __global__ __launch_bounds__(512) void cond_kernel(const float *__restrict__ K, 
     if (tid == 0 && flag) flag[p] = replace ? 1 : 0;
     if (replace) {
         batched_for<8>(
-            tid, kx * kx, 512, [&](int e) { return K64[(size_t)p * kx * kx + e]; },
+            tid, kx * kx, CTH, [&](int e) { return K64[(size_t)p * kx * kx + e]; },
             [&](int e, double v) { Kout[(size_t)p * kx * kx + e] = (float)v; });
         batched_for<8>(
-            tid, ky * kx, 512, [&](int e) { return R64[(size_t)p * ky * kx + e]; },
+            tid, ky * kx, CTH, [&](int e) { return R64[(size_t)p * ky * kx + e]; },
             [&](int e, double v) { Rout[(size_t)p * ky * kx + e] = (float)v; });
     }
 }
@@ -617,7 +618,7 @@ void launch_cond(const float *K, int64_t P, int64_t kx, int64_t ky, float thresh
                                         sizeof(float)));
         attr = true;
     }
-    hipLaunchKernelGGL(cond_kernel, dim3((unsigned)P), dim3(512), lds, st, K, (int)kx, threshold, K64, R64, Kout, Rout,
+    hipLaunchKernelGGL(cond_kernel, dim3((unsigned)P), dim3(CTH), lds, st, K, (int)kx, threshold, K64, R64, Kout, Rout,
                        (int)ky, cond_est, flag);
 }
 
