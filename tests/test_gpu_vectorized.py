@@ -37,11 +37,13 @@ def rel_fro(x, r):
 
 # (P, kx, ky, d, lam, skew): n = kx ky spans the register solve's widths (25, 56, 64) and the tiled instances
 # (81 and 120: 4 tile rows; 196: 7; 256, 300, 306, 315 and 319: 10), with d close to kx in one case (A A^T less
-# well conditioned); kx or ky above 32 (35 x 9, 3 x 100) forms H without the LDS staging
+# well conditioned); kx or ky above 32 (35 x 9, 3 x 100) forms H without the LDS staging; the 1 x 1 map and
+# one-sided maps (kx = 1 or ky = 1)
 CASES = [(3, 5, 5, 32, 0.5, 0.3), (2, 7, 8, 40, 1.0, 0.3), (2, 8, 8, 64, 2.0, 0.3), (2, 9, 9, 64, 0.5, 0.3),
          (2, 4, 30, 40, 1.0, 0.3), (2, 14, 14, 96, 0.5, 0.3), (2, 16, 16, 128, 1.0, 0.3),
          (1, 17, 18, 128, 0.5, 0.3), (2, 29, 11, 64, 1.0, 0.3), (2, 12, 10, 14, 0.2, 0.2),
-         (2, 35, 9, 64, 0.5, 0.3), (1, 3, 100, 128, 0.5, 0.3)]
+         (2, 35, 9, 64, 0.5, 0.3), (1, 3, 100, 128, 0.5, 0.3),
+         (1, 1, 1, 8, 0.5, 0.3), (2, 1, 40, 16, 1.0, 0.3), (2, 40, 1, 64, 1.0, 0.3)]
 
 
 @pytest.mark.parametrize("P,kx,ky,d,lam,skew", CASES)
