@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void vec_form_kernel(const float *__restrict__
 // in LDS (rows padded to 33 floats), forms D1 D1^T and D2^T D2 there once (the dot products in the order of
 // the kernel above), and writes each row of H with consecutive threads on consecutive columns.  Every entry
 // follows the same formula, in the same order, as in the kernel above.
-constexpr int VF_KM = 32, VF_LD = 33, VF_ROWS = 8;
+constexpr int VF_KM = 32, VF_LD = 33, VF_ROWS = 32;
 
 __global__ __launch_bounds__(256) void vec_form_lds_kernel(const float *__restrict__ K, const float *__restrict__ R,
                                                            const float *__restrict__ D1, const float *__restrict__ D2,
