@@ -711,24 +711,57 @@ __device__ __forceinline__ void bwdk_block(const float *__restrict__ P, const fl
                     }
         }
         if (ks == KS - 1) {  // the tile is complete: register r of lane (m16, g4) is column 4 g4 + r of tile mt
+            if (vec) {
+                // whole 128-byte lines: the accumulators are exchanged across lanes (ds_bpermute, no LDS
+                // allocation) so that one store covers 8 vertices x 32 columns, lane L taking vertex L / 8
+                // (+ 8 i) and columns 4 (L % 8) .. + 3 of the half block hh; the values and the mass product
+                // are those of the lane that computed them
+                const int c4 = lane & 7;
+                const bool upper = (c4 >> 2) != 0;  // tile 2 hh + 1
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                const int v = vt * BB_VT + wave * 32 + nt * 16 + m16;
-                float *row = O + (size_t)min(v, n - 1) * d;
+                for (int nt = 0; nt < 2; ++nt) {
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt) {
-                    const int col = dbase + mt * 16 + 4 * g4;
-                    const f32x4 val = acc[mt][nt] * b.m[nt];
-                    if (vec) {
-                        if (v < n && col < d) stream_store(reinterpret_cast<f32x4 *>(row + col), val);
-                    } else {
+                    for (int i = 0; i < 2; ++i) {
+                        const int vr = 8 * i + (lane >> 3);  // vertex within the 16 of nt
+                        const int src = 4 * (vr + 16 * (c4 & 3));
+                        const int v = vt * BB_VT + wave * 32 + nt * 16 + vr;
+                        const float m = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(b.m[nt])));
+                        float *row = O + (size_t)min(v, n - 1) * d;
+#pragma unroll
+                        for (int hh = 0; hh < 2; ++hh) {
+                            f32x4 val;
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const float lo = __int_as_float(
+                                    __builtin_amdgcn_ds_bpermute(src, __float_as_int(acc[2 * hh][nt][r])));
+                                const float hi = __int_as_float(
+                                    __builtin_amdgcn_ds_bpermute(src, __float_as_int(acc[2 * hh + 1][nt][r])));
+                                val[r] = (upper ? hi : lo) * m;
+                            }
+                            const int col = dbase + 32 * hh + 4 * c4;
+                            if (v < n && col < d) stream_store(reinterpret_cast<f32x4 *>(row + col), val);
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    const int v = vt * BB_VT + wave * 32 + nt * 16 + m16;
+                    float *row = O + (size_t)min(v, n - 1) * d;
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt) {
+                        const int col = dbase + mt * 16 + 4 * g4;
+                        const f32x4 val = acc[mt][nt] * b.m[nt];
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
                             if (v < n && col + r < d) stream_store(row + col + r, val[r]);
                     }
-                    acc[mt][nt] = f32x4{0, 0, 0, 0};
                 }
             }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4{0, 0, 0, 0};
         }
     };
     const int last = nsteps - 1;
