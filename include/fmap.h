@@ -204,7 +204,8 @@ fmap_status fmap_solve_resolutions(const float *A, const float *B, const float *
 /* formed in float32 from A A^T, B A^T and the operators).  With diagonal      */
 /* operators X = diag(evals_x), Y = diag(evals_y) the result is fmap_solve's   */
 /* with the Laplacian mask.  Supported: kx ky <= fmap_max_k() (the k^2 x k^2   */
-/* system is for small k), else FMAP_ERR_UNSUPPORTED.  info [pairs] int32 out: */
+/* system is for small k), else FMAP_ERR_UNSUPPORTED; pairs <= 2^20.          */
+/* info [pairs] int32 out:                                                     */
 /* 0; c + 1 if the pivot of vectorized index c = i kx + j is not positive     */
 /* (that pair's C is NaN); -1 for a negative or non-finite lambda.  workspace: */
 /* fmap_solve_vectorized_workspace_bytes(...) bytes (0 for invalid sizes).     */

@@ -55,18 +55,18 @@ VecWs vec_layout(int64_t P, int64_t kx, int64_t ky)
     return w;
 }
 
-// H [P][n][n], g [P][n] of the normal equations, and zero mask inputs for the row solve.  Thread e of pair
-// blockIdx.y owns entry (a, b) = (e / n, e % n) of H, a = i kx + j, b = p kx + q.  Each entry is a fixed
+// H [P][n][n], g [P][n] of the normal equations, and zero mask inputs for the row solve.  Each pair takes bpp
+// consecutive workgroups; its thread e owns entry (a, b) = (e / n, e % n) of H, a = i kx + j, b = p kx + q.  Each entry is a fixed
 // sequence of operations on its own indices and the same products in the same order as its mirror, so H is
 // exactly symmetric when A A^T is.
 __global__ __launch_bounds__(256) void vec_form_kernel(const float *__restrict__ K, const float *__restrict__ R,
                                                        const float *__restrict__ D1, const float *__restrict__ D2,
                                                        const float *__restrict__ lam, int kx, int ky, int n,
                                                        float *__restrict__ H, float *__restrict__ g,
-                                                       float *__restrict__ ex0, float *__restrict__ ey0)
+                                                       float *__restrict__ ex0, float *__restrict__ ey0, int bpp)
 {
-    const int pr = blockIdx.y;
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int pr = blockIdx.x / bpp;  // bpp workgroups per pair (a 1-D grid: no per-dimension limit on pairs)
+    const int e = (blockIdx.x - pr * bpp) * 256 + threadIdx.x;
     const float *Kp = K + (size_t)pr * kx * kx;
     const float *D1p = D1 + (size_t)pr * kx * kx;
     const float *D2p = D2 + (size_t)pr * ky * ky;
@@ -106,11 +106,12 @@ __global__ __launch_bounds__(256) void vec_form_lds_kernel(const float *__restri
                                                            const float *__restrict__ D1, const float *__restrict__ D2,
                                                            const float *__restrict__ lam, int kx, int ky, int n,
                                                            float *__restrict__ H, float *__restrict__ g,
-                                                           float *__restrict__ ex0, float *__restrict__ ey0)
+                                                           float *__restrict__ ex0, float *__restrict__ ey0, int bpp)
 {
     __shared__ float sD1[VF_KM * VF_LD], sD2[VF_KM * VF_LD], sK[VF_KM * VF_LD], sP1[VF_KM * VF_LD],
         sP2[VF_KM * VF_LD];
-    const int pr = blockIdx.y, a0 = blockIdx.x * VF_ROWS, tid = threadIdx.x;
+    const int pr = blockIdx.x / bpp, bx = blockIdx.x - pr * bpp;
+    const int a0 = bx * VF_ROWS, tid = threadIdx.x;
     const float *Kp = K + (size_t)pr * kx * kx;
     const float *D1p = D1 + (size_t)pr * kx * kx;
     const float *D2p = D2 + (size_t)pr * ky * ky;
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(256) void vec_form_lds_kernel(const float *__restri
             Hr[b] = fmaf(lm, s, base);
         }
     }
-    if (blockIdx.x == 0) {
+    if (bx == 0) {
         for (int e = tid; e < n; e += 256) {
             g[(size_t)pr * n + e] = R[(size_t)pr * n + e];
             ex0[(size_t)pr * n + e] = 0.f;
@@ -176,13 +177,13 @@ hipError_t launch_solve_vectorized(const float *A, const float *B, const float *
     float *g = (float *)(base + L.g), *ex0 = (float *)(base + L.ex0), *ey0 = (float *)(base + L.ey0);
     launch_gram(A, B, P, kx, ky, d, true, K, R, st);
     if (kx <= VF_KM && ky <= VF_KM) {
-        const dim3 grid((unsigned)((n + VF_ROWS - 1) / VF_ROWS), (unsigned)P);
-        hipLaunchKernelGGL(vec_form_lds_kernel, grid, dim3(256), 0, st, K, R, D1, D2, lam, (int)kx, (int)ky, (int)n, H,
-                           g, ex0, ey0);
+        const int bpp = (int)((n + VF_ROWS - 1) / VF_ROWS);
+        hipLaunchKernelGGL(vec_form_lds_kernel, dim3((unsigned)(P * bpp)), dim3(256), 0, st, K, R, D1, D2, lam, (int)kx,
+                           (int)ky, (int)n, H, g, ex0, ey0, bpp);
     } else {
-        const dim3 grid((unsigned)((n * n + 255) / 256), (unsigned)P);
-        hipLaunchKernelGGL(vec_form_kernel, grid, dim3(256), 0, st, K, R, D1, D2, lam, (int)kx, (int)ky, (int)n, H, g,
-                           ex0, ey0);
+        const int bpp = (int)((n * n + 255) / 256);
+        hipLaunchKernelGGL(vec_form_kernel, dim3((unsigned)(P * bpp)), dim3(256), 0, st, K, R, D1, D2, lam, (int)kx,
+                           (int)ky, (int)n, H, g, ex0, ey0, bpp);
     }
     launch_rowsolve_dense(H, g, ex0, ey0, lam, P, n, C, info, (float *)(base + L.tiles), st);
     return hipGetLastError();
@@ -195,7 +196,9 @@ extern "C" {
 size_t fmap_solve_vectorized_workspace_bytes(int64_t pairs, int64_t kx, int64_t ky, int64_t d)
 {
     (void)d;
-    if (pairs < 1 || kx < 1 || ky < 1 || kx * ky > fmap::kMaxK || pairs > ((int64_t)1 << 24)) return 0;
+    if (pairs < 1 || kx < 1 || ky < 1 || kx > fmap::kMaxK || ky > fmap::kMaxK || kx * ky > fmap::kMaxK ||
+        pairs > ((int64_t)1 << 20))
+        return 0;
     return fmap::vectorized_workspace_bytes(pairs, kx, ky);
 }
 
@@ -204,9 +207,9 @@ fmap_status fmap_solve_vectorized(const float *A, const float *B, const float *o
                                   int32_t *info, void *workspace, size_t workspace_bytes, void *stream)
 {
     if (!A || !B || !op_x || !op_y || !lambda || !C || !info) return FMAP_ERR_NULL;
-    if (pairs < 1 || kx < 1 || ky < 1 || d < 1 || pairs > ((int64_t)1 << 24) || d > ((int64_t)1 << 30))
+    if (pairs < 1 || kx < 1 || ky < 1 || d < 1 || pairs > ((int64_t)1 << 20) || d > ((int64_t)1 << 30))
         return FMAP_ERR_SHAPE;
-    if (kx * ky > fmap::kMaxK) return FMAP_ERR_UNSUPPORTED;
+    if (kx > fmap::kMaxK || ky > fmap::kMaxK || kx * ky > fmap::kMaxK) return FMAP_ERR_UNSUPPORTED;
     if (pairs * kx * d > ((int64_t)1 << 40) || pairs * ky * d > ((int64_t)1 << 40)) return FMAP_ERR_SHAPE;
     const size_t need = fmap::vectorized_workspace_bytes(pairs, kx, ky);
     if (!workspace || workspace_bytes < need) return FMAP_ERR_WORKSPACE;
