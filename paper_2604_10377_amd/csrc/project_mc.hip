@@ -627,7 +627,8 @@ __global__ __launch_bounds__(512, 2) void proj_bwd_mc_items_kernel(const McItem 
 // register buffers rotated by unrolling, loads unconditional from clamped
 // addresses), so the basis stream never waits for a tile boundary.  The 4 x 2
 // accumulators of a tile are stored, scaled by the masses, after its last K
-// step.  The column blocks of one vertex range share an XCD (their basis rows
+// step, exchanged across lanes first so that each store writes whole 128-byte
+// lines.  The column blocks of one vertex range share an XCD (their basis rows
 // are read from HBM once and from L2 afterwards).
 // ---------------------------------------------------------------------------
 constexpr int BK_COLS = 64;  // columns per workgroup
