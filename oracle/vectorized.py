@@ -27,8 +27,10 @@ Functions:
                used as an independent pin of `system` / `solve`
 
 Pins (tests/test_oracle_pins_vectorized.py): diagonal operators reproduce the row-wise oracle with the
-Laplacian mask; `solve` equals `solve_lstsq`; the gradient of the objective vanishes at the solution;
-transposing the roles of source and target; lambda = 0 gives the plain least-squares map B A^+.
+Laplacian mask; `solve` equals `solve_lstsq`; the gradient of the objective, written in matrix form, vanishes
+at the solution and the objective rises under perturbation; lambda = 0 gives the plain least-squares map
+B A^T (A A^T)^{-1}; the scalar case kx = ky = 1 has a closed form; every entry of H matches the index form
+of the objective's second derivatives.
 """
 from __future__ import annotations
 
