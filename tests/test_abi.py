@@ -195,3 +195,35 @@ def test_plan_validation(L):
     assert L.fmap_overlap_metrics(FAKE, FAKE, FAKE, 2, 10, float("nan"), FAKE, FAKE, None) == 3
     assert L.fmap_plan_group(NULL, 0, NULL, NULL, NULL) == 1
     assert L.fmap_plan_destroy(NULL) == 1
+
+
+def test_vectorized_validation(L):
+    """General-operator solve: sizes, pointers and the workspace are checked before any launch."""
+    mk = L.fmap_max_k()
+    assert L.fmap_solve_vectorized_workspace_bytes(4, 8, 8, 64) > 0
+    assert L.fmap_solve_vectorized_workspace_bytes(0, 8, 8, 64) == 0
+    assert L.fmap_solve_vectorized_workspace_bytes(4, 0, 8, 64) == 0
+    assert L.fmap_solve_vectorized_workspace_bytes(4, mk, 2, 64) == 0  # kx ky above fmap_max_k()
+    assert L.fmap_solve_vectorized_workspace_bytes((1 << 20) + 1, 2, 2, 8) == 0
+    # the workspace grows with the batch
+    assert L.fmap_solve_vectorized_workspace_bytes(8, 8, 8, 64) > L.fmap_solve_vectorized_workspace_bytes(4, 8, 8, 64)
+
+    def sv(A=FAKE, B=FAKE, X=FAKE, Y=FAKE, lam=FAKE, P=4, kx=8, ky=8, d=64, C=FAKE, info=FAKE, ws=FAKE,
+           wsb=1 << 30):
+        return L.fmap_solve_vectorized(A, B, X, Y, lam, P, kx, ky, d, C, info, ws, wsb, None)
+    assert sv(A=NULL) == 1
+    assert sv(X=NULL) == 1
+    assert sv(Y=NULL) == 1
+    assert sv(lam=NULL) == 1
+    assert sv(C=NULL) == 1
+    assert sv(info=NULL) == 1
+    assert sv(P=0) == 2
+    assert sv(kx=0) == 2
+    assert sv(ky=-1) == 2
+    assert sv(d=0) == 2
+    assert sv(P=(1 << 20) + 1) == 2
+    assert sv(kx=18, ky=18) == 6  # n = 324 above fmap_max_k()
+    assert sv(kx=mk + 1, ky=1) == 6
+    need = L.fmap_solve_vectorized_workspace_bytes(4, 8, 8, 64)
+    assert sv(ws=NULL) == 5
+    assert sv(wsb=need - 1) == 5
