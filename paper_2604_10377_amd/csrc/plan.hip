@@ -18,7 +18,8 @@
 // It then autotunes (vertices per item, persistent grid size, row systems per
 // workgroup, backward rows per item) by timing candidates on the caller's
 // stream, or takes them from the cache file, and captures the forward and the
-// backward pass as HIP graphs on a private stream.  fmap_plan_forward /
+// backward pass as HIP graphs on a private stream, the k groups' solves as
+// parallel branches between the projections.  fmap_plan_forward /
 // _backward replay the graphs on the caller's stream: no host work, no
 // allocation, no per-pair launches.
 #include "../../include/fmap.h"
@@ -54,6 +55,9 @@ static hipError_t launch_copies(const CopyItem *items, int nitems, hipStream_t s
     hipLaunchKernelGGL(copy_items_kernel, dim3(4, (unsigned)std::min(nitems, 65535)), dim3(256), 0, st, items, nitems);
     return hipGetLastError();
 }
+
+// Graph branches for the per-group solves, at most HIP's default number of hardware queues per process.
+constexpr int kLanes = 4;
 
 }  // namespace fmap
 
@@ -92,6 +96,10 @@ struct fmap_plan {
     int ngf = 0, nsf = 0, ngb = 0;
     int chunk = 1024, grid_fwd = 512, grid_bwd = 512, rb = 2, from_cache = 0;
     hipStream_t cap = nullptr;
+    // k groups solve on up to kLanes graph branches: lane 0 is the capturing stream, lanes 1.. these streams
+    std::vector<hipStream_t> side;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
     hipGraph_t gf = nullptr, gb = nullptr;
     hipGraphExec_t ef = nullptr, eb = nullptr;
 };
@@ -353,32 +361,68 @@ hipError_t launch_projections_bwd(fmap_plan *pl, int grid, hipStream_t st)
     return e;
 }
 
-hipError_t record_forward(fmap_plan *pl, hipStream_t st)
+// The per-group solves of one pass.  Groups share no buffer (each has its own blocks of A, B, C, factors,
+// info and workspace) and the solve kernels have no inter-workgroup waits, so with `branch` the groups run on
+// separate streams forked from st and joined back into it: under capture, parallel branches of the graph, so
+// that one group's latency-bound kernels run beside another group's.  With `tiled_in_line` the groups of the
+// tiled row solve (k > kSmallK) stay in sequence on st: each is a persistent grid sized to the whole chip, and
+// two side by side contend for it; only the other groups branch off beside them.
+template <typename Fn>
+hipError_t record_groups(fmap_plan *pl, hipStream_t st, bool branch, bool tiled_in_line, Fn fn)
+{
+    const int nb = (int)pl->buckets.size();
+    const int nside = branch ? std::min<int>((int)pl->side.size(), nb - 1) : 0;
+    std::vector<int> lane(nb, 0);
+    int next = 0, used = 0;  // lanes 1..used receive work
+    for (int i = 0; i < nb && nside > 0; ++i) {
+        if (tiled_in_line && pl->buckets[i].k > kSmallK) continue;
+        // round robin over all lanes, or over the side lanes when st carries the tiled groups
+        const int span = tiled_in_line ? nside : nside + 1;
+        const int l = (tiled_in_line ? 1 : 0) + (next++ % span);
+        lane[i] = l;
+        used = std::max(used, l);
+    }
+    hipError_t e = hipSuccess;
+    if (used > 0) {
+        e = hipEventRecord(pl->fork, st);
+        for (int l = 1; l <= used && e == hipSuccess; ++l) e = hipStreamWaitEvent(pl->side[l - 1], pl->fork, 0);
+    }
+    for (int i = 0; i < nb && e == hipSuccess; ++i) e = fn(pl->buckets[i], lane[i] == 0 ? st : pl->side[lane[i] - 1]);
+    // join every forked lane, also after an error, so that the capture ends with no unjoined work
+    for (int l = 1; l <= used; ++l) {
+        hipError_t j = hipEventRecord(pl->join[l - 1], pl->side[l - 1]);
+        if (j == hipSuccess) j = hipStreamWaitEvent(st, pl->join[l - 1], 0);
+        if (e == hipSuccess) e = j;
+    }
+    return e;
+}
+
+hipError_t record_forward(fmap_plan *pl, hipStream_t st, bool branch = false)
 {
     hipError_t e = launch_copies(pl->d_gf, pl->ngf, st);
     if (e == hipSuccess) e = launch_projections_fwd(pl, pl->grid_fwd, st);
-    for (Bucket &B : pl->buckets) {
-        if (e != hipSuccess) break;
-        const int64_t P = (int64_t)B.pairs.size();
-        e = launch_solve(B.AB, B.AB + (size_t)P * B.k * pl->d, B.evx, B.evy, B.lam, pl->mask_kind, pl->gamma, P, B.k,
-                         B.k, pl->d, 0, 0.f, B.C, pl->recompute ? nullptr : B.factors, B.info, nullptr, B.ws, st,
-                         B.waves);
-    }
+    if (e == hipSuccess)
+        e = record_groups(pl, st, branch, true, [&](Bucket &B, hipStream_t s) {
+            const int64_t P = (int64_t)B.pairs.size();
+            return launch_solve(B.AB, B.AB + (size_t)P * B.k * pl->d, B.evx, B.evy, B.lam, pl->mask_kind, pl->gamma,
+                                P, B.k, B.k, pl->d, 0, 0.f, B.C, pl->recompute ? nullptr : B.factors, B.info, nullptr,
+                                B.ws, s, B.waves);
+        });
     if (e == hipSuccess) e = launch_copies(pl->d_sf, pl->nsf, st);
     return e;
 }
 
-hipError_t record_backward(fmap_plan *pl, hipStream_t st)
+hipError_t record_backward(fmap_plan *pl, hipStream_t st, bool branch = false)
 {
     hipError_t e = launch_copies(pl->d_gb, pl->ngb, st);
-    for (Bucket &B : pl->buckets) {
-        if (e != hipSuccess) break;
-        const int64_t P = (int64_t)B.pairs.size();
-        const size_t half = (size_t)P * B.k * pl->d;
-        e = launch_solve_backward(B.dC, B.AB, B.AB + half, B.C, B.evx, B.evy, B.lam, pl->mask_kind, pl->gamma, P, B.k,
-                                  B.k, pl->d, pl->recompute ? nullptr : B.factors, B.dAB, B.dAB + half, nullptr,
-                                  nullptr, B.ws, st, B.waves);
-    }
+    if (e == hipSuccess)
+        e = record_groups(pl, st, branch, false, [&](Bucket &B, hipStream_t s) {
+            const int64_t P = (int64_t)B.pairs.size();
+            const size_t half = (size_t)P * B.k * pl->d;
+            return launch_solve_backward(B.dC, B.AB, B.AB + half, B.C, B.evx, B.evy, B.lam, pl->mask_kind, pl->gamma,
+                                         P, B.k, B.k, pl->d, pl->recompute ? nullptr : B.factors, B.dAB, B.dAB + half,
+                                         nullptr, nullptr, B.ws, s, B.waves);
+        });
     if (e == hipSuccess) e = launch_projections_bwd(pl, pl->grid_bwd, st);
     return e;
 }
@@ -493,6 +537,9 @@ void plan_free(fmap_plan *pl)
     if (pl->gf) (void)hipGraphDestroy(pl->gf);
     if (pl->gb) (void)hipGraphDestroy(pl->gb);
     if (pl->cap) (void)hipStreamDestroy(pl->cap);
+    for (hipStream_t q : pl->side) (void)hipStreamDestroy(q);
+    for (hipEvent_t ev : pl->join) (void)hipEventDestroy(ev);
+    if (pl->fork) (void)hipEventDestroy(pl->fork);
     for (void *p : pl->allocs) (void)hipFree(p);
     delete pl;
 }
@@ -687,15 +734,27 @@ fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, 
     if (bwd) FMAP_TRY(record_backward(pl, st));
     FMAP_TRY(hipStreamSynchronize(st));
     FMAP_TRY(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
+    if (pl->buckets.size() > 1) {
+        FMAP_TRY(hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming));
+        const int nside = std::min<int>((int)pl->buckets.size(), kLanes) - 1;
+        for (int l = 0; l < nside; ++l) {
+            hipStream_t q = nullptr;
+            hipEvent_t ev = nullptr;
+            FMAP_TRY(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+            pl->side.push_back(q);
+            FMAP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            pl->join.push_back(ev);
+        }
+    }
     FMAP_TRY(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t rec = record_forward(pl, pl->cap);
+    hipError_t rec = record_forward(pl, pl->cap, true);
     hipError_t endc = hipStreamEndCapture(pl->cap, &pl->gf);
     FMAP_TRY(rec);
     FMAP_TRY(endc);
     FMAP_TRY(hipGraphInstantiate(&pl->ef, pl->gf, nullptr, nullptr, 0));
     if (bwd) {
         FMAP_TRY(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
-        rec = record_backward(pl, pl->cap);
+        rec = record_backward(pl, pl->cap, true);
         endc = hipStreamEndCapture(pl->cap, &pl->gb);
         FMAP_TRY(rec);
         FMAP_TRY(endc);

@@ -214,8 +214,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX == 10 
     int *s_fail = reinterpret_cast<int *>(s_red + LLW);
     float *Ls = Lws + (size_t)blockIdx.x * NTL * LTS;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l32 = lane & 31, half = lane >> 5;
+    const int tid = threadIdx.x, wave = tid >> 6;
     // the wave that runs the serial diagonal steps: different for the workgroups that share a CU (ids one grid
     // round of CUs apart), so that their diagonal chains do not all land on the same SIMD
     const int dwave = (blockIdx.x / cus) % LLW;
