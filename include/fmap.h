@@ -285,6 +285,9 @@ typedef struct fmap_plan fmap_plan;
 /* `stream`, unless `tune_cache_path` [host, may be NULL] holds a result for   */
 /* this workload signature (results are appended to that file).  k <= 319;     */
 /* bwd_recompute != 0 refactorises in the backward instead of storing factors. */
+/* The plan owns one capture stream and, with several k groups, up to three    */
+/* more (default priority) on which the groups' solves are captured as         */
+/* parallel graph branches; fmap_plan_destroy releases them.                   */
 fmap_status fmap_plan_create(const fmap_pair *pairs, int32_t npairs, int64_t d, int32_t mask_kind, float gamma,
                              int32_t bwd_recompute, const char *tune_cache_path, void *stream, fmap_plan **out);
 fmap_status fmap_plan_forward(fmap_plan *plan, void *stream);   /* replays the captured forward  */
