@@ -79,6 +79,31 @@ def test_plan_ragged_forward_backward(F, dev, mask, recompute):
     plan.close()
 
 
+# more k groups than solve branches: six groups, so that two register-solve groups share one side stream in
+# the forward (the tiled k = 70 and 100 groups stay on the capturing stream) and the backward's groups wrap
+# round the four streams.  d = 128 exceeds every k: with d < k, A A^T is singular and the row systems are
+# conditioned by lambda alone (about 1.7e3 here at d = 64), beyond what the float32 tolerance allows
+MANY_GROUPS = dict(pairs=8, d=128, n_lo=200, n_hi=900, ks=(8, 17, 30, 50, 70, 100))
+
+
+def test_plan_more_groups_than_branches(F, dev):
+    import torch
+    pairs = synth.workload_ragged(**MANY_GROUPS)
+    assert {p.k for p in pairs} == set(MANY_GROUPS["ks"])
+    print("plan six groups:", [(p.n_x, p.n_y, p.k) for p in pairs], flush=True)
+    dpairs = _device_pairs(pairs, dev)
+    plan = F.FmapPlan(dpairs, synth.MASK_LAPLACIAN, 0.5, backward=True, want_AB=True)
+    for i, p in enumerate(pairs):
+        plan.dC[i].copy_(torch.from_numpy(p.dC))
+    refs = [_oracle(p, synth.MASK_LAPLACIAN, 0.5) for p in pairs]
+    for _ in range(2):  # two replays of each graph, checked after the second
+        plan.forward()
+        plan.backward()
+        torch.cuda.synchronize()
+    _check(plan, pairs, refs, with_AB=True)
+    plan.close()
+
+
 # the large-k groups of the uneven workload: k = 120 (four K steps of 32 in the backward projection items)
 # and k = 150 (five), beside a register-solve group; n spans several vertex tiles with ragged tails
 LARGE_GROUPS = dict(pairs=6, d=256, n_lo=900, n_hi=4100, ks=(50, 120, 150))
